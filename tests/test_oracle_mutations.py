@@ -1,0 +1,56 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a temporary copy of the oracle's C source
+(never in the oracle itself), builds it, and runs the pin suite against that
+build in a subprocess.  The suite must fail for every planted mistake.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "isis_oracle.c")
+
+MUTATIONS = {
+    "jacobian_half_dropped": ("dflux += 0.5 * bc * (nb[f] - p) - bf;",
+                              "dflux += bc * (nb[f] - p) - bf;"),
+    "face_average_half_dropped": ("double bf = 0.5 * (bc + exp(nb[f]));",
+                                  "double bf = (bc + exp(nb[f]));"),
+    "flux_missing_inv_h2": ("return flux * ih2 - S;", "return flux - S;"),
+    "symmetron_cubic_sign": ("*S = K * (A * eta * chi - chi + chi * chi * chi);",
+                             "*S = K * (A * eta * chi - chi - chi * chi * chi);"),
+    "symmetron_K_missing_a2": ("double K = m->a * m->a / (2.0 * m->lambda0 * m->lambda0);",
+                               "double K = 1.0 / (2.0 * m->lambda0 * m->lambda0);"),
+    "fr_cL_inverted": ("    double cL = 4.0 * m->omega_l / m->omega_m;\n    double a3",
+                       "    double cL = 4.0 * m->omega_m / m->omega_l;\n    double a3"),
+    "restriction_weight": ("coarse[cidx(nc, I, J, K)] = s / 8.0;",
+                           "coarse[cidx(nc, I, J, K)] = s / 7.0;"),
+    "prolongation_weights_swapped": ("const double w[2] = {0.75, 0.25};",
+                                     "const double w[2] = {0.25, 0.75};"),
+    "prolongation_no_phihat": ("(coarse[q] - coarse_hat[q])", "(coarse[q])"),
+    "fas_sigma_sign": ("c->sigma[q] -= c->work[q];", "c->sigma[q] += c->work[q];"),
+    "laplacian_wrong_diagonal": ("double lap = (sum - 6.0 * p) * ih2;",
+                                 "double lap = (sum - 5.0 * p) * ih2;"),
+    "neighbour_index": ("nb[3] = phi[cidx(n, i, wrap(j + 1, n), k)];",
+                        "nb[3] = phi[cidx(n, i, wrap(j - 1, n), k)];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_fails_a_pin(tmp_path, name):
+    from oracle import oracle as O
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    so = str(tmp_path / "libmutant.so")
+    O.build(force=True, src=str(mut), out=so)
+    env = dict(os.environ, ORACLE_LIB=so, OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"{name}: pins did not fail\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout
