@@ -1,0 +1,225 @@
+/*
+ * isis_mg — nonlinear FAS multigrid for the quasi-static scalar-field
+ * equation of the symmetron and Hu-Sawicki f(R) models on one GPU
+ * (MI355X, gfx950).
+ *
+ * The problem (Llinares, Mota & Winther 2013, "ISIS", Sec. 2 and 3.2): given
+ * the density eta (in units of the mean) on a periodic N^3 cell-centred grid
+ * and the expansion factor a, find phi with L(phi, eta) = 0, where
+ *   canonical (Sec. 3.3):      L = lap_h(phi) - S(phi, eta)
+ *   non-canonical (Sec. 3.4):  L = (1/h^2) sum_faces b_f (u_nb - u) - S(u, eta),
+ *                              b_f = (b(u) + b(u_nb)) / 2,  b(u) = e^u
+ * with the model sources
+ *   ISIS_SYMMETRON (Sec. 4.1, dimensionless symmetron equation):
+ *       S = a^2/(2 lambda0^2) [ (a_ssb/a)^3 eta chi - chi + chi^3 ]
+ *   ISIS_FR_HS (Sec. 4.2, non-canonical f(R) equation, solved for
+ *       u = ln(f_R/f_R0), i.e. the paper's u shifted by ln(a^2 |f_R0|)):
+ *       S = Q [ eta + cL a^3 - a^3 (1 + cL) exp(-u/(n+1)) ],
+ *       Q = Omega_m H0^2 / (a |f_R0|), cL = 4 Omega_L / Omega_m,
+ *       H0 = 1/2997.92458 h/Mpc (lengths in comoving Mpc/h, c = 1)
+ *   ISIS_LINEAR (the Poisson problem of Sec. 3.1 with a mass term):
+ *       S = m2 phi + kappa (eta - 1)
+ * The solve is FAS multigrid (Sec. 3.2): red-black Newton-Gauss-Seidel
+ * smoothing, 8-child mean restriction, cell-centred trilinear prolongation,
+ * V(nu_pre, nu_post) cycles down to a 4^3 grid.
+ *
+ * Conventions for every entry point:
+ *  - Arrays are C-order [x][y][z] (z fastest), index (i*N + j)*N + k, cell
+ *    centres at (i + 1/2) h, periodic in all three directions.
+ *  - Array pointers are DEVICE pointers on the current HIP device, owned by
+ *    the caller; the library never frees them and never calls hipMalloc.
+ *    Scratch memory is the caller-provided workspace (see
+ *    isis_mg_workspace_size).  Pointers must be 8-byte aligned (doubles) or
+ *    4-byte aligned (floats); the workspace 256-byte aligned.
+ *  - All work is enqueued on the given stream (a hipStream_t passed as
+ *    void*; NULL is the null stream).  isis_op_* calls return once the work
+ *    is enqueued; isis_mg_solve / isis_mg_residual synchronise the stream.
+ *  - Return value: ISIS_OK (0) or a negative isis_status.  On error nothing
+ *    is guaranteed about output arrays except where stated.
+ */
+#ifndef ISIS_MG_H
+#define ISIS_MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISIS_MG_ABI_VERSION 1
+#define ISIS_MG_MAX_HIST 128
+
+typedef enum {
+    ISIS_OK = 0,
+    ISIS_ERR_INVALID_ARG = -1,  /* bad size, parameter, pointer or alignment        */
+    ISIS_ERR_NOT_CONVERGED = -2,/* max_cycles reached; field holds the last iterate */
+    ISIS_ERR_DIVERGED = -3,     /* residual non-finite or > 1e3 x initial           */
+    ISIS_ERR_HIP = -4,          /* a HIP runtime call failed (see last_error)       */
+    ISIS_ERR_UNSUPPORTED = -5   /* option not available for this model / size       */
+} isis_status;
+
+typedef enum { ISIS_SYMMETRON = 0, ISIS_FR_HS = 1, ISIS_LINEAR = 2 } isis_model;
+
+typedef enum {
+    ISIS_FP64 = 0,  /* every step in double precision                               */
+    ISIS_MIXED = 1  /* FP32 smoothing and coarse-grid work, FP64 fine-level defect
+                       and FP64 refinement cycles (see isis_mg_solve)                */
+} isis_precision;
+
+typedef struct {
+    int model;        /* isis_model                                              */
+    double lambda0;   /* symmetron: vacuum range, Mpc/h (> 0)                      */
+    double a_ssb;     /* symmetron: symmetry-breaking expansion factor (> 0)       */
+    double beta;      /* symmetron coupling: enters only the fifth force, unused   */
+    double n;         /* f(R): Hu-Sawicki exponent (> 0)                           */
+    double fR0_abs;   /* f(R): |f_R0| (> 0)                                        */
+    double omega_m;   /* f(R): Omega_m (> 0)                                       */
+    double omega_l;   /* f(R): Omega_Lambda (>= 0)                                 */
+    double kappa;     /* LINEAR: source coefficient                                */
+    double m2;        /* LINEAR: mass term (>= 0; 0 = singular Poisson, needs a
+                         zero-mean source; the mean of phi is then removed)        */
+} isis_model_params;
+
+typedef struct {
+    int N;             /* grid cells per side: power of two, >= 8                 */
+    double box;        /* box side, comoving Mpc/h (> 0)                           */
+    int nu_pre;        /* pre-smoothing sweeps per level (>= 0; default 2)          */
+    int nu_post;       /* post-smoothing sweeps per level (>= 0; default 2)         */
+    int nu_coarse;     /* red-black sweeps on the 4^3 grid (>= 1; default 32)       */
+    int max_cycles;    /* V-cycle limit (1 .. ISIS_MG_MAX_HIST-1; default 50)       */
+    int precision;     /* isis_precision                                           */
+    int temporal_block;/* 0: one HBM pass per red or black half-sweep;
+                          1: one pass per full red-black sweep (fused);
+                          2: two full sweeps per pass (temporal blocking)           */
+    void* stream;      /* hipStream_t                                              */
+    void* workspace;   /* device scratch, >= isis_mg_workspace_size bytes          */
+    size_t workspace_bytes;
+} isis_mg_desc;
+
+typedef struct {
+    int cycles;          /* V-cycles run (FP32 + FP64 in mixed mode)              */
+    int cycles_fp32;     /* of which FP32 cycles (mixed mode)                     */
+    double r_ref;        /* RMS of L_0 at the pointwise homogeneous root          */
+    double r0;           /* RMS of L_0 at the initial field                       */
+    double rel_res;      /* final RMS(L_0(phi)) / r_ref; absolute RMS when r_ref <=
+                            1e-14 (6/h^2) RMS(cold start), i.e. when the cold
+                            start is an exact root (uniform density)             */
+    double rel_hist[ISIS_MG_MAX_HIST]; /* [0] initial, [k] after cycle k          */
+    double ms_total;     /* wall time of the solve call, milliseconds             */
+    double cell_updates; /* Newton-GS cell updates performed, all levels          */
+    int used_guess;      /* 1 if the caller's field was used as initial guess     */
+    /* Finest-level smoother timing, filled when profiling is on
+     * (isis_mg_set_profiling): HIP events on the solver's stream around the
+     * sweep launches of the finest level (FP64 and, in mixed mode, FP32). */
+    double fine_sweep_ms;      /* summed kernel time of those launches           */
+    int fine_sweep_launches;   /* number of kernel launches                       */
+    double fine_sweep_updates; /* cell updates they performed                     */
+    double fine_sweep_bytes;   /* their compulsory HBM bytes: per pass over the
+                                  grid, read phi + eta and write phi (8+8+8 B per
+                                  cell in FP64, 4+4+4 in FP32); a pass is one
+                                  sweep, or temporal_block sweeps when blocked  */
+} isis_mg_stats;
+
+typedef struct isis_mg isis_mg_t;
+
+/* Bytes of device workspace needed for desc (N, precision, temporal_block are
+ * used); 0 if desc is invalid. */
+size_t isis_mg_workspace_size(const isis_mg_desc* desc);
+
+/* Create a solver handle for one grid size.  desc is copied; the workspace
+ * must stay valid until isis_mg_destroy.  The handle is bound to the HIP
+ * device current at creation.  On error *out is NULL. */
+int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
+
+/* FAS V-cycles until RMS(L_0(phi)) <= tol * r_ref (Sec. 3.2; the norm and
+ * r_ref are defined in isis_mg_stats).
+ *  density: device, N^3 doubles, eta > 0, read-only.
+ *  field:   device, N^3 doubles.  In: initial guess if use_guess != 0, else
+ *           ignored (the pointwise homogeneous root is used).  Out: solution.
+ *  tol > 0.  stats may be NULL.
+ * Symmetron: the positive branch is the one reached from the cold start.
+ * ISIS_MIXED: FP32 V-cycles (FP32 fields, FP32 smoothing and coarse-grid
+ * work; the f(R) source in FP64), each followed by the FP64 defect of the
+ * FP32 iterate on the finest level; while that residual falls by at least
+ * 0.6x per cycle and is above 3e-6 relative (the FP32 round-off floor is
+ * ~1e-6), then FP64 V-cycles from the promoted iterate to tol.
+ * Returns ISIS_OK, ISIS_ERR_NOT_CONVERGED (field = last iterate) or
+ * ISIS_ERR_DIVERGED (field = last iterate, may be non-finite). */
+int isis_mg_solve(isis_mg_t* h, const double* density, double* field,
+                  const isis_model_params* params, double a, double tol, int use_guess,
+                  isis_mg_stats* stats);
+
+/* Defect of the finest level, Sec. 3.2: res = L(field, density) (no Sigma).
+ * out_res: device N^3 doubles or NULL.  out_rms: host double, receives
+ * sqrt(mean(res^2)); may be NULL. */
+int isis_mg_residual(isis_mg_t* h, const double* density, const double* field,
+                     const isis_model_params* params, double a, double* out_res,
+                     double* out_rms);
+
+void isis_mg_destroy(isis_mg_t* h);
+
+/* Turn the finest-level sweep timing of isis_mg_stats on (1) or off (0).  On
+ * adds two hipEventRecord calls per smoothing step of the finest level. */
+int isis_mg_set_profiling(isis_mg_t* h, int enable);
+
+/* Message of the last error on this handle ("" if none); h may be NULL for
+ * errors of isis_mg_create and isis_op_* (thread-local). */
+const char* isis_mg_last_error(const isis_mg_t* h);
+
+/* ------------------------------------------------------------------------
+ * Level operators: the individual steps of the V-cycle on caller buffers,
+ * n^3 grid with spacing h (n even, >= 4 unless stated).  They launch the same
+ * kernels the solver uses.  phi, eta, sigma, ... are device pointers.
+ * ---------------------------------------------------------------------- */
+
+/* One colour of a red-black Newton-Gauss-Seidel sweep (Sec. 3.2):
+ * phi_c <- phi_c - (L(phi)_c - sigma_c) / D_c for (i+j+k) % 2 == colour,
+ * D_c = dL_c/dphi_c (Sec. 3.3; eq. dbeq of Sec. 3.4 with the exact 1/2 on
+ * db/du), symmetron safeguarded as -6/h^2 - |dS/dphi|.  sigma may be NULL. */
+int isis_op_halfsweep(const isis_model_params* p, double a, int n, double h, double* phi,
+                      const double* eta, const double* sigma, int colour, void* stream);
+
+/* `count` full red-black sweeps with the solver's production kernels
+ * (temporal_block as in isis_mg_desc).  tmp: device n^3 doubles of scratch.
+ * The result is in phi; identical to 2*count isis_op_halfsweep calls up to
+ * floating-point contraction. */
+int isis_op_sweeps(const isis_model_params* p, double a, int n, double h, double* phi,
+                   double* tmp, const double* eta, const double* sigma, int count,
+                   int temporal_block, void* stream);
+
+/* out = L(phi, eta) - sigma (sigma may be NULL = 0). */
+int isis_op_defect(const isis_model_params* p, double a, int n, double h, const double* phi,
+                   const double* eta, const double* sigma, double* out, void* stream);
+
+/* coarse = mean of the 8 children of each coarse cell (n_fine even >= 2). */
+int isis_op_restrict(int n_fine, const double* fine, double* coarse, void* stream);
+
+/* One FAS descent step (Sec. 3.2), fine level of n_fine^3 cells and spacing
+ * h_fine to the coarse level (n_fine/2)^3, spacing 2 h_fine:
+ *   phi_c = phihat_c = R phi_f,
+ *   sigma_c = L_c(phi_c, eta_c) - R[L_f(phi_f, eta_f) - sigma_f].
+ * sigma_f may be NULL (finest level).  rr_c: coarse scratch (receives R of
+ * the fine defect). */
+int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double h_fine,
+                        const double* phi_f, const double* eta_f, const double* sigma_f,
+                        const double* eta_c, double* phi_c, double* phihat_c, double* sigma_c,
+                        double* rr_c, void* stream);
+
+/* fine += P(coarse - coarse_hat), cell-centred trilinear interpolation with
+ * weights 27, 9, 3, 1 over 64 and periodic wrap (n_fine even >= 4). */
+int isis_op_prolong_correct(int n_fine, double* fine, const double* coarse,
+                            const double* coarse_hat, void* stream);
+
+/* nu_c red-black sweeps on the coarsest (n = 4) grid in one workgroup. */
+int isis_op_coarse_solve(const isis_model_params* p, double a, double h, double* phi,
+                         const double* eta, const double* sigma, int nu_c, void* stream);
+
+/* Pointwise homogeneous root (cold start): symmetron sqrt(max(0, 1 -
+ * (a_ssb/a)^3 eta)); f(R) -(n+1) ln[(eta/a^3 + cL)/(1 + cL)]; LINEAR 0. */
+int isis_op_cold_start(const isis_model_params* p, double a, long ncell, const double* eta,
+                       double* phi, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

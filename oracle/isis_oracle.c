@@ -38,7 +38,9 @@
  *   R7  Gauss-Seidel order is red-black: colour (i+j+k) mod 2, colour 0 first.
  *   R8  The coarsest grid (4^3) gets a fixed number of red-black sweeps.
  *   R9  Stop test: RMS of L_0(phi) relative to r_ref, the RMS of L_0 at the
- *       pointwise homogeneous root (the cold start), whatever the guess.
+ *       pointwise homogeneous root (the cold start), whatever the guess.  If
+ *       r_ref <= 1e-14 (6/h^2) RMS(cold start) the cold start is an exact
+ *       root up to rounding and the tolerance is absolute.
  *   R10 Symmetron Newton denominator is safeguarded as -6/h^2 - |dS/dphi|.
  *   R11 LINEAR with m2 = 0 is singular; its mean is removed after each cycle.
  *
@@ -471,9 +473,13 @@ int orc_solve(const orc_model* m, const orc_cfg* cfg, int n, double box, const d
     orc_cold_start(m, n3, eta, cold);
     orc_defect(m, n, lv[0].h, cold, eta, NULL, lv[0].work);
     double r_ref = orc_rms(n, lv[0].work);
+    /* r_ref at the rounding level of the Laplacian of the cold start means
+     * the cold start is an exact root (uniform density): the tolerance is
+     * then absolute (reading R9). */
+    double cold_scale = 1e-14 * 6.0 / (lv[0].h * lv[0].h) * orc_rms(n, cold);
     if (!use_guess) memcpy(phi, cold, sizeof(double) * (size_t)n3);
     free(cold);
-    double r_norm = r_ref > 0.0 ? r_ref : 1.0;
+    double r_norm = r_ref > cold_scale ? r_ref : 1.0;
     int singular = (m->model == ORC_LINEAR && m->m2 == 0.0);
     if (singular) {
         double mu = mean_of(n, phi);

@@ -1,0 +1,874 @@
+// Host driver and C ABI of the FAS multigrid scalar-field solver.
+//
+// The V-cycle (Sec. 3.1 and 3.2 of Llinares, Mota & Winther 2013) runs level
+// by level on the caller's stream:
+//   smooth nu_pre, descend (defect + restriction + FAS source), recurse,
+//   prolongate + correct, smooth nu_post; nu_coarse sweeps on the 4^3 grid.
+// The only device->host traffic is one scalar per V-cycle (the residual
+// norm of the stop test).  Device memory is the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/isis_mg.h"
+#include "fused_sweep.hpp"
+#include "kernels.hpp"
+
+using namespace isis;
+
+namespace {
+
+constexpr double kH0 = 1.0 / 2997.92458;  // h/Mpc with c = 1
+constexpr int kMaxLevels = 16;
+constexpr int kMaxGrid = 16384;
+thread_local char g_err[512];
+
+void fmt_err(char* buf, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+}
+
+int grid_for(long work)
+{
+    long b = (work + kBlock - 1) / kBlock;
+    return (int)std::max(1L, std::min(b, (long)kMaxGrid));
+}
+
+bool is_pow2_ge(int n, int lo)
+{
+    return n >= lo && (n & (n - 1)) == 0;
+}
+
+int num_levels(int N)
+{
+    int L = 1;
+    while (N > 4) {
+        N >>= 1;
+        ++L;
+    }
+    return L;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+bool valid_params(const isis_model_params* p, double a, char* err)
+{
+    if (!p) {
+        fmt_err(err, "model params is NULL");
+        return false;
+    }
+    if (!finite_pos(a)) {
+        fmt_err(err, "expansion factor a must be finite and > 0 (got %g)", a);
+        return false;
+    }
+    switch (p->model) {
+    case ISIS_SYMMETRON:
+        if (!finite_pos(p->lambda0) || !finite_pos(p->a_ssb)) {
+            fmt_err(err, "symmetron needs lambda0 > 0 and a_ssb > 0");
+            return false;
+        }
+        return true;
+    case ISIS_FR_HS:
+        if (!finite_pos(p->n) || !finite_pos(p->fR0_abs) || !finite_pos(p->omega_m) ||
+            !std::isfinite(p->omega_l) || p->omega_l < 0.0) {
+            fmt_err(err, "f(R) needs n > 0, |fR0| > 0, Omega_m > 0, Omega_L >= 0");
+            return false;
+        }
+        return true;
+    case ISIS_LINEAR:
+        if (!std::isfinite(p->kappa) || !std::isfinite(p->m2) || p->m2 < 0.0) {
+            fmt_err(err, "linear model needs finite kappa and m2 >= 0");
+            return false;
+        }
+        return true;
+    default:
+        fmt_err(err, "unknown model %d", p->model);
+        return false;
+    }
+}
+
+template <class T>
+Symmetron<T> make_symmetron(const isis_model_params& p, double a)
+{
+    double K = a * a / (2.0 * p.lambda0 * p.lambda0);
+    double r = p.a_ssb / a;
+    double A = r * r * r;
+    return Symmetron<T>{(T)K, (T)A};
+}
+
+template <class T>
+FofR<T> make_fofr(const isis_model_params& p, double a)
+{
+    FofR<T> m;
+    double cL = 4.0 * p.omega_l / p.omega_m;
+    double a3 = a * a * a;
+    m.Q = p.omega_m * kH0 * kH0 / (a * p.fR0_abs);
+    m.cLa3 = cL * a3;
+    m.c1 = a3 * (1.0 + cL);
+    m.inv_np1 = 1.0 / (p.n + 1.0);
+    m.a3 = a3;
+    m.cL = cL;
+    m.np1 = p.n + 1.0;
+    return m;
+}
+
+template <class T>
+Linear<T> make_linear(const isis_model_params& p)
+{
+    return Linear<T>{(T)p.kappa, (T)p.m2};
+}
+
+// Calls f(model) with the device model of p (precision T).
+template <class T, class F>
+int with_model(const isis_model_params& p, double a, F&& f)
+{
+    switch (p.model) {
+    case ISIS_SYMMETRON:
+        return f(make_symmetron<T>(p, a));
+    case ISIS_FR_HS:
+        return f(make_fofr<T>(p, a));
+    default:
+        return f(make_linear<T>(p));
+    }
+}
+
+int hip_fail(char* err, hipError_t e, const char* what)
+{
+    fmt_err(err, "%s: %s", what, hipGetErrorString(e));
+    return ISIS_ERR_HIP;
+}
+
+#define HIP_TRY(err, call)                                           \
+    do {                                                             \
+        hipError_t e_ = (call);                                      \
+        if (e_ != hipSuccess) return hip_fail((err), e_, #call);     \
+    } while (0)
+
+#define LAUNCH_CHECK(err, what)                                      \
+    do {                                                             \
+        hipError_t e_ = hipGetLastError();                           \
+        if (e_ != hipSuccess) return hip_fail((err), e_, (what));    \
+    } while (0)
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// ---------------------------------------------------------------------------
+// Level launches (shared by the solver and the isis_op_* entry points).
+// ---------------------------------------------------------------------------
+
+template <class T, class M>
+int launch_halfsweep(const M& m, int n, double h, T* phi, const T* eta, const T* sigma,
+                     int colour, hipStream_t s, char* err)
+{
+    T ih2 = (T)(1.0 / (h * h));
+    hipLaunchKernelGGL((k_halfsweep<T, M>), dim3(grid_for((long)n * n * n / 2)), dim3(kBlock), 0,
+                       s, m, n, ih2, phi, eta, sigma, colour);
+    LAUNCH_CHECK(err, "k_halfsweep");
+    return ISIS_OK;
+}
+
+// count full sweeps; result in phi.  tmp (n^3) is used by the fused kernels.
+template <class T, class M>
+int launch_sweeps(const M& m, int n, double h, T* phi, T* tmp, const T* eta, const T* sigma,
+                  int count, int tb, hipStream_t s, char* err)
+{
+    if (count <= 0) return ISIS_OK;
+    if (tb >= 1 && fused_supported<T, M>(n)) {
+        return launch_fused_sweeps<T, M>(m, n, h, phi, tmp, eta, sigma, count, tb, s, err);
+    }
+    for (int q = 0; q < count; ++q) {
+        int r = launch_halfsweep<T, M>(m, n, h, phi, eta, sigma, 0, s, err);
+        if (r) return r;
+        r = launch_halfsweep<T, M>(m, n, h, phi, eta, sigma, 1, s, err);
+        if (r) return r;
+    }
+    return ISIS_OK;
+}
+
+template <class T, class M>
+int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f,
+                   const T* sigma_f, const T* eta_c, T* phi_c, T* phihat_c, T* sigma_c, T* rr_c,
+                   hipStream_t s, char* err)
+{
+    int nc = nf / 2;
+    long c3 = (long)nc * nc * nc;
+    T ih2f = (T)(1.0 / (hf * hf));
+    double hc = 2.0 * hf;
+    T ih2c = (T)(1.0 / (hc * hc));
+    hipLaunchKernelGGL((k_defect_restrict<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m, nf,
+                       ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c);
+    LAUNCH_CHECK(err, "k_defect_restrict");
+    hipLaunchKernelGGL((k_fas_sigma<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m, nc, ih2c,
+                       phi_c, eta_c, rr_c, sigma_c);
+    LAUNCH_CHECK(err, "k_fas_sigma");
+    return ISIS_OK;
+}
+
+template <class T>
+int launch_prolong(int nf, T* fine, const T* coarse, const T* coarse_hat, hipStream_t s,
+                   char* err)
+{
+    long f3 = (long)nf * nf * nf;
+    hipLaunchKernelGGL((k_prolong_correct<T>), dim3(grid_for(f3)), dim3(kBlock), 0, s, nf, fine,
+                       coarse, coarse_hat);
+    LAUNCH_CHECK(err, "k_prolong_correct");
+    return ISIS_OK;
+}
+
+template <class T>
+int launch_restrict(int nf, const T* fine, T* coarse, hipStream_t s, char* err)
+{
+    long c3 = (long)(nf / 2) * (nf / 2) * (nf / 2);
+    hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for(c3)), dim3(kBlock), 0, s, nf, fine, coarse);
+    LAUNCH_CHECK(err, "k_restrict");
+    return ISIS_OK;
+}
+
+template <class T, class M>
+int launch_coarse(const M& m, double h, T* phi, const T* eta, const T* sigma, int nu_c,
+                  hipStream_t s, char* err)
+{
+    T ih2 = (T)(1.0 / (h * h));
+    hipLaunchKernelGGL((k_coarse_solve<T, M>), dim3(1), dim3(64), 0, s, m, ih2, phi, eta, sigma,
+                       nu_c);
+    LAUNCH_CHECK(err, "k_coarse_solve");
+    return ISIS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Solver handle.
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct LevP {
+    int n;
+    double h;
+    T *phi, *phihat, *sigma, *eta, *rr, *tmp;
+};
+
+struct isis_mg {
+    isis_mg_desc d;
+    int nlev;
+    int device;
+    hipStream_t s;
+    LevP<double> L64[kMaxLevels];
+    LevP<float> L32[kMaxLevels];
+    double* partial;  // kReduceBlocks
+    double* scal;     // 16
+    double* host;     // pinned, 16
+    char err[512];
+    // finest-level sweep timing
+    static constexpr int kMaxTimed = 2 * ISIS_MG_MAX_HIST + 8;
+    int profile;
+    int ntimed;
+    hipEvent_t ev0[kMaxTimed], ev1[kMaxTimed];
+    int tlaunch[kMaxTimed];
+    double tupd[kMaxTimed], tbytes[kMaxTimed];
+};
+
+namespace {
+
+// Lays out the workspace; with h == NULL only measures it.
+size_t carve(const isis_mg_desc& d, char* base, isis_mg* h)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~(size_t)255;
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const int nlev = num_levels(d.N);
+    for (int l = 0; l < nlev; ++l) {
+        const long n = d.N >> l;
+        const size_t n3 = (size_t)n * n * n;
+        LevP<double> a{};
+        a.n = (int)n;
+        a.h = (d.box / d.N) * (double)(1 << l);
+        a.tmp = (double*)take(n3 * 8);
+        if (l > 0) {
+            a.phi = (double*)take(n3 * 8);
+            a.phihat = (double*)take(n3 * 8);
+            a.sigma = (double*)take(n3 * 8);
+            a.eta = (double*)take(n3 * 8);
+            a.rr = (double*)take(n3 * 8);
+        }
+        LevP<float> b{};
+        b.n = a.n;
+        b.h = a.h;
+        if (d.precision == ISIS_MIXED) {
+            b.phi = (float*)take(n3 * 4);
+            b.eta = (float*)take(n3 * 4);
+            b.tmp = (float*)take(n3 * 4);
+            if (l > 0) {
+                b.phihat = (float*)take(n3 * 4);
+                b.sigma = (float*)take(n3 * 4);
+                b.rr = (float*)take(n3 * 4);
+            }
+        }
+        if (h) {
+            h->L64[l] = a;
+            h->L32[l] = b;
+        }
+    }
+    double* partial = (double*)take(sizeof(double) * kReduceBlocks);
+    double* scal = (double*)take(sizeof(double) * 16);
+    if (h) {
+        h->partial = partial;
+        h->scal = scal;
+    }
+    return off + 256;
+}
+
+bool valid_desc(const isis_mg_desc* d, char* err)
+{
+    if (!d) {
+        fmt_err(err, "desc is NULL");
+        return false;
+    }
+    if (!is_pow2_ge(d->N, 8) || d->N > 4096) {
+        fmt_err(err, "N must be a power of two in [8, 4096] (got %d)", d->N);
+        return false;
+    }
+    if (!finite_pos(d->box)) {
+        fmt_err(err, "box must be finite and > 0");
+        return false;
+    }
+    if (d->nu_pre < 0 || d->nu_post < 0 || d->nu_coarse < 1 || d->max_cycles < 1 ||
+        d->max_cycles >= ISIS_MG_MAX_HIST || d->nu_pre + d->nu_post < 1) {
+        fmt_err(err, "need nu_pre, nu_post >= 0 (sum >= 1), nu_coarse >= 1, "
+                     "1 <= max_cycles < %d", ISIS_MG_MAX_HIST);
+        return false;
+    }
+    if (d->precision != ISIS_FP64 && d->precision != ISIS_MIXED) {
+        fmt_err(err, "unknown precision %d", d->precision);
+        return false;
+    }
+    if (d->temporal_block < 0 || d->temporal_block > 2) {
+        fmt_err(err, "temporal_block must be 0, 1 or 2");
+        return false;
+    }
+    return true;
+}
+
+// sqrt(mean(L_0(phi)^2)) of the finest level, in double; res may be NULL.
+template <class TF, class M>
+int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* res, double* out)
+{
+    const int n = H->d.N;
+    const long n3 = (long)n * n * n;
+    const double h = H->L64[0].h;
+    int g = std::min(kReduceBlocks, grid_for(n3));
+    hipLaunchKernelGGL((k_defect_norm<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
+                       1.0 / (h * h), phi, eta, res, H->partial);
+    LAUNCH_CHECK(H->err, "k_defect_norm");
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
+    LAUNCH_CHECK(H->err, "k_reduce");
+    HIP_TRY(H->err, hipMemcpyAsync(H->host, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->s));
+    HIP_TRY(H->err, hipStreamSynchronize(H->s));
+    *out = std::sqrt(H->host[0] / (double)n3);
+    return ISIS_OK;
+}
+
+// sqrt(mean(f^2)) of a field.
+template <class T>
+int field_rms(isis_mg* H, const T* f, long n3, double* out)
+{
+    int g = std::min(kReduceBlocks, grid_for(n3));
+    hipLaunchKernelGGL((k_sumsq<T>), dim3(g), dim3(kBlock), 0, H->s, n3, f, H->partial);
+    LAUNCH_CHECK(H->err, "k_sumsq");
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
+    LAUNCH_CHECK(H->err, "k_reduce");
+    HIP_TRY(H->err, hipMemcpyAsync(H->host, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->s));
+    HIP_TRY(H->err, hipStreamSynchronize(H->s));
+    *out = std::sqrt(H->host[0] / (double)n3);
+    return ISIS_OK;
+}
+
+template <class T>
+int sub_mean(isis_mg* H, T* f, long n3)
+{
+    int g = std::min(kReduceBlocks, grid_for(n3));
+    hipLaunchKernelGGL((k_sum<T>), dim3(g), dim3(kBlock), 0, H->s, n3, f, H->partial);
+    LAUNCH_CHECK(H->err, "k_sum");
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
+    LAUNCH_CHECK(H->err, "k_reduce");
+    hipLaunchKernelGGL((k_sub_mean<T>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s, n3, f, H->scal);
+    LAUNCH_CHECK(H->err, "k_sub_mean");
+    return ISIS_OK;
+}
+
+// Smoothing step of level l; on the finest level with profiling on, the
+// launches are bracketed by HIP events on the solver stream.
+template <class T, class M>
+int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
+{
+    const int tb = H->d.temporal_block;
+    const bool timed = H->profile && l == 0 && count > 0 && H->ntimed < isis_mg::kMaxTimed;
+    const int q = H->ntimed;
+    if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
+    int r = launch_sweeps<T, M>(m, f.n, f.h, f.phi, f.tmp, f.eta, f.sigma, count, tb, H->s,
+                                H->err);
+    if (r) return r;
+    if (timed) {
+        HIP_TRY(H->err, hipEventRecord(H->ev1[q], H->s));
+        const double n3 = (double)f.n * f.n * f.n;
+        const int tblk = std::max(1, tb);
+        const bool fused = tb >= 1 && fused_supported<T, M>(f.n);
+        const int passes = fused ? (count + tblk - 1) / tblk : count;
+        H->tlaunch[q] = fused ? fused_launches(count, tb) : 2 * count;
+        H->tupd[q] = n3 * count;
+        H->tbytes[q] = (double)passes * n3 * 3.0 * sizeof(T);
+        H->ntimed = q + 1;
+    }
+    return ISIS_OK;
+}
+
+template <class T, class M>
+int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
+{
+    const isis_mg_desc& d = H->d;
+    LevP<T>& f = L[l];
+    const double n3 = (double)f.n * f.n * f.n;
+    int r;
+    if (l == H->nlev - 1) {
+        *updates += (double)d.nu_coarse * n3;
+        return launch_coarse<T, M>(m, f.h, f.phi, f.eta, f.sigma, d.nu_coarse, H->s, H->err);
+    }
+    LevP<T>& c = L[l + 1];
+    const int tb = d.temporal_block;
+    if ((r = timed_sweeps<T, M>(H, m, f, l, d.nu_pre))) return r;
+    *updates += d.nu_pre * n3;
+    if ((r = launch_descend<T, M>(m, f.n, f.h, f.phi, f.eta, f.sigma, c.eta, c.phi, c.phihat,
+                                  c.sigma, c.rr, H->s, H->err)))
+        return r;
+    if ((r = vcycle<T, M>(H, m, L, l + 1, updates))) return r;
+    if ((r = launch_prolong<T>(f.n, f.phi, c.phi, c.phihat, H->s, H->err))) return r;
+    if ((r = timed_sweeps<T, M>(H, m, f, l, d.nu_post))) return r;
+    *updates += d.nu_post * n3;
+    return ISIS_OK;
+}
+
+// The solve for one model; M64/M32 are its double and float device models.
+template <class M64, class M32>
+int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_params& p,
+               const double* density, double* field, double tol, int use_guess,
+               isis_mg_stats* st)
+{
+    const isis_mg_desc& d = H->d;
+    const int N = d.N;
+    const long n3 = (long)N * N * N;
+    const bool singular = (p.model == ISIS_LINEAR && p.m2 == 0.0);
+    const bool mixed = (d.precision == ISIS_MIXED);
+    int r;
+    H->ntimed = 0;
+    H->L64[0].phi = field;
+    H->L64[0].eta = const_cast<double*>(density);
+    H->L64[0].sigma = nullptr;
+    for (int l = 1; l < H->nlev; ++l)
+        if ((r = launch_restrict<double>(H->L64[l - 1].n, H->L64[l - 1].eta, H->L64[l].eta, H->s,
+                                         H->err)))
+            return r;
+
+    // r_ref from the cold start, whatever the initial guess.
+    double* cold = H->L64[0].tmp;
+    hipLaunchKernelGGL((k_cold_start<double, M64>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
+                       m64, n3, density, cold);
+    LAUNCH_CHECK(H->err, "k_cold_start");
+    double r_ref;
+    if ((r = fine_rms<double, M64>(H, m64, cold, density, nullptr, &r_ref))) return r;
+    if (!std::isfinite(r_ref)) {
+        fmt_err(H->err, "density gives a non-finite cold-start residual (NaN/Inf or invalid "
+                        "values in eta)");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    // A cold-start residual at the rounding level of its Laplacian means the
+    // cold start is an exact root (uniform density): absolute tolerance.
+    double cold_rms;
+    if ((r = field_rms<double>(H, cold, n3, &cold_rms))) return r;
+    const double h0 = H->L64[0].h;
+    const double cold_scale = 1e-14 * 6.0 / (h0 * h0) * cold_rms;
+    if (!use_guess)
+        HIP_TRY(H->err, hipMemcpyAsync(field, cold, sizeof(double) * n3,
+                                       hipMemcpyDeviceToDevice, H->s));
+    if (singular && (r = sub_mean<double>(H, field, n3))) return r;
+    const double rnorm = r_ref > cold_scale ? r_ref : 1.0;
+    double r0;
+    if ((r = fine_rms<double, M64>(H, m64, field, density, nullptr, &r0))) return r;
+    if (st) {
+        st->r_ref = r_ref;
+        st->r0 = r0;
+        st->rel_hist[0] = r0 / rnorm;
+        st->used_guess = use_guess ? 1 : 0;
+    }
+    double updates = 0.0, rcur = r0;
+    int cyc = 0, cyc32 = 0;
+    int status = ISIS_ERR_NOT_CONVERGED;
+    if (!std::isfinite(r0)) status = ISIS_ERR_DIVERGED;
+    else if (r0 <= tol * rnorm) status = ISIS_OK;
+
+    // Mixed precision, phase 1: FP32 V-cycles on the FP32 copy of the
+    // problem, monitored by the FP64 defect of the FP32 iterate.
+    if (mixed && status == ISIS_ERR_NOT_CONVERGED) {
+        for (int l = 0; l < H->nlev; ++l) {
+            long c3 = (long)H->L32[l].n * H->L32[l].n * H->L32[l].n;
+            hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(c3)), dim3(kBlock), 0,
+                               H->s, c3, H->L64[l].eta, H->L32[l].eta);
+            LAUNCH_CHECK(H->err, "k_convert");
+        }
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
+                           n3, field, H->L32[0].phi);
+        LAUNCH_CHECK(H->err, "k_convert");
+        H->L32[0].sigma = nullptr;
+        double rprev = r0;
+        while (cyc < d.max_cycles) {
+            if ((r = vcycle<float, M32>(H, m32, H->L32, 0, &updates))) return r;
+            if (singular && (r = sub_mean<float>(H, H->L32[0].phi, n3))) return r;
+            ++cyc;
+            ++cyc32;
+            double rc;
+            if ((r = fine_rms<float, M64>(H, m64, H->L32[0].phi, density, nullptr, &rc))) return r;
+            if (st) st->rel_hist[cyc] = rc / rnorm;
+            rcur = rc;
+            if (!std::isfinite(rc) || rc > 1e3 * r0) {
+                status = ISIS_ERR_DIVERGED;
+                break;
+            }
+            if (rc <= tol * rnorm) {
+                status = ISIS_OK;
+                break;
+            }
+            // FP32 round-off floor reached (or the FP32 phase stalls): refine in FP64.
+            if (rc > 0.6 * rprev || rc <= 3e-6 * rnorm) break;
+            rprev = rc;
+        }
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
+                           n3, H->L32[0].phi, field);
+        LAUNCH_CHECK(H->err, "k_convert");
+    }
+
+    // FP64 V-cycles (the whole solve in ISIS_FP64; the refinement phase in
+    // ISIS_MIXED).
+    while (status == ISIS_ERR_NOT_CONVERGED && cyc < d.max_cycles) {
+        if ((r = vcycle<double, M64>(H, m64, H->L64, 0, &updates))) return r;
+        if (singular && (r = sub_mean<double>(H, field, n3))) return r;
+        ++cyc;
+        double rc;
+        if ((r = fine_rms<double, M64>(H, m64, field, density, nullptr, &rc))) return r;
+        if (st) st->rel_hist[cyc] = rc / rnorm;
+        rcur = rc;
+        if (!std::isfinite(rc) || rc > 1e3 * r0) status = ISIS_ERR_DIVERGED;
+        else if (rc <= tol * rnorm) status = ISIS_OK;
+    }
+    HIP_TRY(H->err, hipStreamSynchronize(H->s));
+    if (st && H->profile) {
+        double ms = 0.0, upd = 0.0, bytes = 0.0;
+        int launches = 0;
+        for (int q = 0; q < H->ntimed; ++q) {
+            float e = 0.f;
+            HIP_TRY(H->err, hipEventElapsedTime(&e, H->ev0[q], H->ev1[q]));
+            ms += e;
+            launches += H->tlaunch[q];
+            upd += H->tupd[q];
+            bytes += H->tbytes[q];
+        }
+        st->fine_sweep_ms = ms;
+        st->fine_sweep_launches = launches;
+        st->fine_sweep_updates = upd;
+        st->fine_sweep_bytes = bytes;
+    }
+    if (st) {
+        st->cycles = cyc;
+        st->cycles_fp32 = cyc32;
+        st->rel_res = rcur / rnorm;
+        st->cell_updates = updates;
+    }
+    if (status == ISIS_ERR_NOT_CONVERGED)
+        fmt_err(H->err, "not converged after %d cycles (rel. residual %.3e)", cyc, rcur / rnorm);
+    if (status == ISIS_ERR_DIVERGED)
+        fmt_err(H->err, "diverged after %d cycles (residual %.3e, initial %.3e)", cyc, rcur, r0);
+    return status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI.
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+size_t isis_mg_workspace_size(const isis_mg_desc* desc)
+{
+    char err[512];
+    if (!valid_desc(desc, err)) return 0;
+    return carve(*desc, nullptr, nullptr);
+}
+
+int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out)
+{
+    if (!out) {
+        fmt_err(g_err, "out is NULL");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (!valid_desc(desc, g_err)) return ISIS_ERR_INVALID_ARG;
+    size_t need = carve(*desc, nullptr, nullptr);
+    if (!desc->workspace || desc->workspace_bytes < need || !aligned(desc->workspace, 256)) {
+        fmt_err(g_err, "workspace must be 256-byte aligned and >= %zu bytes", need);
+        return ISIS_ERR_INVALID_ARG;
+    }
+    isis_mg* H = new (std::nothrow) isis_mg();
+    if (!H) {
+        fmt_err(g_err, "out of host memory");
+        return ISIS_ERR_HIP;
+    }
+    H->d = *desc;
+    H->nlev = num_levels(desc->N);
+    H->s = (hipStream_t)desc->stream;
+    H->err[0] = 0;
+    if (hipGetDevice(&H->device) != hipSuccess ||
+        hipHostMalloc((void**)&H->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        fmt_err(g_err, "HIP device or pinned host buffer unavailable");
+        delete H;
+        return ISIS_ERR_HIP;
+    }
+    for (int q = 0; q < isis_mg::kMaxTimed; ++q) {
+        if (hipEventCreate(&H->ev0[q]) != hipSuccess || hipEventCreate(&H->ev1[q]) != hipSuccess) {
+            fmt_err(g_err, "hipEventCreate failed");
+            isis_mg_destroy(H);
+            return ISIS_ERR_HIP;
+        }
+    }
+    carve(*desc, (char*)desc->workspace, H);
+    *out = H;
+    return ISIS_OK;
+}
+
+int isis_mg_set_profiling(isis_mg_t* h, int enable)
+{
+    if (!h) {
+        fmt_err(g_err, "handle is NULL");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    h->profile = enable ? 1 : 0;
+    return ISIS_OK;
+}
+
+void isis_mg_destroy(isis_mg_t* h)
+{
+    if (!h) return;
+    for (int q = 0; q < isis_mg::kMaxTimed; ++q) {
+        if (h->ev0[q]) (void)hipEventDestroy(h->ev0[q]);
+        if (h->ev1[q]) (void)hipEventDestroy(h->ev1[q]);
+    }
+    if (h->host) (void)hipHostFree(h->host);
+    delete h;
+}
+
+const char* isis_mg_last_error(const isis_mg_t* h)
+{
+    return h ? h->err : g_err;
+}
+
+int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
+                  const isis_model_params* params, double a, double tol, int use_guess,
+                  isis_mg_stats* stats)
+{
+    if (!H) {
+        fmt_err(g_err, "handle is NULL");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    H->err[0] = 0;
+    auto t0 = std::chrono::steady_clock::now();
+    if (!density || !field || !aligned(density, 8) || !aligned(field, 8)) {
+        fmt_err(H->err, "density and field must be non-NULL, 8-byte aligned device pointers");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!valid_params(params, a, H->err)) return ISIS_ERR_INVALID_ARG;
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        fmt_err(H->err, "tol must be finite and > 0");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (hipSetDevice(H->device) != hipSuccess) return hip_fail(H->err, hipGetLastError(), "hipSetDevice");
+    if (stats) memset(stats, 0, sizeof(*stats));
+    int r;
+    switch (params->model) {
+    case ISIS_SYMMETRON:
+        r = solve_impl(H, make_symmetron<double>(*params, a), make_symmetron<float>(*params, a),
+                       *params, density, field, tol, use_guess, stats);
+        break;
+    case ISIS_FR_HS:
+        r = solve_impl(H, make_fofr<double>(*params, a), make_fofr<float>(*params, a), *params,
+                       density, field, tol, use_guess, stats);
+        break;
+    default:
+        r = solve_impl(H, make_linear<double>(*params), make_linear<float>(*params), *params,
+                       density, field, tol, use_guess, stats);
+        break;
+    }
+    if (stats) {
+        auto t1 = std::chrono::steady_clock::now();
+        stats->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    return r;
+}
+
+int isis_mg_residual(isis_mg_t* H, const double* density, const double* field,
+                     const isis_model_params* params, double a, double* out_res, double* out_rms)
+{
+    if (!H) {
+        fmt_err(g_err, "handle is NULL");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    H->err[0] = 0;
+    if (!density || !field || !aligned(density, 8) || !aligned(field, 8) ||
+        (out_res && !aligned(out_res, 8))) {
+        fmt_err(H->err, "density, field (and out_res) must be 8-byte aligned device pointers");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!valid_params(params, a, H->err)) return ISIS_ERR_INVALID_ARG;
+    if (hipSetDevice(H->device) != hipSuccess) return hip_fail(H->err, hipGetLastError(), "hipSetDevice");
+    double rms = 0.0;
+    int r = with_model<double>(*params, a, [&](auto m) {
+        return fine_rms<double, decltype(m)>(H, m, field, density, out_res, &rms);
+    });
+    if (r) return r;
+    if (out_rms) *out_rms = rms;
+    return ISIS_OK;
+}
+
+static bool op_grid_ok(int n, int lo)
+{
+    return n >= lo && n % 2 == 0 && n <= 4096;
+}
+
+int isis_op_halfsweep(const isis_model_params* p, double a, int n, double h, double* phi,
+                      const double* eta, const double* sigma, int colour, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!op_grid_ok(n, 2) || !finite_pos(h) || !phi || !eta || (colour != 0 && colour != 1)) {
+        fmt_err(g_err, "halfsweep: need even n >= 2, h > 0, phi/eta non-NULL, colour 0 or 1");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    return with_model<double>(*p, a, [&](auto m) {
+        return launch_halfsweep<double, decltype(m)>(m, n, h, phi, eta, sigma, colour,
+                                                     (hipStream_t)stream, g_err);
+    });
+}
+
+int isis_op_sweeps(const isis_model_params* p, double a, int n, double h, double* phi,
+                   double* tmp, const double* eta, const double* sigma, int count,
+                   int temporal_block, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!op_grid_ok(n, 2) || !finite_pos(h) || !phi || !tmp || !eta || count < 0 ||
+        temporal_block < 0 || temporal_block > 2) {
+        fmt_err(g_err, "sweeps: need even n >= 2, h > 0, phi/tmp/eta non-NULL, count >= 0, "
+                       "temporal_block in 0..2");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    return with_model<double>(*p, a, [&](auto m) {
+        return launch_sweeps<double, decltype(m)>(m, n, h, phi, tmp, eta, sigma, count,
+                                                  temporal_block, (hipStream_t)stream, g_err);
+    });
+}
+
+int isis_op_defect(const isis_model_params* p, double a, int n, double h, const double* phi,
+                   const double* eta, const double* sigma, double* out, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!op_grid_ok(n, 2) || !finite_pos(h) || !phi || !eta || !out) {
+        fmt_err(g_err, "defect: need even n >= 2, h > 0, phi/eta/out non-NULL");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    return with_model<double>(*p, a, [&](auto m) {
+        using M = decltype(m);
+        hipLaunchKernelGGL((k_defect<double, M>), dim3(grid_for((long)n * n * n)), dim3(kBlock),
+                           0, (hipStream_t)stream, m, n, 1.0 / (h * h), phi, eta, sigma, out);
+        LAUNCH_CHECK(g_err, "k_defect");
+        return (int)ISIS_OK;
+    });
+}
+
+int isis_op_restrict(int n_fine, const double* fine, double* coarse, void* stream)
+{
+    if (!op_grid_ok(n_fine, 2) || !fine || !coarse) {
+        fmt_err(g_err, "restrict: need even n_fine >= 2 and non-NULL arrays");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    return launch_restrict<double>(n_fine, fine, coarse, (hipStream_t)stream, g_err);
+}
+
+int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double h_fine,
+                        const double* phi_f, const double* eta_f, const double* sigma_f,
+                        const double* eta_c, double* phi_c, double* phihat_c, double* sigma_c,
+                        double* rr_c, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!op_grid_ok(n_fine, 4) || !finite_pos(h_fine) || !phi_f || !eta_f || !eta_c || !phi_c ||
+        !phihat_c || !sigma_c || !rr_c) {
+        fmt_err(g_err, "fas_descend: need even n_fine >= 4, h > 0, non-NULL arrays");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    return with_model<double>(*p, a, [&](auto m) {
+        return launch_descend<double, decltype(m)>(m, n_fine, h_fine, phi_f, eta_f, sigma_f,
+                                                   eta_c, phi_c, phihat_c, sigma_c, rr_c,
+                                                   (hipStream_t)stream, g_err);
+    });
+}
+
+int isis_op_prolong_correct(int n_fine, double* fine, const double* coarse,
+                            const double* coarse_hat, void* stream)
+{
+    if (!op_grid_ok(n_fine, 4) || !fine || !coarse || !coarse_hat) {
+        fmt_err(g_err, "prolong_correct: need even n_fine >= 4 and non-NULL arrays");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    return launch_prolong<double>(n_fine, fine, coarse, coarse_hat, (hipStream_t)stream, g_err);
+}
+
+int isis_op_coarse_solve(const isis_model_params* p, double a, double h, double* phi,
+                         const double* eta, const double* sigma, int nu_c, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!finite_pos(h) || !phi || !eta || nu_c < 0) {
+        fmt_err(g_err, "coarse_solve: need h > 0, phi/eta non-NULL, nu_c >= 0");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    return with_model<double>(*p, a, [&](auto m) {
+        return launch_coarse<double, decltype(m)>(m, h, phi, eta, sigma, nu_c,
+                                                  (hipStream_t)stream, g_err);
+    });
+}
+
+int isis_op_cold_start(const isis_model_params* p, double a, long ncell, const double* eta,
+                       double* phi, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (ncell < 0 || (ncell > 0 && (!eta || !phi))) {
+        fmt_err(g_err, "cold_start: need ncell >= 0 and non-NULL arrays");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (ncell == 0) return ISIS_OK;
+    return with_model<double>(*p, a, [&](auto m) {
+        using M = decltype(m);
+        hipLaunchKernelGGL((k_cold_start<double, M>), dim3(grid_for(ncell)), dim3(kBlock), 0,
+                           (hipStream_t)stream, m, ncell, eta, phi);
+        LAUNCH_CHECK(g_err, "k_cold_start");
+        return (int)ISIS_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+"""Python face of the GPU solver: torch tensors in, C ABI calls out.
+
+PyTorch provides device memory and the stream; every step of the solve runs
+in the HIP kernels of libisis_mg.so.  There is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _capi as A
+
+
+class IsisError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"isis_mg error {code}: {msg}")
+        self.code = code
+
+
+class NotConverged(IsisError):
+    pass
+
+
+class Diverged(IsisError):
+    pass
+
+
+def _raise(code: int, msg: str):
+    if code == A.ISIS_ERR_NOT_CONVERGED:
+        raise NotConverged(code, msg)
+    if code == A.ISIS_ERR_DIVERGED:
+        raise Diverged(code, msg)
+    raise IsisError(code, msg)
+
+
+@dataclass
+class ModelParams:
+    """Model parameters (lengths in comoving Mpc/h, c = 1)."""
+    model: int = A.ISIS_SYMMETRON
+    lambda0: float = 1.0
+    a_ssb: float = 0.5
+    beta: float = 1.0
+    n: float = 1.0
+    fR0_abs: float = 1e-5
+    omega_m: float = 0.27
+    omega_l: float = 0.73
+    kappa: float = 1.0
+    m2: float = 0.0
+
+    def c(self) -> A.ModelParamsC:
+        return A.ModelParamsC(int(self.model), self.lambda0, self.a_ssb, self.beta, self.n,
+                              self.fR0_abs, self.omega_m, self.omega_l, self.kappa, self.m2)
+
+
+def symmetron(lambda0=1.0, a_ssb=0.5, beta=1.0) -> ModelParams:
+    return ModelParams(model=A.ISIS_SYMMETRON, lambda0=lambda0, a_ssb=a_ssb, beta=beta)
+
+
+def fofr(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=None) -> ModelParams:
+    ol = 1.0 - omega_m if omega_l is None else omega_l
+    return ModelParams(model=A.ISIS_FR_HS, n=n, fR0_abs=fR0_abs, omega_m=omega_m, omega_l=ol)
+
+
+def linear(kappa=1.0, m2=0.0) -> ModelParams:
+    return ModelParams(model=A.ISIS_LINEAR, kappa=kappa, m2=m2)
+
+
+@dataclass
+class Stats:
+    status: int
+    cycles: int
+    cycles_fp32: int
+    r_ref: float
+    r0: float
+    rel_res: float
+    rel_hist: list = field(default_factory=list)
+    ms_total: float = 0.0
+    cell_updates: float = 0.0
+    used_guess: bool = False
+    fine_sweep_ms: float = 0.0
+    fine_sweep_launches: int = 0
+    fine_sweep_updates: float = 0.0
+    fine_sweep_bytes: float = 0.0
+
+    @staticmethod
+    def from_c(status: int, s: A.StatsC) -> "Stats":
+        return Stats(status, s.cycles, s.cycles_fp32, s.r_ref, s.r0, s.rel_res,
+                     list(s.rel_hist[: s.cycles + 1]), s.ms_total, s.cell_updates,
+                     bool(s.used_guess), s.fine_sweep_ms, s.fine_sweep_launches,
+                     s.fine_sweep_updates, s.fine_sweep_bytes)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _check_field(t: torch.Tensor, n: int, name: str, dtype=torch.float64):
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != n ** 3:
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor with {n}^3 elements")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+PRECISIONS = {"fp64": A.ISIS_FP64, "mixed": A.ISIS_MIXED}
+
+
+class Solver:
+    """FAS multigrid solver for one grid size (one C-ABI handle).
+
+    The workspace is a torch uint8 tensor on the current device; kernels run
+    on the torch stream current at construction."""
+
+    def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = 2,
+                 nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
+                 temporal_block: int = 0):
+        self.N, self.box = int(N), float(box)
+        self._h = None
+        lib = A.lib()
+        d = A.DescC(self.N, self.box, nu_pre, nu_post, nu_coarse, max_cycles,
+                    PRECISIONS[precision], temporal_block, _stream(), None, 0)
+        nbytes = lib.isis_mg_workspace_size(C.byref(d))
+        if nbytes == 0:
+            raise ValueError("invalid solver description (N, box, nu_*, max_cycles, precision, "
+                             "temporal_block)")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        d.workspace = C.c_void_p(self.workspace.data_ptr())
+        d.workspace_bytes = nbytes
+        h = C.c_void_p()
+        rc = lib.isis_mg_create(C.byref(d), C.byref(h))
+        if rc != A.ISIS_OK:
+            _raise(rc, lib.isis_mg_last_error(None).decode())
+        self._h = h
+        self._desc = d
+
+    def set_profiling(self, enable: bool = True):
+        """Time the finest-level sweep launches with HIP events (see Stats)."""
+        rc = A.lib().isis_mg_set_profiling(self._h, 1 if enable else 0)
+        if rc != A.ISIS_OK:
+            _raise(rc, self._err())
+
+    def close(self):
+        if self._h is not None:
+            A.lib().isis_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self) -> str:
+        return A.lib().isis_mg_last_error(self._h).decode()
+
+    def solve(self, eta: torch.Tensor, params: ModelParams, a: float, tol: float,
+              phi: torch.Tensor | None = None, use_guess: bool = False,
+              check: bool = True) -> tuple[torch.Tensor, Stats]:
+        """Solve L(phi, eta) = 0.  If `phi` is given it receives the solution
+        (and is the initial guess when use_guess is True)."""
+        _check_field(eta, self.N, "eta")
+        if phi is None:
+            phi = torch.empty_like(eta)
+            use_guess = False
+        _check_field(phi, self.N, "phi")
+        st = A.StatsC()
+        pc = params.c()
+        rc = A.lib().isis_mg_solve(self._h, _ptr(eta), _ptr(phi), C.byref(pc), float(a),
+                                   float(tol), 1 if use_guess else 0, C.byref(st))
+        stats = Stats.from_c(rc, st)
+        if check and rc != A.ISIS_OK:
+            _raise(rc, self._err())
+        if rc in (A.ISIS_ERR_INVALID_ARG, A.ISIS_ERR_HIP, A.ISIS_ERR_UNSUPPORTED):
+            _raise(rc, self._err())
+        return phi, stats
+
+    def residual(self, eta: torch.Tensor, phi: torch.Tensor, params: ModelParams, a: float,
+                 out: torch.Tensor | None = None) -> float:
+        _check_field(eta, self.N, "eta")
+        _check_field(phi, self.N, "phi")
+        if out is not None:
+            _check_field(out, self.N, "out")
+        rms = C.c_double()
+        pc = params.c()
+        rc = A.lib().isis_mg_residual(self._h, _ptr(eta), _ptr(phi), C.byref(pc), float(a),
+                                      _ptr(out), C.byref(rms))
+        if rc != A.ISIS_OK:
+            _raise(rc, self._err())
+        return rms.value
+
+
+# ---------------------------------------------------------------------------
+# Level operators (one V-cycle step each) on torch tensors, in place.
+# ---------------------------------------------------------------------------
+
+def _side(t: torch.Tensor) -> int:
+    n = round(t.numel() ** (1.0 / 3.0))
+    if n ** 3 != t.numel():
+        raise ValueError("field is not cubic")
+    return n
+
+
+def _ok(rc: int):
+    if rc != A.ISIS_OK:
+        _raise(rc, A.lib().isis_mg_last_error(None).decode())
+
+
+def halfsweep(params: ModelParams, a: float, h: float, phi, eta, sigma=None, colour: int = 0):
+    n = _side(phi)
+    for t, nm in ((phi, "phi"), (eta, "eta")):
+        _check_field(t, n, nm)
+    if sigma is not None:
+        _check_field(sigma, n, "sigma")
+    pc = params.c()
+    _ok(A.lib().isis_op_halfsweep(C.byref(pc), float(a), n, float(h), _ptr(phi), _ptr(eta),
+                                  _ptr(sigma), int(colour), _stream()))
+
+
+def sweeps(params: ModelParams, a: float, h: float, phi, eta, sigma=None, count: int = 1,
+           temporal_block: int = 0, tmp=None):
+    n = _side(phi)
+    _check_field(phi, n, "phi")
+    _check_field(eta, n, "eta")
+    if sigma is not None:
+        _check_field(sigma, n, "sigma")
+    tmp = torch.empty_like(phi) if tmp is None else tmp
+    pc = params.c()
+    _ok(A.lib().isis_op_sweeps(C.byref(pc), float(a), n, float(h), _ptr(phi), _ptr(tmp),
+                               _ptr(eta), _ptr(sigma), int(count), int(temporal_block),
+                               _stream()))
+
+
+def defect(params: ModelParams, a: float, h: float, phi, eta, sigma=None, out=None):
+    n = _side(phi)
+    _check_field(phi, n, "phi")
+    _check_field(eta, n, "eta")
+    out = torch.empty_like(phi) if out is None else out
+    pc = params.c()
+    _ok(A.lib().isis_op_defect(C.byref(pc), float(a), n, float(h), _ptr(phi), _ptr(eta),
+                               _ptr(sigma), _ptr(out), _stream()))
+    return out
+
+
+def restrict(fine, out=None):
+    n = _side(fine)
+    _check_field(fine, n, "fine")
+    out = torch.empty(fine.numel() // 8, dtype=fine.dtype, device=fine.device) if out is None else out
+    _ok(A.lib().isis_op_restrict(n, _ptr(fine), _ptr(out), _stream()))
+    return out
+
+
+def fas_descend(params: ModelParams, a: float, h_fine: float, phi_f, eta_f, sigma_f, eta_c):
+    n = _side(phi_f)
+    _check_field(phi_f, n, "phi_f")
+    _check_field(eta_f, n, "eta_f")
+    _check_field(eta_c, n // 2, "eta_c")
+    mk = lambda: torch.empty_like(eta_c)  # noqa: E731
+    phi_c, phihat_c, sigma_c, rr_c = mk(), mk(), mk(), mk()
+    pc = params.c()
+    _ok(A.lib().isis_op_fas_descend(C.byref(pc), float(a), n, float(h_fine), _ptr(phi_f),
+                                    _ptr(eta_f), _ptr(sigma_f), _ptr(eta_c), _ptr(phi_c),
+                                    _ptr(phihat_c), _ptr(sigma_c), _ptr(rr_c), _stream()))
+    return phi_c, phihat_c, sigma_c
+
+
+def prolong_correct(fine, coarse, coarse_hat):
+    n = _side(fine)
+    _check_field(fine, n, "fine")
+    _check_field(coarse, n // 2, "coarse")
+    _check_field(coarse_hat, n // 2, "coarse_hat")
+    _ok(A.lib().isis_op_prolong_correct(n, _ptr(fine), _ptr(coarse), _ptr(coarse_hat), _stream()))
+
+
+def coarse_solve(params: ModelParams, a: float, h: float, phi, eta, sigma=None, nu_c: int = 32):
+    _check_field(phi, 4, "phi")
+    _check_field(eta, 4, "eta")
+    pc = params.c()
+    _ok(A.lib().isis_op_coarse_solve(C.byref(pc), float(a), float(h), _ptr(phi), _ptr(eta),
+                                     _ptr(sigma), int(nu_c), _stream()))
+
+
+def cold_start(params: ModelParams, a: float, eta, out=None):
+    out = torch.empty_like(eta) if out is None else out
+    pc = params.c()
+    _ok(A.lib().isis_op_cold_start(C.byref(pc), float(a), eta.numel(), _ptr(eta), _ptr(out),
+                                   _stream()))
+    return out

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+the header declares, and rejects invalid arguments before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1307_6748_amd import _capi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "isis_mg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b(isis_[a-z0-9_]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("isis_mg_create", "isis_mg_solve", "isis_mg_residual", "isis_mg_destroy"):
+        assert n in names
+    assert len(names) >= 14
+
+
+def test_library_exports_every_declared_symbol():
+    lib = A.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(n for n, _, _ in A.SIGNATURES) == declared_functions()
+
+
+def _desc(**kw):
+    d = A.DescC(64, 64.0, 2, 2, 32, 50, A.ISIS_FP64, 0, None, None, 0)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_workspace_size_validation():
+    lib = A.lib()
+    ok = lib.isis_mg_workspace_size(C.byref(_desc()))
+    assert ok > 0
+    # bigger with the FP32 hierarchy of the mixed mode
+    assert lib.isis_mg_workspace_size(C.byref(_desc(precision=A.ISIS_MIXED))) > ok
+    for bad in (dict(N=12), dict(N=4), dict(box=0.0), dict(box=float("nan")),
+                dict(nu_coarse=0), dict(max_cycles=0), dict(max_cycles=A.MAX_HIST),
+                dict(precision=7), dict(temporal_block=3), dict(nu_pre=0, nu_post=0)):
+        assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad
+
+
+def test_create_rejects_bad_workspace_without_gpu():
+    lib = A.lib()
+    h = C.c_void_p()
+    assert lib.isis_mg_create(C.byref(_desc()), C.byref(h)) == A.ISIS_ERR_INVALID_ARG
+    assert h.value is None
+    assert b"workspace" in lib.isis_mg_last_error(None)
+    assert lib.isis_mg_create(C.byref(_desc(N=10)), C.byref(h)) == A.ISIS_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("params,a", [
+    (A.ModelParamsC(A.ISIS_SYMMETRON, 0.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0), 1.0),
+    (A.ModelParamsC(A.ISIS_SYMMETRON, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0), 0.0),
+    (A.ModelParamsC(A.ISIS_SYMMETRON, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0), float("nan")),
+    (A.ModelParamsC(A.ISIS_FR_HS, 1.0, 0.5, 1, 1, 0.0, 0.27, 0.73, 1, 0), 1.0),
+    (A.ModelParamsC(A.ISIS_FR_HS, 1.0, 0.5, 1, -1.0, 1e-5, 0.27, 0.73, 1, 0), 1.0),
+    (A.ModelParamsC(A.ISIS_LINEAR, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, -1.0), 1.0),
+    (A.ModelParamsC(9, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0), 1.0),
+])
+def test_ops_validate_params_on_host(params, a):
+    lib = A.lib()
+    rc = lib.isis_op_defect(C.byref(params), a, 8, 1.0, None, None, None, None, None)
+    assert rc == A.ISIS_ERR_INVALID_ARG
+    assert lib.isis_mg_last_error(None)
+
+
+def test_ops_validate_sizes_on_host():
+    lib = A.lib()
+    p = A.ModelParamsC(A.ISIS_LINEAR, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0)
+    fake = C.c_void_p(256)  # never dereferenced: validation fails first
+    assert lib.isis_op_halfsweep(C.byref(p), 1.0, 7, 1.0, fake, fake, None, 0, None) == -1
+    assert lib.isis_op_halfsweep(C.byref(p), 1.0, 8, 1.0, fake, fake, None, 2, None) == -1
+    assert lib.isis_op_restrict(5, fake, fake, None) == -1
+    assert lib.isis_op_prolong_correct(2, fake, fake, fake, None) == -1
+    assert lib.isis_op_sweeps(C.byref(p), 1.0, 8, 1.0, fake, fake, fake, None, 1, 5, None) == -1
+    assert lib.isis_op_cold_start(C.byref(p), 1.0, 0, None, None, None) == 0

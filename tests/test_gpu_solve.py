@@ -1,0 +1,200 @@
+"""GPU FAS solve vs the oracle's FAS solve (same algorithm, same inputs).
+
+Per-V-cycle relative residuals must agree (they are the convergence factors
+of the method); the field after k cycles and at convergence must agree
+element by element.  The GPU runs FMA-contracted arithmetic, so agreement is
+to rounding (~1e-13 relative), not bitwise.
+"""
+import numpy as np
+import pytest
+
+from gpucase import cubic, dev, models
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(n, box, **kw):
+    from paper_1307_6748_amd import solver as S
+    return S.Solver(n, box, **kw)
+
+
+def _hist_close(g, o, rtol=1e-6, floor=1e-12):
+    g, o = np.asarray(g), np.asarray(o)
+    assert len(g) == len(o), (g, o)
+    assert np.all(np.abs(g - o) <= rtol * np.abs(o) + floor), (g, o)
+
+
+def _wl(name, n=None):
+    from paper_1307_6748_amd import synth
+    return synth.workload(name, n)
+
+
+@pytest.mark.parametrize("tb", [0, 1, 2])
+def test_small_symmetron_config(orc, tb):
+    """32^3 symmetron, box 64, lambda0 = 1, a_ssb = 0.5, a = 1, lognormal
+    sigma_delta = 1: solve to 1e-10, per-cycle factors and field vs oracle."""
+    om, sp, a = models("symmetron_a1")
+    w = _wl("small_symmetron")
+    ro = orc.solve(om, w["eta"], w["box"], tol=1e-10)
+    s = _solver(32, w["box"], temporal_block=tb)
+    phi, st = s.solve(dev(w["eta"]), sp, a, 1e-10)
+    assert st.status == 0 and ro.status == 0
+    assert st.cycles == ro.cycles
+    _hist_close(st.rel_hist, ro.rel_hist)
+    assert abs(st.r_ref - ro.r_ref) <= 1e-12 * ro.r_ref
+    got = cubic(phi, 32)
+    assert np.max(np.abs(got - ro.phi)) <= 1e-11 * np.abs(ro.phi).max()
+    assert st.cell_updates > 0 and st.ms_total > 0
+
+
+@pytest.mark.parametrize("name", ["symmetron_a1", "symmetron_a05", "fofr", "fofr_a07", "linear",
+                                  "linear_m0"])
+@pytest.mark.parametrize("n", [16, 64])
+def test_k_cycles_match(orc, name, n):
+    """Exactly k V-cycles from the cold start: identical iterates."""
+    from paper_1307_6748_amd import synth
+    om, sp, a = models(name)
+    box = 4.0 * n
+    eta = synth.lognormal(n, box, 2.0, 100 + n)
+    k = 3
+    cold = orc.cold_start(om, eta)
+    if name == "linear_m0":
+        cold = cold - cold.mean()
+    ro = orc.vcycles(om, eta, box, cold, k)
+    s = _solver(n, box, max_cycles=k)
+    phi, st = s.solve(dev(eta), sp, a, 1e-300, check=False)
+    assert st.status == -2 and st.cycles == k
+    _hist_close(st.rel_hist, ro.rel_hist, rtol=1e-8)
+    got = cubic(phi, n)
+    assert np.max(np.abs(got - ro.phi)) <= 1e-12 * (np.abs(ro.phi).max() + 1e-300)
+
+
+@pytest.mark.parametrize("a", [0.5, 0.6, 0.8, 1.0])
+def test_symmetron_a_sweep_64(orc, a):
+    """The a sweep of the 256^3 workload on a 64^3 grid of the same box
+    (h = 4): lognormal sigma_delta = 3 (contrast 1e-2 .. 1e3)."""
+    from paper_1307_6748_amd import synth
+    om, sp, _ = models("symmetron_a1")
+    om.a = a
+    eta = synth.lognormal(64, 256.0, 3.0, 2)
+    ro = orc.solve(om, eta, 256.0, tol=1e-10)
+    phi, st = _solver(64, 256.0).solve(dev(eta), sp, a, 1e-10)
+    assert ro.status == 0 and st.status == 0 and st.cycles == ro.cycles
+    _hist_close(st.rel_hist, ro.rel_hist, rtol=1e-5)
+    assert np.max(np.abs(cubic(phi, 64) - ro.phi)) <= 1e-9 * np.abs(ro.phi).max()
+
+
+def test_fofr_with_haloes_64(orc):
+    """f(R) with lognormal + NFW haloes on 64^3 (box 128): stiff regime."""
+    om, sp, a = models("fofr")
+    w = _wl("fr_256", 64)
+    ro = orc.solve(om, w["eta"], w["box"], tol=1e-10)
+    phi, st = _solver(64, w["box"]).solve(dev(w["eta"]), sp, a, 1e-10)
+    assert ro.status == 0 and st.status == 0 and st.cycles == ro.cycles
+    _hist_close(st.rel_hist, ro.rel_hist, rtol=1e-5)
+    ref = ro.phi
+    assert np.max(np.abs(cubic(phi, 64) - ref)) <= 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("m2", [0.0, 0.3])
+def test_linear_sine_exact(orc, m2):
+    """Linear problem with a sine source: exact discrete solution."""
+    from paper_1307_6748_amd import solver as S
+    from paper_1307_6748_amd import synth
+    n, box, kappa = 32, 20.0, 1.7
+    h = box / n
+    modes = (1, 3, 2)
+    s = synth.sine_mode(n, box, modes)
+    lam = sum((2 - 2 * np.cos(2 * np.pi * m / n)) / h ** 2 for m in modes)
+    exact = -kappa * s / (lam + m2)
+    phi, st = _solver(n, box).solve(dev(1.0 + s), S.linear(kappa, m2), 1.0, 1e-12)
+    assert st.status == 0
+    assert np.max(np.abs(cubic(phi, n) - exact)) < 1e-11 * np.abs(exact).max()
+
+
+def test_homogeneous_perturbed_guess(orc):
+    """Uniform density (r_ref at rounding level: absolute tolerance) from a
+    perturbed guess."""
+    from paper_1307_6748_amd import synth
+    om, sp, a = models("symmetron_a1")
+    n = 16
+    eta = synth.uniform(n, 2.0)
+    chi = np.sqrt(1 - 0.125 * 2.0)
+    guess = chi + 0.05 * synth.random_field(n, 3)
+    ro = orc.solve(om, eta, 32.0, tol=1e-12, phi0=guess)
+    phi, st = _solver(n, 32.0).solve(dev(eta), sp, a, 1e-12, phi=dev(guess), use_guess=True)
+    assert st.status == 0 and st.used_guess and st.r_ref < 1e-15
+    assert np.max(np.abs(cubic(phi, n) - chi)) < 1e-11
+    assert np.max(np.abs(cubic(phi, n) - ro.phi)) < 1e-12
+
+
+def test_domain_wall(orc):
+    """Planar walls from the tanh guess: GPU follows the oracle iterate."""
+    from paper_1307_6748_amd import synth
+    om, sp, a = models("symmetron_a1")
+    n, box = 32, 32.0
+    v = np.sqrt(1 - 0.125)
+    d = 2.0 / v
+    x = synth.cell_centres(n, box)
+    prof = v * np.tanh((x - 8) / d) * np.tanh((24 - x) / d)
+    guess = np.ascontiguousarray(np.broadcast_to(prof[:, None, None], (n, n, n)))
+    eta = synth.uniform(n, 1.0)
+    ro = orc.vcycles(om, eta, box, guess, 8)
+    phi, st = _solver(n, box, max_cycles=8).solve(dev(eta), sp, a, 1e-300, phi=dev(guess),
+                                                  use_guess=True, check=False)
+    assert st.cycles == 8
+    assert np.max(np.abs(cubic(phi, n) - ro.phi)) < 1e-11
+
+
+def test_residual_api(orc):
+    from paper_1307_6748_amd import synth
+    om, sp, a = models("fofr")
+    n, box = 32, 64.0
+    eta = synth.lognormal(n, box, 2.0, 7)
+    u = orc.cold_start(om, eta) + 0.1 * synth.random_field(n, 8)
+    s = _solver(n, box)
+    out = dev(np.zeros((n, n, n)))
+    rms = s.residual(dev(eta), dev(u), sp, a, out=out)
+    ref = orc.defect(om, box / n, u, eta)
+    assert abs(rms - orc.rms(ref)) <= 1e-12 * orc.rms(ref)
+    assert np.max(np.abs(cubic(out, n) - ref)) <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name,wl,n", [("symmetron_a1", "small_symmetron", 32),
+                                       ("symmetron_a1", "symmetron_256", 64),
+                                       ("fofr", "fr_256", 64)])
+def test_mixed_precision_matches_oracle(orc, name, wl, n):
+    """FP32 smoothing and coarse-grid cycles, FP64 defect and refinement:
+    reaches the same relative residual and agrees with the oracle's converged
+    field to <= 1e-6 relative L2."""
+    om, sp, a = models(name)
+    w = _wl(wl, n)
+    ro = orc.solve(om, w["eta"], w["box"], tol=1e-12)
+    phi, st = _solver(n, w["box"], precision="mixed").solve(dev(w["eta"]), sp, a, 1e-8)
+    assert st.status == 0 and st.rel_res <= 1e-8
+    assert st.cycles_fp32 >= 1
+    got = cubic(phi, n)
+    err = np.linalg.norm(got - ro.phi) / np.linalg.norm(ro.phi)
+    assert err <= 1e-6, err
+
+
+def test_not_converged_and_errors(orc):
+    from paper_1307_6748_amd import solver as S
+    from paper_1307_6748_amd import synth
+    om, sp, a = models("symmetron_a1")
+    w = _wl("small_symmetron")
+    s = _solver(32, w["box"], max_cycles=1)
+    with pytest.raises(S.NotConverged):
+        s.solve(dev(w["eta"]), sp, a, 1e-10)
+    with pytest.raises(S.IsisError):
+        s.solve(dev(w["eta"]), sp, -1.0, 1e-10)
+    with pytest.raises(S.IsisError):
+        s.solve(dev(w["eta"]), sp, 1.0, 0.0)
+    with pytest.raises(ValueError):
+        s.solve(dev(synth.uniform(16, 1.0)), sp, 1.0, 1e-8)
+    # a NaN in the density is reported, not hidden
+    bad = w["eta"].copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(S.IsisError) as e:
+        _solver(32, w["box"]).solve(dev(bad), sp, a, 1e-8)
+    assert e.value.code == -1
