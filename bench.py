@@ -89,7 +89,7 @@ def main() -> int:
 
     n = args.n
     box = 256.0
-    tb = args.temporal_block if args.temporal_block >= 0 else 2
+    tb = args.temporal_block if args.temporal_block >= 0 else 1
     log(f"generating density {n}^3 (lognormal sigma_delta=2 seed 20 + 400 NFW seed 22)")
     t0 = time.time()
     eta_np = synth.lognormal_nfw(n, box, 2.0, 20, 400, 22, omega_m=0.27,

@@ -176,19 +176,26 @@ int launch_halfsweep(const M& m, int n, double h, T* phi, const T* eta, const T*
     return ISIS_OK;
 }
 
-// count full sweeps; result in phi.  tmp (n^3) is used by the fused kernels.
+// count full sweeps of *phi.  The fused kernels work out of place between
+// *phi and *tmp (n^3 each) and may leave the two pointers swapped: on return
+// *phi is the buffer that holds the result.
+// Levels smaller than this (per side) use the per-colour kernels inside the
+// solver: there the streaming pipeline of the fused kernel has too few
+// workgroups to hide its per-plane latency.
+constexpr int kFusedSolverMinN = 256;
+
 template <class T, class M>
-int launch_sweeps(const M& m, int n, double h, T* phi, T* tmp, const T* eta, const T* sigma,
-                  int count, int tb, hipStream_t s, char* err)
+int launch_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta, const T* sigma,
+                  int count, int tb, hipStream_t s, char* err, int min_fused_n = kFusedSolverMinN)
 {
     if (count <= 0) return ISIS_OK;
-    if (tb >= 1 && fused_supported<T, M>(n)) {
+    if (tb >= 1 && n >= min_fused_n && fused_supported<T, M>(n)) {
         return launch_fused_sweeps<T, M>(m, n, h, phi, tmp, eta, sigma, count, tb, s, err);
     }
     for (int q = 0; q < count; ++q) {
-        int r = launch_halfsweep<T, M>(m, n, h, phi, eta, sigma, 0, s, err);
+        int r = launch_halfsweep<T, M>(m, n, h, *phi, eta, sigma, 0, s, err);
         if (r) return r;
-        r = launch_halfsweep<T, M>(m, n, h, phi, eta, sigma, 1, s, err);
+        r = launch_halfsweep<T, M>(m, n, h, *phi, eta, sigma, 1, s, err);
         if (r) return r;
     }
     return ISIS_OK;
@@ -267,6 +274,7 @@ struct isis_mg {
     double* partial;  // kReduceBlocks
     double* scal;     // 16
     double* host;     // pinned, 16
+    double* tmp0;     // finest-level scratch field (workspace)
     char err[512];
     // finest-level sweep timing
     static constexpr int kMaxTimed = 2 * ISIS_MG_MAX_HIST + 8;
@@ -320,6 +328,7 @@ size_t carve(const isis_mg_desc& d, char* base, isis_mg* h)
         if (h) {
             h->L64[l] = a;
             h->L32[l] = b;
+            if (l == 0) h->tmp0 = a.tmp;
         }
     }
     double* partial = (double*)take(sizeof(double) * kReduceBlocks);
@@ -418,14 +427,14 @@ int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
     const bool timed = H->profile && l == 0 && count > 0 && H->ntimed < isis_mg::kMaxTimed;
     const int q = H->ntimed;
     if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
-    int r = launch_sweeps<T, M>(m, f.n, f.h, f.phi, f.tmp, f.eta, f.sigma, count, tb, H->s,
+    int r = launch_sweeps<T, M>(m, f.n, f.h, &f.phi, &f.tmp, f.eta, f.sigma, count, tb, H->s,
                                 H->err);
     if (r) return r;
     if (timed) {
         HIP_TRY(H->err, hipEventRecord(H->ev1[q], H->s));
         const double n3 = (double)f.n * f.n * f.n;
         const int tblk = std::max(1, tb);
-        const bool fused = tb >= 1 && fused_supported<T, M>(f.n);
+        const bool fused = tb >= 1 && f.n >= kFusedSolverMinN && fused_supported<T, M>(f.n);
         const int passes = fused ? (count + tblk - 1) / tblk : count;
         H->tlaunch[q] = fused ? fused_launches(count, tb) : 2 * count;
         H->tupd[q] = n3 * count;
@@ -474,6 +483,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     int r;
     H->ntimed = 0;
     H->L64[0].phi = field;
+    H->L64[0].tmp = H->tmp0;
     H->L64[0].eta = const_cast<double*>(density);
     H->L64[0].sigma = nullptr;
     for (int l = 1; l < H->nlev; ++l)
@@ -504,6 +514,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                                        hipMemcpyDeviceToDevice, H->s));
     if (singular && (r = sub_mean<double>(H, field, n3))) return r;
     const double rnorm = r_ref > cold_scale ? r_ref : 1.0;
+    LevP<double>& F = H->L64[0];  // F.phi: the current finest field (may move to tmp0)
     double r0;
     if ((r = fine_rms<double, M64>(H, m64, field, density, nullptr, &r0))) return r;
     if (st) {
@@ -554,7 +565,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             rprev = rc;
         }
         hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                           n3, H->L32[0].phi, field);
+                           n3, H->L32[0].phi, F.phi);
         LAUNCH_CHECK(H->err, "k_convert");
     }
 
@@ -562,14 +573,20 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     // ISIS_MIXED).
     while (status == ISIS_ERR_NOT_CONVERGED && cyc < d.max_cycles) {
         if ((r = vcycle<double, M64>(H, m64, H->L64, 0, &updates))) return r;
-        if (singular && (r = sub_mean<double>(H, field, n3))) return r;
+        if (singular && (r = sub_mean<double>(H, F.phi, n3))) return r;
         ++cyc;
         double rc;
-        if ((r = fine_rms<double, M64>(H, m64, field, density, nullptr, &rc))) return r;
+        if ((r = fine_rms<double, M64>(H, m64, F.phi, density, nullptr, &rc))) return r;
         if (st) st->rel_hist[cyc] = rc / rnorm;
         rcur = rc;
         if (!std::isfinite(rc) || rc > 1e3 * r0) status = ISIS_ERR_DIVERGED;
         else if (rc <= tol * rnorm) status = ISIS_OK;
+    }
+    if (F.phi != field) {  // an odd number of fused passes left the result in tmp0
+        HIP_TRY(H->err, hipMemcpyAsync(field, F.phi, sizeof(double) * n3,
+                                       hipMemcpyDeviceToDevice, H->s));
+        F.tmp = F.phi;
+        F.phi = field;
     }
     HIP_TRY(H->err, hipStreamSynchronize(H->s));
     if (st && H->profile) {
@@ -780,8 +797,16 @@ int isis_op_sweeps(const isis_model_params* p, double a, int n, double h, double
         return ISIS_ERR_INVALID_ARG;
     }
     return with_model<double>(*p, a, [&](auto m) {
-        return launch_sweeps<double, decltype(m)>(m, n, h, phi, tmp, eta, sigma, count,
-                                                  temporal_block, (hipStream_t)stream, g_err);
+        double* cur = phi;
+        double* other = tmp;
+        int r = launch_sweeps<double, decltype(m)>(m, n, h, &cur, &other, eta, sigma, count,
+                                                   temporal_block, (hipStream_t)stream, g_err,
+                                                   kFusedMinN);
+        if (r) return r;
+        if (cur != phi)
+            HIP_TRY(g_err, hipMemcpyAsync(phi, cur, sizeof(double) * (size_t)n * n * n,
+                                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
+        return (int)ISIS_OK;
     });
 }
 

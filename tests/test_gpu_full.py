@@ -1,0 +1,155 @@
+"""Full-size parity: the 256^3 workloads against the oracle's own FAS solve,
+and the 512^3 benchmark configuration (as bench.py runs it) against the
+oracle's residual of the GPU solution.
+
+256^3 symmetron: box 256 Mpc/h, lognormal sigma_delta = 3, a in {0.5, 0.6,
+0.8, 1.0}; uniform densities (closed form) and planar domain walls.
+256^3 f(R): box 128 Mpc/h, n = 1, |f_R0| = 1e-5, lognormal sigma_delta = 2 +
+50 NFW haloes.  Each in FP64 with the production sweep kernels (fused,
+temporally blocked) and in mixed precision (error vs the oracle stated and
+bounded by 1e-6 relative L2).
+"""
+import numpy as np
+import pytest
+
+from gpucase import cubic, dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _S():
+    from paper_1307_6748_amd import solver as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def sym256():
+    from paper_1307_6748_amd import synth
+    return synth.workload("symmetron_256")
+
+
+@pytest.fixture(scope="module")
+def fr256():
+    from paper_1307_6748_amd import synth
+    return synth.workload("fr_256")
+
+
+def _hist_close(g, o, rtol):
+    g, o = np.asarray(g), np.asarray(o)
+    assert len(g) == len(o), (g, o)
+    assert np.all(np.abs(g - o) <= rtol * np.abs(o) + 1e-12), (g, o)
+
+
+@pytest.mark.parametrize("a", [0.5, 0.6, 0.8, 1.0])
+def test_symmetron_256_fp64(orc, sym256, a):
+    S = _S()
+    om = orc.Model(model=orc.SYMMETRON, a=a, lambda0=1.0, a_ssb=0.5)
+    ro = orc.solve(om, sym256["eta"], 256.0, tol=1e-10)
+    assert ro.status == orc.OK
+    s = S.Solver(256, 256.0, temporal_block=2)
+    phi, st = s.solve(dev(sym256["eta"]), S.symmetron(1.0, 0.5), a, 1e-10)
+    assert st.cycles == ro.cycles
+    _hist_close(st.rel_hist, ro.rel_hist, 1e-5)
+    err = np.max(np.abs(cubic(phi, 256) - ro.phi)) / np.abs(ro.phi).max()
+    assert err <= 1e-9, err
+
+
+@pytest.mark.parametrize("a", [0.6, 1.0])
+def test_symmetron_256_mixed(orc, sym256, a):
+    S = _S()
+    om = orc.Model(model=orc.SYMMETRON, a=a, lambda0=1.0, a_ssb=0.5)
+    ro = orc.solve(om, sym256["eta"], 256.0, tol=1e-12)
+    s = S.Solver(256, 256.0, precision="mixed", temporal_block=2)
+    phi, st = s.solve(dev(sym256["eta"]), S.symmetron(1.0, 0.5), a, 1e-8)
+    assert st.status == 0 and st.rel_res <= 1e-8 and st.cycles_fp32 >= 1
+    err = np.linalg.norm(cubic(phi, 256) - ro.phi) / np.linalg.norm(ro.phi)
+    print(f"mixed symmetron 256^3 a={a}: rel. L2 error vs oracle {err:.2e}")
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("eta0,a", [(0.1, 1.0), (0.5, 0.8), (2.0, 0.6), (10.0, 1.0)])
+def test_symmetron_256_homogeneous(eta0, a):
+    """Uniform density: the closed form sqrt(max(0, 1 - (a_ssb/a)^3 eta)),
+    reached from a perturbed positive guess."""
+    S = _S()
+    from paper_1307_6748_amd import synth
+    chi = np.sqrt(max(0.0, 1.0 - (0.5 / a) ** 3 * eta0))
+    guess = chi + 0.05 + 0.02 * synth.random_field(256, 4)
+    s = S.Solver(256, 256.0, temporal_block=2)
+    phi, st = s.solve(dev(synth.uniform(256, eta0)), S.symmetron(1.0, 0.5), a, 1e-12,
+                      phi=dev(guess), use_guess=True)
+    assert st.status == 0
+    assert np.max(np.abs(cubic(phi, 256) - chi)) < 1e-10
+
+
+@pytest.mark.parametrize("a,eta0", [(1.0, 1.0), (0.8, 1.0), (0.5, 0.5)])
+def test_symmetron_256_domain_walls(orc, a, eta0):
+    """Walls at x = B/4 and 3B/4 from the tanh-product guess: the GPU iterate
+    after 8 V-cycles equals the oracle's, and the profile is the continuum
+    v tanh(x/delta) to O(h^2) (delta = 2 lambda0 / (a v))."""
+    S = _S()
+    from paper_1307_6748_amd import synth
+    n, box = 256, 256.0
+    v = np.sqrt(1.0 - (0.5 / a) ** 3 * eta0)
+    d = 2.0 / (a * v)
+    x = synth.cell_centres(n, box)
+    prof = v * np.tanh((x - box / 4) / d) * np.tanh((3 * box / 4 - x) / d)
+    guess = np.ascontiguousarray(np.broadcast_to(prof[:, None, None], (n, n, n)))
+    eta = synth.uniform(n, eta0)
+    om = orc.Model(model=orc.SYMMETRON, a=a, lambda0=1.0, a_ssb=0.5)
+    ro = orc.vcycles(om, eta, box, guess, 8)
+    s = S.Solver(n, box, temporal_block=2, max_cycles=8)
+    phi, st = s.solve(dev(eta), S.symmetron(1.0, 0.5), a, 1e-300, phi=dev(guess),
+                      use_guess=True, check=False)
+    got = cubic(phi, n)
+    assert np.max(np.abs(got - ro.phi)) < 1e-10
+    # the discrete wall vs the continuum profile: O(h^2) with h = 1 Mpc/h
+    assert np.max(np.abs(got[:, 0, 0] - prof)) < 0.5 * (1.0 / d) ** 2 * v
+
+
+def test_fofr_256_fp64_and_mixed(orc, fr256):
+    S = _S()
+    om = orc.Model(model=orc.FR_HS, a=1.0, n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73)
+    ro = orc.solve(om, fr256["eta"], 128.0, tol=1e-10)
+    assert ro.status == orc.OK
+    p = S.fofr(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73)
+    s = S.Solver(256, 128.0, temporal_block=2)
+    phi, st = s.solve(dev(fr256["eta"]), p, 1.0, 1e-10)
+    assert st.cycles == ro.cycles
+    _hist_close(st.rel_hist, ro.rel_hist, 1e-5)
+    err = np.max(np.abs(cubic(phi, 256) - ro.phi)) / np.abs(ro.phi).max()
+    assert err <= 1e-9, err
+    sm = S.Solver(256, 128.0, precision="mixed", temporal_block=2)
+    phim, stm = sm.solve(dev(fr256["eta"]), p, 1.0, 1e-8)
+    assert stm.status == 0 and stm.rel_res <= 1e-8
+    errm = np.linalg.norm(cubic(phim, 256) - ro.phi) / np.linalg.norm(ro.phi)
+    print(f"mixed f(R) 256^3: rel. L2 error vs oracle {errm:.2e}, "
+          f"{stm.cycles_fp32} FP32 + {stm.cycles - stm.cycles_fp32} FP64 cycles")
+    assert errm <= 1e-6
+
+
+def test_512_bench_configuration(orc):
+    """The 512^3 benchmark configuration (mixed precision, temporal block 2),
+    checked by the oracle: the oracle's own residual of the GPU solution is
+    within the tolerance, and equals the residual the GPU reports."""
+    S = _S()
+    from paper_1307_6748_amd import synth
+    n, box = 512, 256.0
+    eta = synth.lognormal_nfw(n, box, 2.0, 20, 400, 22, omega_m=0.27)
+    s = S.Solver(n, box, precision="mixed", temporal_block=2, max_cycles=100)
+    ge = dev(eta)
+    h = box / n
+    cases = [
+        (S.symmetron(1.0, 0.5), orc.Model(model=orc.SYMMETRON, a=1.0, lambda0=1.0, a_ssb=0.5)),
+        (S.fofr(1.0, 1e-5, 0.27, 0.73),
+         orc.Model(model=orc.FR_HS, a=1.0, n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73)),
+    ]
+    for sp, om in cases:
+        phi, st = s.solve(ge, sp, 1.0, 1e-8)
+        got = cubic(phi, n)
+        r = orc.rms(orc.defect(om, h, got, eta))
+        r_ref = orc.rms(orc.defect(om, h, orc.cold_start(om, eta), eta))
+        assert abs(r_ref - st.r_ref) <= 1e-9 * r_ref
+        assert r / r_ref <= 1e-8 * 1.001
+        assert abs(r / r_ref - st.rel_res) <= 1e-6 * st.rel_res
+        del got, phi
