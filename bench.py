@@ -13,7 +13,8 @@ models of the timed steps).  Also reported: Newton-GS cell updates/s, the
 finest-level smoother's achieved HBM bandwidth measured with HIP events on the
 solver stream (roofline), the plain FP64 GPU solve for comparison, a full-size
 residual check of the GPU solutions by the CPU oracle, and the CPU oracle timed
-on a bounded sample (cpu_baseline).
+solving the same two problems (cpu_baseline), and the learned warm start
+(U-Net prediction + solve, symmetron) as a separate leg.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -70,8 +71,9 @@ def main() -> int:
     ap.add_argument("--temporal-block", type=int, default=-1,
                     help="sweep fusion of the production path (-1: best available)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the CPU oracle (full-size parity and cpu_baseline)")
+    ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--points-per-halo", type=int, default=200_000)
     args = ap.parse_args()
@@ -156,41 +158,77 @@ def main() -> int:
         plain.close()
         del plain
 
+    warm = None
+    if not args.no_warm_start:
+        from paper_1307_6748_amd import warmstart as W
+        if os.path.exists(W.DEFAULT_WEIGHTS):
+            net = W.WarmStart.load()
+            p, a = mods["symmetron"]
+            cold = S.cold_start(p, a, eta)
+            guess = net.predict(eta, cold, a)  # warm-up (allocates the workspace)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            guess = net.predict(eta, cold, a, guess=guess)
+            torch.cuda.synchronize()
+            t_pred = time.perf_counter() - t1
+            r_guess = prod.residual(eta, guess, p, a)
+            phw = guess.clone()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, stw = prod.solve(eta, p, a, TOL, phi=phw, use_guess=2)
+            torch.cuda.synchronize()
+            t_solve = time.perf_counter() - t1
+            warm = dict(model="symmetron", predict_s=t_pred, solve_s=t_solve,
+                        total_s=t_pred + t_solve, used_guess=bool(stw.used_guess),
+                        cycles=stw.cycles, cycles_cold=per_model["symmetron"]["cycles"],
+                        cycles_saved=per_model["symmetron"]["cycles"] - stw.cycles,
+                        rel_res_guess=r_guess / stw.r_ref,
+                        seconds_cold=per_model["symmetron"]["seconds"])
+            log(f"warm start: predict {t_pred * 1e3:.1f} ms, solve {t_solve * 1e3:.1f} ms, "
+                f"{stw.cycles} cycles (cold {warm['cycles_cold']}), guess rel. residual "
+                f"{warm['rel_res_guess']:.3e}")
+            guess_np = guess.cpu().numpy().reshape(n, n, n)
+            del net, cold, phw
+            torch.cuda.empty_cache()
+        else:
+            log(f"no trained warm-start weights at {W.DEFAULT_WEIGHTS}")
+
     parity = {}
+    cpu = None
     if not args.no_oracle_check:
+        # The FP64 CPU oracle solves the same two problems (to 1e-8: the CPU
+        # baseline, timed), then two more V-cycles give the reference field
+        # for the GPU solutions' relative L2 error.
         from oracle import oracle as O
         om = oracle_models()
         h = box / n
+        cores = omp_threads()
+        times = {}
         for name in mods:
+            r8 = O.solve(om[name], eta_np, box, tol=TOL, cfg=O.Cfg(max_cycles=100))
+            times[name] = dict(seconds=r8.wall_s, cycles=r8.cycles)
+            ref = O.vcycles(om[name], eta_np, box, r8.phi, 2).phi
+            del r8
             phi_np = phis[name].cpu().numpy().reshape(n, n, n)
+            err = float(np.linalg.norm(phi_np - ref) / np.linalg.norm(ref))
             r = O.rms(O.defect(om[name], h, phi_np, eta_np))
             cold = O.cold_start(om[name], eta_np)
             r_ref = O.rms(O.defect(om[name], h, cold, eta_np))
-            parity[name] = dict(oracle_rel_residual=r / r_ref, tol=TOL, ok=bool(r / r_ref <= 1.5 * TOL))
-            del phi_np, cold
-            log(f"oracle residual check {name}: rel {r / r_ref:.3e}")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        om = oracle_models()
-        cores = omp_threads()
-        est, detail = [], {}
-        for name in mods:
-            cfg0 = O.Cfg(max_cycles=0)
-            cfg2 = O.Cfg(max_cycles=2)
-            r0 = O.solve(om[name], eta_np, box, tol=TOL, cfg=cfg0)
-            r2 = O.solve(om[name], eta_np, box, tol=TOL, cfg=cfg2)
-            per_cycle = (r2.wall_s - r0.wall_s) / 2.0
-            cycles = fp64.get(name, {}).get("cycles") or per_model[name]["cycles"]
-            est.append(r0.wall_s + per_cycle * cycles)
-            detail[name] = dict(setup_s=r0.wall_s, per_cycle_s=per_cycle, cycles=cycles)
-            log(f"oracle {name}: setup {r0.wall_s:.2f}s, {per_cycle:.2f}s per V-cycle")
-        cpu = dict(value=float(np.mean(est)), unit="s", cores=cores, kind="oracle",
-                   sample=("FP64 CPU oracle at 512^3 on the same density: setup (density "
-                           "hierarchy, cold start, r_ref) plus 2 V-cycles per model, timed; "
-                           "scaled to the plain-FP64 cycle count of each solve; mean over "
-                           "the two models"), detail=detail)
+            parity[name] = dict(rel_l2_vs_oracle=err, oracle_rel_residual_of_gpu=r / r_ref,
+                                tol=TOL, ok=bool(r / r_ref <= 1.5 * TOL and err <= 1e-6))
+            if name == "symmetron" and warm is not None:
+                warm["cnn_rel_l2_vs_oracle"] = float(np.linalg.norm(guess_np - ref) /
+                                                     np.linalg.norm(ref))
+                warm["cold_rel_l2_vs_oracle"] = float(np.linalg.norm(cold - ref) /
+                                                      np.linalg.norm(ref))
+            del phi_np, cold, ref
+            log(f"oracle {name}: {times[name]['seconds']:.1f}s ({times[name]['cycles']} cycles); "
+                f"GPU rel. L2 error {err:.2e}, oracle residual of GPU field {r / r_ref:.3e}")
+        cpu = dict(value=float(np.mean([t["seconds"] for t in times.values()])), unit="s",
+                   cores=cores, kind="oracle",
+                   sample=("complete FP64 CPU-oracle FAS solves of both models at 512^3 on the "
+                           "same density, to relative residual 1e-8 (wall time of each solve "
+                           "call, mean over the two models)"), detail=times)
 
     out = {
         "metric": METRIC,
@@ -235,6 +273,7 @@ def main() -> int:
         },
         "cpu_baseline": cpu,
         "parity": parity or None,
+        "warm_start": warm,
     }
     print(json.dumps(out), flush=True)
     return 0

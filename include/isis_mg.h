@@ -41,6 +41,7 @@
 #define ISIS_MG_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -136,6 +137,9 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
  *  density: device, N^3 doubles, eta > 0, read-only.
  *  field:   device, N^3 doubles.  In: initial guess if use_guess != 0, else
  *           ignored (the pointwise homogeneous root is used).  Out: solution.
+ *  use_guess: 0 cold start; 1 the caller's field; 2 the caller's field
+ *           unless its residual is not below r_ref (or not finite), in which
+ *           case the cold start is used (stats->used_guess tells which).
  *  tol > 0.  stats may be NULL.
  * Symmetron: the positive branch is the one reached from the cold start.
  * ISIS_MIXED: FP32 V-cycles (FP32 fields, FP32 smoothing and coarse-grid
@@ -213,6 +217,76 @@ int isis_op_prolong_correct(int n_fine, double* fine, const double* coarse,
 /* nu_c red-black sweeps on the coarsest (n = 4) grid in one workgroup. */
 int isis_op_coarse_solve(const isis_model_params* p, double a, double h, double* phi,
                          const double* eta, const double* sigma, int nu_c, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (a project addition, not part of the paper's method):
+ * a 3D U-Net predicts the correction phi* - phi_cold from (log eta, a,
+ * phi_cold); isis_mg_solve with use_guess = 2 then starts from the
+ * prediction unless its residual is not below the cold start's.
+ *
+ * Network: 4 levels, channels 16/32/64/64, periodic 3x3x3 convolutions with
+ * ReLU, 2x2x2 average pooling, nearest upsampling, skip concatenation
+ * [upsampled, skip], 1x1x1 head (16 -> 1):
+ *   16->16, 16->16 | pool 16->32, 32->32 | pool 32->64, 64->64 |
+ *   pool 64->64, 64->64 | up+cat 128->64, 64->64 | up+cat 96->32, 32->32 |
+ *   up+cat 48->16, 16->16 | head.
+ * Inputs (16 channels, bf16): log(eta)/2, a, phi_cold, then zeros.
+ * Parameters: one flat FP32 vector; per convolution W[t][cout][cin] then
+ * b[cout], t = (di+1)*9 + (dj+1)*3 + (dk+1) for the input at
+ * (i+di, j+dj, k+dk); then the head w[16], b.  Activations and gradients are
+ * stored as bfloat16 (round to nearest even), products accumulate in FP32 on
+ * the matrix cores.  Tensors of the conv entry points are channels-last
+ * [x][y][z][c], bf16 as raw uint16 bits.
+ * ---------------------------------------------------------------------- */
+
+size_t isis_unet_param_count(void);
+
+/* Device workspace bytes for an n^3 grid (n a power of two, 16 <= n <= 2048);
+ * training = 1 adds the gradient buffers.  0 if n is invalid. */
+size_t isis_unet_workspace_size(int n, int training);
+
+/* guess[v] = phi_cold[v] + net(log eta, a, phi_cold)[v] (FP64 out; guess may
+ * be NULL), out[v] = the network output (FP32; may be NULL).  eta, phi_cold:
+ * device n^3 doubles. */
+int isis_unet_predict(const float* params, const double* eta, const double* phi_cold, double a,
+                      int n, double* guess, float* out, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* One training step on one sample: forward, loss = mean((out - (phi_target -
+ * phi_cold))^2), backward, Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected with the 1-based step).  params, adam_m, adam_v: device FP32
+ * vectors of isis_unet_param_count() entries, updated in place.  loss_out
+ * (host, may be NULL) receives the loss before the update (synchronises the
+ * stream); grad_out (device, may be NULL) the gradient. */
+int isis_unet_train_step(float* params, float* adam_m, float* adam_v, int step, float lr,
+                         const double* eta, const double* phi_cold, const double* phi_target,
+                         double a, int n, void* workspace, size_t workspace_bytes,
+                         float* loss_out, float* grad_out, void* stream);
+
+/* Message of the last error of the isis_unet_* / isis_conv3_* calls
+ * (thread-local). */
+const char* isis_unet_last_error(void);
+
+/* y[v][co] = sum_t sum_ci x[v + d_t][ci] w[t][co][ci] + bias[co], ReLU if
+ * relu != 0; periodic n^3 grid (n a power of two >= 2).  (cin, cout) must be
+ * one of the network's shapes or their transposes.  y (bf16) and/or yf
+ * (FP32) receive the result; bias may be NULL.  With weights prepared by
+ * isis_conv3_flip_weights and the channel counts swapped, this is the data
+ * gradient of a convolution. */
+int isis_conv3_fwd(const uint16_t* x, int n, int cin, const uint16_t* w, const float* bias,
+                   int cout, int relu, uint16_t* y, float* yf, void* stream);
+
+/* wt[t][ci][co] = bf16(w[26 - t][co][ci]): the weights of the adjoint
+ * (data-gradient) convolution. */
+int isis_conv3_flip_weights(const float* w, int cin, int cout, uint16_t* wt, void* stream);
+
+size_t isis_conv3_bwd_weight_workspace(int n, int cin, int cout);
+
+/* dw[t][co][ci] = sum_v dy[v][co] x[v + d_t][ci] (FP32), db[co] = sum_v
+ * dy[v][co] (may be NULL); deterministic (fixed-order partial sums). */
+int isis_conv3_bwd_weight(const uint16_t* x, int n, int cin, const uint16_t* dy, int cout,
+                          float* dw, float* db, void* workspace, size_t workspace_bytes,
+                          void* stream);
 
 /* Pointwise homogeneous root (cold start): symmetron sqrt(max(0, 1 -
  * (a_ssb/a)^3 eta)); f(R) -(n+1) ln[(eta/a^3 + cL)/(1 + cL)]; LINEAR 0. */

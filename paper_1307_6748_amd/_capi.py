@@ -65,6 +65,16 @@ SIGNATURES = [
     ("isis_op_prolong_correct", _I, [_I, _P, _P, _P, _P]),
     ("isis_op_coarse_solve", _I, [C.POINTER(ModelParamsC), _D, _D, _P, _P, _P, _I, _P]),
     ("isis_op_cold_start", _I, [C.POINTER(ModelParamsC), _D, C.c_long, _P, _P, _P]),
+    ("isis_unet_param_count", C.c_size_t, []),
+    ("isis_unet_workspace_size", C.c_size_t, [_I, _I]),
+    ("isis_unet_predict", _I, [_P, _P, _P, _D, _I, _P, _P, _P, C.c_size_t, _P]),
+    ("isis_unet_train_step", _I, [_P, _P, _P, _I, C.c_float, _P, _P, _P, _D, _I, _P, C.c_size_t,
+                                  C.POINTER(C.c_float), _P, _P]),
+    ("isis_unet_last_error", C.c_char_p, []),
+    ("isis_conv3_fwd", _I, [_P, _I, _I, _P, _P, _I, _I, _P, _P, _P]),
+    ("isis_conv3_flip_weights", _I, [_P, _I, _I, _P, _P]),
+    ("isis_conv3_bwd_weight_workspace", C.c_size_t, [_I, _I, _I]),
+    ("isis_conv3_bwd_weight", _I, [_P, _I, _I, _P, _I, _P, _P, _P, C.c_size_t, _P]),
 ]
 
 

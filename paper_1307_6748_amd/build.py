@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libisis_mg.so")
-SOURCES = ["isis_mg.hip"]
+SOURCES = ["isis_mg.hip", "unet.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

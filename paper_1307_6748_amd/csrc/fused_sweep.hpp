@@ -76,6 +76,7 @@ struct FusedGeom {
     static constexpr int EY = TY + 2 * H;       // loaded plane rows
     static constexpr int EZ = TZ + 2 * H;       // loaded plane columns (even)
     static constexpr int NP = EZ / 2;           // column pairs per row
+    static constexpr int HZ = EZ / 2;           // LDS rows: HZ even columns, then HZ odd
     static constexpr int PLANE = EY * EZ;       // elements per plane
     static constexpr int NR = 2 * TB + 2;       // phi ring planes
     static constexpr int PAIRS = EY * NP;       // pair loads per plane
@@ -84,14 +85,6 @@ struct FusedGeom {
     static constexpr int items(int k) { return (EY - 2 * k) * ((EZ - 2 * k) / 2); }
     static constexpr int ipt(int k) { return (items(k) + NT - 1) / NT; }
     static constexpr int MAXI = (items(1) + NT - 1) / NT;
-};
-
-// Native two-element vectors (16- or 8-byte loads and stores).  Clang's
-// ext_vector_type keeps them in registers; HIP's struct-based double2 is
-// copied with memcpy, which pins arrays of it to scratch memory.
-template <class T>
-struct Vec2 {
-    using type = T __attribute__((ext_vector_type(2)));
 };
 
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
@@ -163,14 +156,21 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
 
     auto slot = [&](int p) __attribute__((always_inline)) { return (p - sbeg) % G::NR; };
     auto stage_valid = [&](int p, int k) __attribute__((always_inline)) { return p >= sbeg + k && p <= send - k; };
-    // LDS offset of the q-th item of stage k on plane p
-    auto item_off = [&](int p, int k, int it) __attribute__((always_inline)) {
+    // Plane row r, column c of a plane in LDS.  Rows are stored colour-split
+    // (even columns, then odd columns): the cells one stage updates have one
+    // column parity per row, so consecutive lanes touch consecutive words and
+    // the LDS accesses are free of bank conflicts.
+    auto lds = [&](int r, int c) __attribute__((always_inline)) {
+        return r * G::EZ + (c & 1) * G::HZ + (c >> 1);
+    };
+    // Row and column of the it-th cell updated by stage k on plane p.
+    auto item_rc = [&](int p, int k, int it, int& r, int& c) __attribute__((always_inline)) {
         const int colour = (k - 1) & 1;  // stages 1, 3: red; 2, 4: black
         const int pairs = (G::EZ - 2 * k) / 2;
         const int rr = it / pairs, cp = it - rr * pairs;
-        const int r = k + rr;
+        r = k + rr;
         const int par = (p + y0 + z0 + k + colour + r) & 1;
-        return r * G::EZ + k + 2 * cp + par;
+        c = k + 2 * cp + par;
     };
 
     V pA[G::LPT], pB[G::LPT];
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
             static_for<0, G::ipt(k)>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 const int it = min(tid + q * NT, G::items(k) - 1);
-                const int o = item_off(p, k, it);
-                const int r = o / G::EZ, c = o - r * G::EZ;
+                int r, c;
+                item_rc(p, k, it, r, c);
                 const long g = (xoff + ((y0 - G::H + r) & msk)) * n + ((z0 - G::H + c) & msk);
                 e[k - 1][q] = eta[g];
                 if constexpr (SIG) sg[k - 1][q] = sigma[g];
@@ -205,11 +205,13 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
             int it = tid + q * NT;
             if (it < G::PAIRS) {
                 int r = it / G::NP, cp = it - r * G::NP;
-                int o = r * G::EZ + 2 * cp;
-                *reinterpret_cast<V*>(dst + o) = regs[q];
+                const int oe = r * G::EZ + cp;  // column 2cp (even half)
+                const int oo = oe + G::HZ;        // column 2cp+1 (odd half)
+                dst[oe] = regs[q].x;
+                dst[oo] = regs[q].y;
                 if constexpr (STAGED) {
-                    xd[o] = exp(regs[q].x);
-                    xd[o + 1] = exp(regs[q].y);
+                    xd[oe] = exp(regs[q].x);
+                    xd[oo] = exp(regs[q].y);
                 }
             }
         }
@@ -231,14 +233,17 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                     constexpr int q = decltype(qc)::value;
                     const int it = tid + q * NT;
                     if (it < G::items(k)) {
-                        const int o = item_off(p, k, it);
+                        int r, c;
+                        item_rc(p, k, it, r, c);
+                        const int o = lds(r, c);
+                        const int ozm = lds(r, c - 1), ozp = lds(r, c + 1);
                         T nb[6];
                         nb[0] = prv[o];
                         nb[1] = nxt[o];
                         nb[2] = cur[o - G::EZ];
                         nb[3] = cur[o + G::EZ];
-                        nb[4] = cur[o - 1];
-                        nb[5] = cur[o + 1];
+                        nb[4] = cur[ozm];
+                        nb[5] = cur[ozp];
                         const T pc = cur[o];
                         T L, D;
                         if constexpr (STAGED) {
@@ -247,8 +252,8 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                             enb[1] = xnxt[o];
                             enb[2] = xcur[o - G::EZ];
                             enb[3] = xcur[o + G::EZ];
-                            enb[4] = xcur[o - 1];
-                            enb[5] = xcur[o + 1];
+                            enb[4] = xcur[ozm];
+                            enb[5] = xcur[ozp];
                             StageOp<T, M>::eval(m, pc, nb, xcur[o], enb, e[k - 1][q], ih2, L, D);
                         } else {
                             StageOp<T, M>::eval(m, pc, nb, T(0), nullptr, e[k - 1][q], ih2, L, D);
@@ -275,10 +280,10 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
             constexpr int OP = TZ / 2;  // output pairs per row
             for (int it = tid; it < TY * OP; it += NT) {
                 const int rr = it / OP, cp = it - rr * OP;
-                const int o = (G::H + rr) * G::EZ + G::H + 2 * cp;
+                const int o = lds(G::H + rr, G::H + 2 * cp);  // even column (H is even)
                 V v;
                 v.x = src[o];
-                v.y = src[o + 1];
+                v.y = src[o + G::HZ];
                 *reinterpret_cast<V*>(out + (xoff + y0 + rr) * n + z0 + 2 * cp) = v;
             }
         }

@@ -517,6 +517,14 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     LevP<double>& F = H->L64[0];  // F.phi: the current finest field (may move to tmp0)
     double r0;
     if ((r = fine_rms<double, M64>(H, m64, field, density, nullptr, &r0))) return r;
+    if (use_guess == 2 && !(r0 < r_ref)) {
+        // the supplied guess is no better than the cold start: use the latter
+        HIP_TRY(H->err, hipMemcpyAsync(field, cold, sizeof(double) * n3,
+                                       hipMemcpyDeviceToDevice, H->s));
+        if (singular && (r = sub_mean<double>(H, field, n3))) return r;
+        if ((r = fine_rms<double, M64>(H, m64, field, density, nullptr, &r0))) return r;
+        use_guess = 0;
+    }
     if (st) {
         st->r_ref = r_ref;
         st->r0 = r0;

@@ -16,6 +16,14 @@ namespace isis {
 constexpr int kBlock = 256;
 constexpr int kReduceBlocks = 1024;  // partial sums per reduction (fixed: deterministic)
 
+// Native two-element vectors (16- or 8-byte loads and stores).  Clang's
+// ext_vector_type keeps them in registers; HIP's struct-based double2 is
+// copied with memcpy, which pins arrays of it to scratch memory.
+template <class T>
+struct Vec2 {
+    using type = T __attribute__((ext_vector_type(2)));
+};
+
 __device__ __forceinline__ int wrap_dec(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int wrap_inc(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 __device__ __forceinline__ long cell(int n, int i, int j, int k)

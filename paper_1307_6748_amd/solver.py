@@ -161,8 +161,9 @@ class Solver:
     def solve(self, eta: torch.Tensor, params: ModelParams, a: float, tol: float,
               phi: torch.Tensor | None = None, use_guess: bool = False,
               check: bool = True) -> tuple[torch.Tensor, Stats]:
-        """Solve L(phi, eta) = 0.  If `phi` is given it receives the solution
-        (and is the initial guess when use_guess is True)."""
+        """Solve L(phi, eta) = 0.  If `phi` is given it receives the solution.
+        use_guess: False/0 cold start; True/1 start from `phi`; 2 start from
+        `phi` unless its residual is not below the cold start's."""
         _check_field(eta, self.N, "eta")
         if phi is None:
             phi = torch.empty_like(eta)
@@ -171,7 +172,7 @@ class Solver:
         st = A.StatsC()
         pc = params.c()
         rc = A.lib().isis_mg_solve(self._h, _ptr(eta), _ptr(phi), C.byref(pc), float(a),
-                                   float(tol), 1 if use_guess else 0, C.byref(st))
+                                   float(tol), int(use_guess), C.byref(st))
         stats = Stats.from_c(rc, st)
         if check and rc != A.ISIS_OK:
             _raise(rc, self._err())
