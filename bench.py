@@ -54,12 +54,81 @@ def oracle_models():
     }
 
 
+# Sources of the fused sweep kernel: HBM traffic counted by rocprofv3 is valid
+# for the kernel built from exactly these files.
+SWEEP_SOURCES = ("paper_1307_6748_amd/csrc/fused_sweep.hpp", "paper_1307_6748_amd/csrc/model.hpp",
+                 "paper_1307_6748_amd/csrc/kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_sweep_512_pmc.txt")
+TYPES = {"fp64": "double", "fp32": "float"}
+MODEL_TYPES = {"symmetron": "Symmetron", "fofr": "FofR"}
+
+
+def sweep_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(model: str, prec: str, n: int, tb: int):
+    """HBM bytes per launch (FETCH + WRITE, calibrated) recorded for this
+    kernel by rocprofv3 counters, if recorded for the current sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = sweep_source_hash()
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 8 and f[0] == "traffic" and f[1:5] == [model, prec, str(n), str(tb)] \
+                    and f[5] == src:
+                return float(f[6]) + float(f[7])
+    return None
+
+
+def roofline(kern: dict, n: int, tb: int):
+    """Roofline of the finest-level sweep kernels: achieved = compulsory bytes
+    per launch / mean event-timed launch duration.  The dominant kernel (most
+    time in the step) is the headline."""
+    kernels = []
+    for (model, prec), v in kern.items():
+        t, mt = TYPES[prec], MODEL_TYPES[model]
+        avg_ms = v["ms"] / v["launches"]
+        bpl = v["bytes"] / v["launches"]
+        ach = bpl / (avg_ms * 1e-3) / 1e9
+        kernels.append(dict(
+            kernel=f"k_sweep_fused<{t}, {mt}<{t}>, {tb}, ...> ({n}^3, no FAS source)",
+            model=model, precision=prec, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
+            unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(model, prec, n, tb),
+            launches=v["launches"], total_ms=v["ms"], avg_launch_ms=avg_ms,
+            bytes_per_launch=bpl))
+    kernels.sort(key=lambda k: -k["total_ms"])
+    head = dict(kernels[0]) if kernels else None
+    return head, kernels
+
+
 def omp_threads() -> int:
     import ctypes
     try:
         return int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
     except OSError:
         return 1
+
+
+def copy_probe(mib: int) -> int:
+    """A plain device copy of known size: the counters read for it turn
+    FETCH_SIZE / WRITE_SIZE of other kernels into bytes."""
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(dst[:4096], src[:4096]))
+    print(json.dumps({"copy_probe_bytes": nbytes, "copies": 2, "ok": ok}), flush=True)
+    return 0 if ok else 1
 
 
 def main() -> int:
@@ -76,12 +145,17 @@ def main() -> int:
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--points-per-halo", type=int, default=200_000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device twice (calibrates the HBM "
+                         "byte counters of rocprofv3) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr, flush=True)
         return 2
+    if args.copy_probe > 0:
+        return copy_probe(args.copy_probe)
 
     import numpy as np
     import torch
@@ -128,10 +202,19 @@ def main() -> int:
     value = elapsed / (args.steps * n_solves)
 
     updates = sum(st.cell_updates for sts in rec.values() for st in sts)
-    sweep_ms = sum(st.fine_sweep_ms for sts in rec.values() for st in sts)
-    sweep_launch = sum(st.fine_sweep_launches for sts in rec.values() for st in sts)
-    sweep_upd = sum(st.fine_sweep_updates for sts in rec.values() for st in sts)
-    sweep_bytes = sum(st.fine_sweep_bytes for sts in rec.values() for st in sts)
+    # finest-level sweep kernels, per (model, precision), timed with HIP events
+    kern = {}
+    for name, sts in rec.items():
+        for k, prec in enumerate(("fp64", "fp32")):
+            ms = sum(st.fine_sweep_ms[k] for st in sts)
+            nl = sum(st.fine_sweep_launches[k] for st in sts)
+            if nl == 0:
+                continue
+            kern[(name, prec)] = dict(
+                ms=ms, launches=nl, updates=sum(st.fine_sweep_updates[k] for st in sts),
+                bytes=sum(st.fine_sweep_bytes[k] for st in sts))
+    sweep_ms = sum(v["ms"] for v in kern.values())
+    sweep_upd = sum(v["updates"] for v in kern.values())
     per_model = {}
     for name, sts in rec.items():
         st = sts[-1]
@@ -139,7 +222,7 @@ def main() -> int:
             seconds=float(np.mean([s.ms_total for s in sts]) / 1000.0),
             cycles=st.cycles, cycles_fp32=st.cycles_fp32, rel_res=st.rel_res,
             rho=[st.rel_hist[i + 1] / st.rel_hist[i] for i in range(st.cycles)])
-    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+    roof, kernels = roofline(kern, n, tb)
 
     fp64 = {}
     if not args.no_fp64_compare:
@@ -259,18 +342,8 @@ def main() -> int:
         "fp64_plain": fp64 or None,
         "speedup_vs_fp64_plain": (float(np.mean([fp64[k]["seconds"] for k in fp64])) / value
                                   if fp64 else None),
-        "roofline": {
-            "kernel": "finest-level red-black Newton-GS sweeps",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "launches": sweep_launch,
-            "avg_launch_ms": sweep_ms / sweep_launch if sweep_launch else None,
-            "bytes_per_launch": sweep_bytes / sweep_launch if sweep_launch else None,
-        },
+        "roofline": roof,
+        "sweep_kernels": kernels,
         "cpu_baseline": cpu,
         "parity": parity or None,
         "warm_start": warm,

@@ -29,8 +29,9 @@
  *  - Array pointers are DEVICE pointers on the current HIP device, owned by
  *    the caller; the library never frees them and never calls hipMalloc.
  *    Scratch memory is the caller-provided workspace (see
- *    isis_mg_workspace_size).  Pointers must be 8-byte aligned (doubles) or
- *    4-byte aligned (floats); the workspace 256-byte aligned.
+ *    isis_mg_workspace_size).  Array pointers must be 16-byte aligned (the
+ *    kernels move neighbouring cells as pairs); the workspace 256-byte
+ *    aligned.  A misaligned pointer is rejected with ISIS_ERR_INVALID_ARG.
  *  - All work is enqueued on the given stream (a hipStream_t passed as
  *    void*; NULL is the null stream).  isis_op_* calls return once the work
  *    is enqueued; isis_mg_solve / isis_mg_residual synchronise the stream.
@@ -111,14 +112,16 @@ typedef struct {
     int used_guess;      /* 1 if the caller's field was used as initial guess     */
     /* Finest-level smoother timing, filled when profiling is on
      * (isis_mg_set_profiling): HIP events on the solver's stream around the
-     * sweep launches of the finest level (FP64 and, in mixed mode, FP32). */
-    double fine_sweep_ms;      /* summed kernel time of those launches           */
-    int fine_sweep_launches;   /* number of kernel launches                       */
-    double fine_sweep_updates; /* cell updates they performed                     */
-    double fine_sweep_bytes;   /* their compulsory HBM bytes: per pass over the
-                                  grid, read phi + eta and write phi (8+8+8 B per
-                                  cell in FP64, 4+4+4 in FP32); a pass is one
-                                  sweep, or temporal_block sweeps when blocked  */
+     * sweep launches of the finest level.  Index 0: FP64 sweeps, index 1: FP32
+     * sweeps (mixed mode). */
+    double fine_sweep_ms[2];      /* summed kernel time of those launches        */
+    int fine_sweep_launches[2];   /* number of kernel launches                    */
+    double fine_sweep_updates[2]; /* cell updates they performed                  */
+    double fine_sweep_bytes[2];   /* their compulsory HBM bytes: per pass over the
+                                     grid, read phi + eta and write phi (8+8+8 B
+                                     per cell in FP64, 4+4+4 in FP32); a pass is
+                                     one sweep, or temporal_block sweeps when
+                                     blocked                                      */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;

@@ -38,8 +38,8 @@ class StatsC(C.Structure):
                 ("r0", C.c_double), ("rel_res", C.c_double),
                 ("rel_hist", C.c_double * MAX_HIST), ("ms_total", C.c_double),
                 ("cell_updates", C.c_double), ("used_guess", C.c_int),
-                ("fine_sweep_ms", C.c_double), ("fine_sweep_launches", C.c_int),
-                ("fine_sweep_updates", C.c_double), ("fine_sweep_bytes", C.c_double)]
+                ("fine_sweep_ms", C.c_double * 2), ("fine_sweep_launches", C.c_int * 2),
+                ("fine_sweep_updates", C.c_double * 2), ("fine_sweep_bytes", C.c_double * 2)]
 
 
 _lib = None

@@ -22,9 +22,10 @@
 // ahead into registers and stored to LDS after the stages of the step in
 // between, so HBM latency overlaps two steps of compute.  For f(R) the flux
 // coefficients e^u are computed once per loaded cell and refreshed only for
-// updated cells (instead of seven exponentials per cell update).  Workgroup ids are remapped so that each XCD (ids are dealt
-// round-robin over 8 XCDs) processes a contiguous, spatially adjacent range
-// of tiles, whose shared halo rows then hit in that XCD's L2.
+// updated cells (instead of seven exponentials per cell update).  Workgroup
+// ids are remapped so that each XCD (ids are dealt round-robin over 8 XCDs)
+// processes a contiguous, spatially adjacent range of tiles, whose shared
+// halo rows then hit in that XCD's L2.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -33,41 +34,6 @@
 #include "kernels.hpp"
 
 namespace isis {
-
-// Per-model stage update with neighbour data from LDS.  The generic version
-// calls the model's op(); f(R) uses staged exponentials.
-template <class T, class M>
-struct StageOp {
-    static constexpr bool kStaged = false;
-    __device__ __forceinline__ static void eval(const M& m, T p, const T nb[6], T, const T*,
-                                                T eta, T ih2, T& L, T& D)
-    {
-        m.op(p, nb, eta, ih2, L, D);
-    }
-};
-
-template <class T>
-struct StageOp<T, FofR<T>> {
-    static constexpr bool kStaged = true;
-    // Same arithmetic as FofR::op with e^u of the cell (ep) and of the
-    // neighbours (enb) supplied.
-    __device__ __forceinline__ static void eval(const FofR<T>& m, T p, const T nb[6], T ep,
-                                                const T enb[6], T eta, T ih2, T& L, T& D)
-    {
-        T flux = T(0), dflux = T(0);
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            T bf = T(0.5) * (ep + enb[f]);
-            flux += bf * (nb[f] - p);
-            dflux += T(0.5) * ep * (nb[f] - p) - bf;
-        }
-        double e = exp(-(double)p * m.inv_np1);
-        double S = m.Q * ((double)eta + m.cLa3 - m.c1 * e);
-        double dS = m.Q * m.c1 * e * m.inv_np1;
-        L = flux * ih2 - (T)S;
-        D = dflux * ih2 - (T)dS;
-    }
-};
 
 template <class T, int TB_, int TY_, int TZ_, int NT_>
 struct FusedGeom {
@@ -210,8 +176,8 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                 dst[oe] = regs[q].x;
                 dst[oo] = regs[q].y;
                 if constexpr (STAGED) {
-                    xd[oe] = exp(regs[q].x);
-                    xd[oo] = exp(regs[q].y);
+                    xd[oe] = StageOp<T, M>::stage(regs[q].x);
+                    xd[oo] = StageOp<T, M>::stage(regs[q].y);
                 }
             }
         }
@@ -263,7 +229,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                         const T nv = pc - eps / D;
                         cur[o] = nv;
                         if constexpr (STAGED) {
-                            if (k < NK) xcur[o] = exp(nv);
+                            if (k < NK) xcur[o] = StageOp<T, M>::stage(nv);
                         }
                     }
                 });

@@ -8,6 +8,8 @@
 // norm of the stop test).  Device memory is the caller's workspace.
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -19,6 +21,7 @@
 #include "../../include/isis_mg.h"
 #include "fused_sweep.hpp"
 #include "kernels.hpp"
+#include "pair_kernels.hpp"
 
 using namespace isis;
 
@@ -118,6 +121,7 @@ FofR<T> make_fofr(const isis_model_params& p, double a)
     m.a3 = a3;
     m.cL = cL;
     m.np1 = p.n + 1.0;
+    m.n_is_one = p.n == 1.0 ? 1 : 0;
     return m;
 }
 
@@ -211,8 +215,12 @@ int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f
     T ih2f = (T)(1.0 / (hf * hf));
     double hc = 2.0 * hf;
     T ih2c = (T)(1.0 / (hc * hc));
-    hipLaunchKernelGGL((k_defect_restrict<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m, nf,
-                       ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c);
+    if (nf >= 4)
+        hipLaunchKernelGGL((k_defect_restrict_pairs<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s,
+                           m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c);
+    else
+        hipLaunchKernelGGL((k_defect_restrict<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m,
+                           nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c);
     LAUNCH_CHECK(err, "k_defect_restrict");
     hipLaunchKernelGGL((k_fas_sigma<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m, nc, ih2c,
                        phi_c, eta_c, rr_c, sigma_c);
@@ -225,8 +233,17 @@ int launch_prolong(int nf, T* fine, const T* coarse, const T* coarse_hat, hipStr
                    char* err)
 {
     long f3 = (long)nf * nf * nf;
-    hipLaunchKernelGGL((k_prolong_correct<T>), dim3(grid_for(f3)), dim3(kBlock), 0, s, nf, fine,
-                       coarse, coarse_hat);
+    using PG = ProlongTileF;
+    const int nc = nf / 2;
+    if ((nc & (nc - 1)) == 0 && nc % PG::TK == 0 && nc % PG::TJ == 0 && nc % PG::XC == 0)
+        hipLaunchKernelGGL((k_prolong_tiled<T>), dim3((nc / PG::TK) * (nc / PG::TJ) * (nc / PG::XC)),
+                           dim3(kBlock), 0, s, nf, fine, coarse, coarse_hat);
+    else if (nf >= 4)
+        hipLaunchKernelGGL((k_prolong_pairs<T>), dim3(grid_for(f3 / 8)), dim3(kBlock), 0, s, nf,
+                           fine, coarse, coarse_hat);
+    else
+        hipLaunchKernelGGL((k_prolong_correct<T>), dim3(grid_for(f3)), dim3(kBlock), 0, s, nf,
+                           fine, coarse, coarse_hat);
     LAUNCH_CHECK(err, "k_prolong_correct");
     return ISIS_OK;
 }
@@ -281,7 +298,7 @@ struct isis_mg {
     int profile;
     int ntimed;
     hipEvent_t ev0[kMaxTimed], ev1[kMaxTimed];
-    int tlaunch[kMaxTimed];
+    int tlaunch[kMaxTimed], tprec[kMaxTimed];  // tprec: 0 FP64, 1 FP32
     double tupd[kMaxTimed], tbytes[kMaxTimed];
 };
 
@@ -378,9 +395,21 @@ int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* r
     const int n = H->d.N;
     const long n3 = (long)n * n * n;
     const double h = H->L64[0].h;
-    int g = std::min(kReduceBlocks, grid_for(n3));
-    hipLaunchKernelGGL((k_defect_norm<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
-                       1.0 / (h * h), phi, eta, res, H->partial);
+    int g = std::min(kReduceBlocks, grid_for(n3 / 2));
+    bool tiled = false;
+    if constexpr (StageOp<double, M>::kStaged) {
+        using G = NormTileF;
+        tiled = (n & (n - 1)) == 0 && n % G::TZ == 0 && n % G::TY == 0 && n % G::XC == 0;
+        if (tiled) {
+            const long tiles = (long)(n / G::TZ) * (n / G::TY) * (n / G::XC);
+            g = (int)std::min<long>(kReduceBlocks, tiles);
+            hipLaunchKernelGGL((k_defect_norm_tiled<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m,
+                               n, 1.0 / (h * h), phi, eta, res, H->partial);
+        }
+    }
+    if (!tiled)
+        hipLaunchKernelGGL((k_defect_norm_pairs<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
+                           1.0 / (h * h), phi, eta, res, H->partial);
     LAUNCH_CHECK(H->err, "k_defect_norm");
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
     LAUNCH_CHECK(H->err, "k_reduce");
@@ -439,6 +468,7 @@ int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
         H->tlaunch[q] = fused ? fused_launches(count, tb) : 2 * count;
         H->tupd[q] = n3 * count;
         H->tbytes[q] = (double)passes * n3 * 3.0 * sizeof(T);
+        H->tprec[q] = sizeof(T) == 4 ? 1 : 0;
         H->ntimed = q + 1;
     }
     return ISIS_OK;
@@ -598,20 +628,15 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     }
     HIP_TRY(H->err, hipStreamSynchronize(H->s));
     if (st && H->profile) {
-        double ms = 0.0, upd = 0.0, bytes = 0.0;
-        int launches = 0;
         for (int q = 0; q < H->ntimed; ++q) {
             float e = 0.f;
             HIP_TRY(H->err, hipEventElapsedTime(&e, H->ev0[q], H->ev1[q]));
-            ms += e;
-            launches += H->tlaunch[q];
-            upd += H->tupd[q];
-            bytes += H->tbytes[q];
+            const int k = H->tprec[q];
+            st->fine_sweep_ms[k] += e;
+            st->fine_sweep_launches[k] += H->tlaunch[q];
+            st->fine_sweep_updates[k] += H->tupd[q];
+            st->fine_sweep_bytes[k] += H->tbytes[q];
         }
-        st->fine_sweep_ms = ms;
-        st->fine_sweep_launches = launches;
-        st->fine_sweep_updates = upd;
-        st->fine_sweep_bytes = bytes;
     }
     if (st) {
         st->cycles = cyc;
@@ -717,8 +742,8 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
     }
     H->err[0] = 0;
     auto t0 = std::chrono::steady_clock::now();
-    if (!density || !field || !aligned(density, 8) || !aligned(field, 8)) {
-        fmt_err(H->err, "density and field must be non-NULL, 8-byte aligned device pointers");
+    if (!density || !field || !aligned(density, 16) || !aligned(field, 16)) {
+        fmt_err(H->err, "density and field must be non-NULL, 16-byte aligned device pointers");
         return ISIS_ERR_INVALID_ARG;
     }
     if (!valid_params(params, a, H->err)) return ISIS_ERR_INVALID_ARG;
@@ -758,9 +783,9 @@ int isis_mg_residual(isis_mg_t* H, const double* density, const double* field,
         return ISIS_ERR_INVALID_ARG;
     }
     H->err[0] = 0;
-    if (!density || !field || !aligned(density, 8) || !aligned(field, 8) ||
-        (out_res && !aligned(out_res, 8))) {
-        fmt_err(H->err, "density, field (and out_res) must be 8-byte aligned device pointers");
+    if (!density || !field || !aligned(density, 16) || !aligned(field, 16) ||
+        (out_res && !aligned(out_res, 16))) {
+        fmt_err(H->err, "density, field (and out_res) must be 16-byte aligned device pointers");
         return ISIS_ERR_INVALID_ARG;
     }
     if (!valid_params(params, a, H->err)) return ISIS_ERR_INVALID_ARG;
@@ -779,6 +804,17 @@ static bool op_grid_ok(int n, int lo)
     return n >= lo && n % 2 == 0 && n <= 4096;
 }
 
+// Every array argument (NULL allowed where optional) 16-byte aligned.
+static bool ptrs_aligned(std::initializer_list<const void*> ps)
+{
+    for (const void* q : ps)
+        if (q && !aligned(q, 16)) {
+            fmt_err(g_err, "array pointers must be 16-byte aligned");
+            return false;
+        }
+    return true;
+}
+
 int isis_op_halfsweep(const isis_model_params* p, double a, int n, double h, double* phi,
                       const double* eta, const double* sigma, int colour, void* stream)
 {
@@ -787,6 +823,7 @@ int isis_op_halfsweep(const isis_model_params* p, double a, int n, double h, dou
         fmt_err(g_err, "halfsweep: need even n >= 2, h > 0, phi/eta non-NULL, colour 0 or 1");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({phi, eta, sigma})) return ISIS_ERR_INVALID_ARG;
     return with_model<double>(*p, a, [&](auto m) {
         return launch_halfsweep<double, decltype(m)>(m, n, h, phi, eta, sigma, colour,
                                                      (hipStream_t)stream, g_err);
@@ -804,6 +841,7 @@ int isis_op_sweeps(const isis_model_params* p, double a, int n, double h, double
                        "temporal_block in 0..2");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({phi, tmp, eta, sigma})) return ISIS_ERR_INVALID_ARG;
     return with_model<double>(*p, a, [&](auto m) {
         double* cur = phi;
         double* other = tmp;
@@ -826,6 +864,7 @@ int isis_op_defect(const isis_model_params* p, double a, int n, double h, const 
         fmt_err(g_err, "defect: need even n >= 2, h > 0, phi/eta/out non-NULL");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({phi, eta, sigma, out})) return ISIS_ERR_INVALID_ARG;
     return with_model<double>(*p, a, [&](auto m) {
         using M = decltype(m);
         hipLaunchKernelGGL((k_defect<double, M>), dim3(grid_for((long)n * n * n)), dim3(kBlock),
@@ -841,6 +880,7 @@ int isis_op_restrict(int n_fine, const double* fine, double* coarse, void* strea
         fmt_err(g_err, "restrict: need even n_fine >= 2 and non-NULL arrays");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({fine, coarse})) return ISIS_ERR_INVALID_ARG;
     return launch_restrict<double>(n_fine, fine, coarse, (hipStream_t)stream, g_err);
 }
 
@@ -855,6 +895,8 @@ int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double
         fmt_err(g_err, "fas_descend: need even n_fine >= 4, h > 0, non-NULL arrays");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({phi_f, eta_f, sigma_f, eta_c, phi_c, phihat_c, sigma_c, rr_c}))
+        return ISIS_ERR_INVALID_ARG;
     return with_model<double>(*p, a, [&](auto m) {
         return launch_descend<double, decltype(m)>(m, n_fine, h_fine, phi_f, eta_f, sigma_f,
                                                    eta_c, phi_c, phihat_c, sigma_c, rr_c,
@@ -869,6 +911,7 @@ int isis_op_prolong_correct(int n_fine, double* fine, const double* coarse,
         fmt_err(g_err, "prolong_correct: need even n_fine >= 4 and non-NULL arrays");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({fine, coarse, coarse_hat})) return ISIS_ERR_INVALID_ARG;
     return launch_prolong<double>(n_fine, fine, coarse, coarse_hat, (hipStream_t)stream, g_err);
 }
 
@@ -880,6 +923,7 @@ int isis_op_coarse_solve(const isis_model_params* p, double a, double h, double*
         fmt_err(g_err, "coarse_solve: need h > 0, phi/eta non-NULL, nu_c >= 0");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({phi, eta, sigma})) return ISIS_ERR_INVALID_ARG;
     return with_model<double>(*p, a, [&](auto m) {
         return launch_coarse<double, decltype(m)>(m, h, phi, eta, sigma, nu_c,
                                                   (hipStream_t)stream, g_err);
@@ -894,6 +938,7 @@ int isis_op_cold_start(const isis_model_params* p, double a, long ncell, const d
         fmt_err(g_err, "cold_start: need ncell >= 0 and non-NULL arrays");
         return ISIS_ERR_INVALID_ARG;
     }
+    if (!ptrs_aligned({eta, phi})) return ISIS_ERR_INVALID_ARG;
     if (ncell == 0) return ISIS_OK;
     return with_model<double>(*p, a, [&](auto m) {
         using M = decltype(m);

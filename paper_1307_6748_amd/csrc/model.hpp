@@ -46,28 +46,60 @@ struct Symmetron {
 //   cLa3 = cL a^3, c1 = a^3 (1 + cL), cL = 4 Omega_L/Omega_m.
 // Jacobian (Sec. 3.4, eq. dbeq, with the exact factor 1/2 on db/du):
 //   (1/h^2) sum_f [ e^u (u_nb - u)/2 - b_f ] - dS/du.
-// The source is always evaluated in double precision: in dense haloes eta and
-// c1 e^{-u/(n+1)} are both ~1e4 and cancel.
+// Stiff regime of the source: where the field is screened, e^{-u/(n+1)} is
+// large and eta cancels against c1 e^{-u/(n+1)} (both ~1e4 in halo cores), and
+// dS/du dominates the Newton denominator.  There the FP32 operator still
+// evaluates the source in FP64; elsewhere in FP32.
+constexpr float kFofRStiff = 8.0f;  // e^{-u/(n+1)} above which the source is stiff
+
 template <class T>
 struct FofR {
     double Q, cLa3, c1, inv_np1;
     double a3, cL, np1;  // for the cold start
-    __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
+    int n_is_one;        // n = 1: e^{-u/2} = 1/sqrt(e^u) (double precision only)
+    // S(u) and dS/du at one cell, given e^u (ep)
+    __device__ __forceinline__ void source(T p, T ep, T eta, T& S, T& dS) const
     {
-        T bc = exp(p);
+        if constexpr (sizeof(T) == 4) {
+            const float e = expf(-p * float(inv_np1));
+            if (e <= kFofRStiff) {
+                S = float(Q) * (eta + float(cLa3) - float(c1) * e);
+                dS = float(Q) * float(c1) * e * float(inv_np1);
+                return;
+            }
+            const double ed = exp(-(double)p * inv_np1);
+            S = (T)(Q * ((double)eta + cLa3 - c1 * ed));
+            dS = (T)(Q * c1 * ed * inv_np1);
+        } else {
+            const T e = n_is_one ? rsqrt(ep) : exp(-p * inv_np1);
+            S = Q * (eta + cLa3 - c1 * e);
+            dS = Q * c1 * e * inv_np1;
+        }
+    }
+    // L and D from the cell value p, its e^p (ep) and the neighbours' values
+    // and exponentials: the exponentials may be computed once per cell and
+    // shared by all stencils that use them.
+    __device__ __forceinline__ void op_staged(T p, const T nb[6], T ep, const T enb[6], T eta,
+                                              T ih2, T& L, T& D) const
+    {
         T flux = T(0), dflux = T(0);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            T bf = T(0.5) * (bc + exp(nb[f]));
+            T bf = T(0.5) * (ep + enb[f]);
             flux += bf * (nb[f] - p);
-            dflux += T(0.5) * bc * (nb[f] - p) - bf;
+            dflux += T(0.5) * ep * (nb[f] - p) - bf;
         }
-        double pd = (double)p;
-        double e = exp(-pd * inv_np1);
-        double S = Q * ((double)eta + cLa3 - c1 * e);
-        double dS = Q * c1 * e * inv_np1;
-        L = flux * ih2 - (T)S;
-        D = dflux * ih2 - (T)dS;
+        T S, dS;
+        source(p, ep, eta, S, dS);
+        L = flux * ih2 - S;
+        D = dflux * ih2 - dS;
+    }
+    __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
+    {
+        T enb[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) enb[f] = exp(nb[f]);
+        op_staged(p, nb, exp(p), enb, eta, ih2, L, D);
     }
     __device__ __forceinline__ T cold(T eta) const
     {
@@ -90,6 +122,31 @@ struct Linear {
         D = -T(6) * ih2 - m2;
     }
     __device__ __forceinline__ T cold(T) const { return T(0); }
+};
+
+// Per-model form of the operator for kernels that share per-cell work between
+// neighbouring stencils.  Staged models (f(R)) take a per-cell quantity
+// computed once, stage(phi) = e^phi, next to each value; others ignore it.
+template <class T, class M>
+struct StageOp {
+    static constexpr bool kStaged = false;
+    __device__ __forceinline__ static T stage(T) { return T(0); }
+    __device__ __forceinline__ static void eval(const M& m, T p, const T nb[6], T, const T*,
+                                                T eta, T ih2, T& L, T& D)
+    {
+        m.op(p, nb, eta, ih2, L, D);
+    }
+};
+
+template <class T>
+struct StageOp<T, FofR<T>> {
+    static constexpr bool kStaged = true;
+    __device__ __forceinline__ static T stage(T x) { return exp(x); }
+    __device__ __forceinline__ static void eval(const FofR<T>& m, T p, const T nb[6], T ep,
+                                                const T enb[6], T eta, T ih2, T& L, T& D)
+    {
+        m.op_staged(p, nb, ep, enb, eta, ih2, L, D);
+    }
 };
 
 }  // namespace isis

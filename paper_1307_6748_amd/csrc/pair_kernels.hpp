@@ -1,0 +1,487 @@
+// Level kernels that move data in z-pairs: each thread owns either one
+// coarse cell and its 8 children (restriction side, prolongation) or two
+// z-neighbouring fine cells (defect norm), and loads the fine field as
+// 16-byte (FP64) / 8-byte (FP32) pairs.  They compute exactly what the
+// per-cell kernels in kernels.hpp compute, in the same summation order, with
+// about a third of the load instructions.  Fine sides must be even and >= 4.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace isis {
+
+// FAS descent, first half (see k_defect_restrict): one thread per coarse
+// cell.  The 32 fine values its 8 stencils touch are loaded once (as pairs
+// along z); for f(R) their e^phi are computed once as well (32 instead of 56
+// exponentials per coarse cell).
+template <class T, class M>
+__global__ __launch_bounds__(kBlock) void k_defect_restrict_pairs(
+    M m, int nf, T ih2, const T* __restrict__ phi, const T* __restrict__ eta,
+    const T* __restrict__ sigma, T* __restrict__ phi_c, T* __restrict__ phihat_c,
+    T* __restrict__ rr_c)
+{
+    using V = typename Vec2<T>::type;
+    using SO = StageOp<T, M>;
+    const int nc = nf >> 1;
+    const long total = (long)nc * nc * nc;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long)gridDim.x * blockDim.x) {
+        const int K = (int)(q % nc);
+        const long r = q / nc;
+        const int J = (int)(r % nc), I = (int)(r / nc);
+        const int k0 = 2 * K, km = wrap_dec(k0, nf), kp = wrap_inc(k0 + 1, nf);
+        // fine rows: x index 2I-1 .. 2I+2, y index 2J-1 .. 2J+2 (periodic)
+        int xi[4], yj[4];
+        xi[0] = wrap_dec(2 * I, nf);
+        xi[1] = 2 * I;
+        xi[2] = 2 * I + 1;
+        xi[3] = wrap_inc(2 * I + 1, nf);
+        yj[0] = wrap_dec(2 * J, nf);
+        yj[1] = 2 * J;
+        yj[2] = 2 * J + 1;
+        yj[3] = wrap_inc(2 * J + 1, nf);
+        auto row = [&](int a, int b) { return ((long)xi[a] * nf + yj[b]) * nf; };
+        // the 8 children: cp[di][dj] = cells (2I+di, 2J+dj, 2K..2K+1); their
+        // z-neighbours outside the pair: cm (2K-1) and cq (2K+2)
+        V cp[2][2];
+        T cm[2][2], cq[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const long o = row(a + 1, b + 1);
+                cp[a][b] = *reinterpret_cast<const V*>(phi + o + k0);
+                cm[a][b] = phi[o + km];
+                cq[a][b] = phi[o + kp];
+            }
+        // x-neighbours outside the block: xs[0][dj] at 2I-1, xs[1][dj] at 2I+2;
+        // y-neighbours: ys[0][di] at 2J-1, ys[1][di] at 2J+2
+        V xs[2][2], ys[2][2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            xs[0][t] = *reinterpret_cast<const V*>(phi + row(0, t + 1) + k0);
+            xs[1][t] = *reinterpret_cast<const V*>(phi + row(3, t + 1) + k0);
+            ys[0][t] = *reinterpret_cast<const V*>(phi + row(t + 1, 0) + k0);
+            ys[1][t] = *reinterpret_cast<const V*>(phi + row(t + 1, 3) + k0);
+        }
+        V cpE[2][2], xsE[2][2], ysE[2][2];
+        T cmE[2][2], cqE[2][2];
+        if constexpr (SO::kStaged) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cpE[a][b] = V{SO::stage(cp[a][b].x), SO::stage(cp[a][b].y)};
+                    xsE[a][b] = V{SO::stage(xs[a][b].x), SO::stage(xs[a][b].y)};
+                    ysE[a][b] = V{SO::stage(ys[a][b].x), SO::stage(ys[a][b].y)};
+                    cmE[a][b] = SO::stage(cm[a][b]);
+                    cqE[a][b] = SO::stage(cq[a][b]);
+                }
+        }
+        T sr = T(0), sp = T(0);
+#pragma unroll
+        for (int di = 0; di < 2; ++di)
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const long o = row(di + 1, dj + 1) + k0;
+                const V e2 = *reinterpret_cast<const V*>(eta + o);
+                V s2 = V{T(0), T(0)};
+                if (sigma) s2 = *reinterpret_cast<const V*>(sigma + o);
+#pragma unroll
+                for (int dk = 0; dk < 2; ++dk) {
+                    // neighbour order x-, x+, y-, y+, z-, z+
+                    T nb[6];
+                    nb[0] = di ? cp[0][dj][dk] : xs[0][dj][dk];
+                    nb[1] = di ? xs[1][dj][dk] : cp[1][dj][dk];
+                    nb[2] = dj ? cp[di][0][dk] : ys[0][di][dk];
+                    nb[3] = dj ? ys[1][di][dk] : cp[di][1][dk];
+                    nb[4] = dk ? cp[di][dj][0] : cm[di][dj];
+                    nb[5] = dk ? cq[di][dj] : cp[di][dj][1];
+                    const T p = cp[di][dj][dk];
+                    T L, D;
+                    if constexpr (SO::kStaged) {
+                        T enb[6];
+                        enb[0] = di ? cpE[0][dj][dk] : xsE[0][dj][dk];
+                        enb[1] = di ? xsE[1][dj][dk] : cpE[1][dj][dk];
+                        enb[2] = dj ? cpE[di][0][dk] : ysE[0][di][dk];
+                        enb[3] = dj ? ysE[1][di][dk] : cpE[di][1][dk];
+                        enb[4] = dk ? cpE[di][dj][0] : cmE[di][dj];
+                        enb[5] = dk ? cqE[di][dj] : cpE[di][dj][1];
+                        SO::eval(m, p, nb, cpE[di][dj][dk], enb, e2[dk], ih2, L, D);
+                    } else {
+                        m.op(p, nb, e2[dk], ih2, L, D);
+                    }
+                    sr += L - (sigma ? s2[dk] : T(0));
+                    sp += p;
+                }
+            }
+        const T pc = sp / T(8);
+        phi_c[q] = pc;
+        phihat_c[q] = pc;
+        rr_c[q] = sr / T(8);
+    }
+}
+
+// fine += P(coarse - coarse_hat) (see k_prolong_correct): one thread per
+// coarse cell updates its 8 children, in the same order of terms per child.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_prolong_pairs(int nf, T* __restrict__ fine,
+                                                          const T* __restrict__ coarse,
+                                                          const T* __restrict__ coarse_hat)
+{
+    using V = typename Vec2<T>::type;
+    const int nc = nf >> 1;
+    const long total = (long)nc * nc * nc;
+    const T w[2] = {T(0.75), T(0.25)};
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long)gridDim.x * blockDim.x) {
+        const int K = (int)(q % nc);
+        const long r = q / nc;
+        const int J = (int)(r % nc), I = (int)(r / nc);
+        // coarse index offsets -1, 0, +1 per axis (periodic)
+        const int Ix[3] = {wrap_dec(I, nc), I, wrap_inc(I, nc)};
+        const int Jy[3] = {wrap_dec(J, nc), J, wrap_inc(J, nc)};
+        const int Kz[3] = {wrap_dec(K, nc), K, wrap_inc(K, nc)};
+        T d[3][3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const long cq = ((long)Ix[a] * nc + Jy[b]) * nc + Kz[c];
+                    d[a][b][c] = coarse[cq] - coarse_hat[cq];
+                }
+#pragma unroll
+        for (int di = 0; di < 2; ++di)
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const long o = ((long)(2 * I + di) * nf + (2 * J + dj)) * nf + 2 * K;
+                V f = *reinterpret_cast<const V*>(fine + o);
+#pragma unroll
+                for (int dk = 0; dk < 2; ++dk) {
+                    // parent index 1; the other coarse cell is 2 for odd, 0 for even
+                    const int ai[2] = {1, di ? 2 : 0};
+                    const int bj[2] = {1, dj ? 2 : 0};
+                    const int ck[2] = {1, dk ? 2 : 0};
+                    T s = T(0);
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                s += w[a] * w[b] * w[c] * d[ai[a]][bj[b]][ck[c]];
+                    f[dk] += s;
+                }
+                *reinterpret_cast<V*>(fine + o) = f;
+            }
+    }
+}
+
+// fine += P(coarse - coarse_hat), LDS-staged: each workgroup owns a TJ x TK
+// tile of coarse (y, z) cells and streams along coarse x over XC planes.  The
+// coarse differences pass through a ring of three planes (tile plus a
+// one-cell halo) in LDS, so each is loaded about 1.6 times instead of 27;
+// each thread then updates the 8 children of one coarse cell with 16-byte
+// pair loads and stores.  Same terms, same order as k_prolong_correct.
+template <int TJ_, int TK_, int XC_>
+struct ProlongTile {
+    static constexpr int TJ = TJ_, TK = TK_, XC = XC_, NT = kBlock;
+    static constexpr int EJ = TJ + 2, EK = TK + 2;
+    static constexpr int PLANE = EJ * EK;
+    static constexpr int LPT = (PLANE + NT - 1) / NT;
+    static_assert(TJ * TK == NT, "one coarse cell per thread");
+};
+using ProlongTileF = ProlongTile<4, 64, 8>;
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_prolong_tiled(int nf, T* __restrict__ fine,
+                                                          const T* __restrict__ coarse,
+                                                          const T* __restrict__ coarse_hat)
+{
+    using G = ProlongTileF;
+    using V = typename Vec2<T>::type;
+    __shared__ T ring[3][G::PLANE];
+    const int nc = nf >> 1;
+    const int cm = nc - 1;
+    const int tid = threadIdx.x;
+    const int ntk = nc / G::TK, ntj = nc / G::TJ;
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
+    const int kt = b % ntk, jt = (b / ntk) % ntj, it = b / (ntk * ntj);
+    const int I0 = it * G::XC, J0 = jt * G::TJ, K0 = kt * G::TK;
+    const T w[2] = {T(0.75), T(0.25)};
+    T d[G::LPT];
+    // coarse differences of plane I (tile + halo) into registers
+    auto load = [&](int I) __attribute__((always_inline)) {
+        const long xoff = (long)(I & cm) * nc;
+#pragma unroll
+        for (int q = 0; q < G::LPT; ++q) {
+            const int e = min(tid + q * G::NT, G::PLANE - 1);
+            const int r = e / G::EK, c = e - r * G::EK;
+            const long g = (xoff + ((J0 - 1 + r) & cm)) * nc + ((K0 - 1 + c) & cm);
+            d[q] = coarse[g] - coarse_hat[g];
+        }
+    };
+    auto deposit = [&](int I) __attribute__((always_inline)) {
+        T* dst = ring[(I - I0 + 3) % 3];
+#pragma unroll
+        for (int q = 0; q < G::LPT; ++q) {
+            const int e = tid + q * G::NT;
+            if (e < G::PLANE) dst[e] = d[q];
+        }
+    };
+    const int jj = tid / G::TK, kk = tid - jj * G::TK;  // this thread's coarse (J, K)
+    load(I0 - 1);
+    deposit(I0 - 1);
+    load(I0);
+    deposit(I0);
+    load(I0 + 1);
+    for (int I = I0; I < I0 + G::XC; ++I) {
+        deposit(I + 1);
+        load(min(I + 2, I0 + G::XC));  // clamped: branch-free
+        // this coarse cell's 8 children: 4 z-pairs
+        V f[2][2];
+#pragma unroll
+        for (int di = 0; di < 2; ++di)
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const long o = ((long)(2 * I + di) * nf + (2 * (J0 + jj) + dj)) * nf +
+                               2 * (K0 + kk);
+                f[di][dj] = *reinterpret_cast<const V*>(fine + o);
+            }
+        __syncthreads();
+        const T* pl[3] = {ring[(I - 1 - I0 + 3) % 3], ring[(I - I0 + 3) % 3],
+                          ring[(I + 1 - I0 + 3) % 3]};
+#pragma unroll
+        for (int di = 0; di < 2; ++di)
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+#pragma unroll
+                for (int dk = 0; dk < 2; ++dk) {
+                    // parent at window index 1; the other neighbour at 2 (odd child) or 0
+                    const int ai[2] = {1, di ? 2 : 0};
+                    const int bj[2] = {1, dj ? 2 : 0};
+                    const int ck[2] = {1, dk ? 2 : 0};
+                    T s = T(0);
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                s += w[a] * w[bb] * w[c] *
+                                     pl[ai[a]][(jj + bj[bb]) * G::EK + kk + ck[c]];
+                    f[di][dj][dk] += s;
+                }
+                const long o = ((long)(2 * I + di) * nf + (2 * (J0 + jj) + dj)) * nf +
+                               2 * (K0 + kk);
+                *reinterpret_cast<V*>(fine + o) = f[di][dj];
+            }
+        __syncthreads();  // the slot of plane I-1 is refilled next
+    }
+}
+
+// Finest-level defect in double precision and per-block partial sums of r^2
+// (see k_defect_norm): one thread per z-pair of cells.
+template <class TF, class M>
+__global__ __launch_bounds__(kBlock) void k_defect_norm_pairs(M m, int n, double ih2,
+                                                              const TF* __restrict__ phi,
+                                                              const double* __restrict__ eta,
+                                                              double* __restrict__ res,
+                                                              double* __restrict__ partial)
+{
+    using VF = typename Vec2<TF>::type;
+    using VD = typename Vec2<double>::type;
+    const int hn = n >> 1;
+    const long total = (long)n * n * hn;
+    double acc = 0.0;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (long)gridDim.x * blockDim.x) {
+        const int kk = (int)(t % hn);
+        const long r = t / hn;
+        const int j = (int)(r % n), i = (int)(r / n);
+        const int k0 = 2 * kk;
+        const long o = ((long)i * n + j) * n;
+        const long oxm = ((long)wrap_dec(i, n) * n + j) * n, oxp = ((long)wrap_inc(i, n) * n + j) * n;
+        const long oym = ((long)i * n + wrap_dec(j, n)) * n, oyp = ((long)i * n + wrap_inc(j, n)) * n;
+        const VF c = *reinterpret_cast<const VF*>(phi + o + k0);
+        const VF xm = *reinterpret_cast<const VF*>(phi + oxm + k0);
+        const VF xp = *reinterpret_cast<const VF*>(phi + oxp + k0);
+        const VF ym = *reinterpret_cast<const VF*>(phi + oym + k0);
+        const VF yp = *reinterpret_cast<const VF*>(phi + oyp + k0);
+        const double zm = (double)phi[o + wrap_dec(k0, n)];
+        const double zp = (double)phi[o + wrap_inc(k0 + 1, n)];
+        const VD e = *reinterpret_cast<const VD*>(eta + o + k0);
+        double L2[2];
+#pragma unroll
+        for (int dk = 0; dk < 2; ++dk) {
+            double nb[6];
+            nb[0] = (double)xm[dk];
+            nb[1] = (double)xp[dk];
+            nb[2] = (double)ym[dk];
+            nb[3] = (double)yp[dk];
+            nb[4] = dk ? (double)c[0] : zm;
+            nb[5] = dk ? zp : (double)c[1];
+            double L, D;
+            m.op((double)c[dk], nb, e[dk], ih2, L, D);
+            L2[dk] = L;
+            acc += L * L;
+        }
+        if (res) *reinterpret_cast<VD*>(res + o + k0) = VD{L2[0], L2[1]};
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Finest-level defect and per-block partial sums of r^2 for staged models
+// (f(R)), computed in double precision: each workgroup streams a TY x TZ
+// tile of the y-z plane along x through a ring of three planes in LDS that
+// hold phi and e^phi, so each exponential is computed once per loaded cell
+// (about 1.3 per cell with the halo) instead of seven times per stencil.
+// Tiles are visited grid-stride; n must be a multiple of TZ, TY and XC.
+template <int TY_, int TZ_, int XC_>
+struct NormTile {
+    static constexpr int TY = TY_, TZ = TZ_, XC = XC_, NT = kBlock;
+    static constexpr int EY = TY + 2;         // rows with the y halo
+    static constexpr int EZ = TZ + 4;         // columns z0-2 .. z0+TZ+1 (pairs stay aligned)
+    static constexpr int NP = EZ / 2;         // pairs per row
+    static constexpr int PAIRS = EY * NP;     // pairs per plane
+    static constexpr int LPT = (PAIRS + NT - 1) / NT;
+    static constexpr int PLANE = EY * EZ;
+    static_assert(TY * TZ == 2 * NT, "one z-pair of cells per thread");
+};
+using NormTileF = NormTile<8, 64, 32>;
+
+template <class TF, class M>
+__global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double ih2,
+                                                              const TF* __restrict__ phi,
+                                                              const double* __restrict__ eta,
+                                                              double* __restrict__ res,
+                                                              double* __restrict__ partial)
+{
+    using G = NormTileF;
+    using SO = StageOp<double, M>;
+    using VF = typename Vec2<TF>::type;
+    using VD = typename Vec2<double>::type;
+    __shared__ __align__(16) double ring[3][G::PLANE];
+    __shared__ __align__(16) double xring[3][G::PLANE];
+    const int tid = threadIdx.x;
+    const int msk = n - 1;
+    const int ntz = n / G::TZ, nty = n / G::TY, ntx = n / G::XC;
+    const int ntiles = ntz * nty * ntx;
+    // Each XCD (block ids are dealt round-robin over 8) walks a contiguous
+    // range of tiles, so the rows neighbouring tiles share stay in its L2.
+    const int nb = gridDim.x;
+    const bool remap = (nb & 7) == 0 && (ntiles & 7) == 0;
+    const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, per = ntiles >> 3;
+    // this thread's output pair: row rr, columns 2cp, 2cp+1 of the tile
+    const int rr = tid / (G::TZ / 2), cp = tid - rr * (G::TZ / 2);
+    double acc = 0.0;
+    for (int it = 0;; ++it) {
+        int t;
+        if (remap) {
+            const int loc = lb + it * (nb >> 3);
+            if (loc >= per) break;
+            t = xcd * per + loc;
+        } else {
+            t = blockIdx.x + it * nb;
+            if (t >= ntiles) break;
+        }
+        const int zt = t % ntz, yt = (t / ntz) % nty, xt = t / (ntz * nty);
+        const int x0 = xt * G::XC, y0 = yt * G::TY, z0 = zt * G::TZ;
+        VF regs[G::LPT];
+        auto load = [&](int x) __attribute__((always_inline)) {
+            const long xoff = (long)(x & msk) * n;
+#pragma unroll
+            for (int q = 0; q < G::LPT; ++q) {
+                const int k = min(tid + q * G::NT, G::PAIRS - 1);
+                const int r = k / G::NP, c2 = k - r * G::NP;
+                const long g = (xoff + ((y0 - 1 + r) & msk)) * n + ((z0 - 2 + 2 * c2) & msk);
+                regs[q] = *reinterpret_cast<const VF*>(phi + g);
+            }
+        };
+        auto deposit = [&](int x) __attribute__((always_inline)) {
+            double* d = ring[(x - x0 + 3) % 3];
+            double* e = xring[(x - x0 + 3) % 3];
+#pragma unroll
+            for (int q = 0; q < G::LPT; ++q) {
+                const int k = tid + q * G::NT;
+                if (k < G::PAIRS) {
+                    const double a = (double)regs[q].x, b = (double)regs[q].y;
+                    *reinterpret_cast<VD*>(d + 2 * k) = VD{a, b};
+                    *reinterpret_cast<VD*>(e + 2 * k) = VD{SO::stage(a), SO::stage(b)};
+                }
+            }
+        };
+        auto eta_at = [&](int x) __attribute__((always_inline)) {
+            return ((long)(x & msk) * n + (y0 + rr)) * n + z0 + 2 * cp;
+        };
+        load(x0 - 1);
+        deposit(x0 - 1);
+        load(x0);
+        deposit(x0);
+        VD enext = *reinterpret_cast<const VD*>(eta + eta_at(x0));
+        load(x0 + 1);
+        __syncthreads();
+        for (int x = x0; x < x0 + G::XC; ++x) {
+            // Everything loaded last step is consumed now; this step's loads
+            // (clamped to the chunk: branch-free, so the compiler's wait
+            // counts stay exact) overlap the stencil work below.
+            deposit(x + 1);
+            const VD e2 = enext;
+            const long g = eta_at(x);
+            enext = *reinterpret_cast<const VD*>(eta + eta_at(min(x + 1, x0 + G::XC - 1)));
+            load(min(x + 2, x0 + G::XC));
+            __syncthreads();
+            const double* pv = ring[(x - 1 - x0 + 3) % 3];
+            const double* cu = ring[(x - x0 + 3) % 3];
+            const double* nx = ring[(x + 1 - x0 + 3) % 3];
+            const double* epv = xring[(x - 1 - x0 + 3) % 3];
+            const double* ecu = xring[(x - x0 + 3) % 3];
+            const double* enx = xring[(x + 1 - x0 + 3) % 3];
+            const int o = (rr + 1) * G::EZ + 2 + 2 * cp;
+            const VD c = *reinterpret_cast<const VD*>(cu + o);
+            const VD xm = *reinterpret_cast<const VD*>(pv + o);
+            const VD xp = *reinterpret_cast<const VD*>(nx + o);
+            const VD ym = *reinterpret_cast<const VD*>(cu + o - G::EZ);
+            const VD yp = *reinterpret_cast<const VD*>(cu + o + G::EZ);
+            const VD ec = *reinterpret_cast<const VD*>(ecu + o);
+            const VD exm = *reinterpret_cast<const VD*>(epv + o);
+            const VD exp_ = *reinterpret_cast<const VD*>(enx + o);
+            const VD eym = *reinterpret_cast<const VD*>(ecu + o - G::EZ);
+            const VD eyp = *reinterpret_cast<const VD*>(ecu + o + G::EZ);
+            const double zm = cu[o - 1], zp = cu[o + 2], ezm = ecu[o - 1], ezp = ecu[o + 2];
+            double L2[2];
+#pragma unroll
+            for (int dk = 0; dk < 2; ++dk) {
+                double nbv[6], enb[6];
+                nbv[0] = xm[dk];
+                nbv[1] = xp[dk];
+                nbv[2] = ym[dk];
+                nbv[3] = yp[dk];
+                nbv[4] = dk ? c[0] : zm;
+                nbv[5] = dk ? zp : c[1];
+                enb[0] = exm[dk];
+                enb[1] = exp_[dk];
+                enb[2] = eym[dk];
+                enb[3] = eyp[dk];
+                enb[4] = dk ? ec[0] : ezm;
+                enb[5] = dk ? ezp : ec[1];
+                double L, D;
+                SO::eval(m, c[dk], nbv, ec[dk], enb, e2[dk], ih2, L, D);
+                L2[dk] = L;
+                acc += L * L;
+            }
+            if (res) *reinterpret_cast<VD*>(res + g) = VD{L2[0], L2[1]};
+            __syncthreads();  // plane x-1's slot is refilled next
+        }
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+}  // namespace isis

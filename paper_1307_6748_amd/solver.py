@@ -79,17 +79,18 @@ class Stats:
     ms_total: float = 0.0
     cell_updates: float = 0.0
     used_guess: bool = False
-    fine_sweep_ms: float = 0.0
-    fine_sweep_launches: int = 0
-    fine_sweep_updates: float = 0.0
-    fine_sweep_bytes: float = 0.0
+    # finest-level sweep timing (profiling on): [FP64, FP32]
+    fine_sweep_ms: list = field(default_factory=lambda: [0.0, 0.0])
+    fine_sweep_launches: list = field(default_factory=lambda: [0, 0])
+    fine_sweep_updates: list = field(default_factory=lambda: [0.0, 0.0])
+    fine_sweep_bytes: list = field(default_factory=lambda: [0.0, 0.0])
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
         return Stats(status, s.cycles, s.cycles_fp32, s.r_ref, s.r0, s.rel_res,
                      list(s.rel_hist[: s.cycles + 1]), s.ms_total, s.cell_updates,
-                     bool(s.used_guess), s.fine_sweep_ms, s.fine_sweep_launches,
-                     s.fine_sweep_updates, s.fine_sweep_bytes)
+                     bool(s.used_guess), list(s.fine_sweep_ms), list(s.fine_sweep_launches),
+                     list(s.fine_sweep_updates), list(s.fine_sweep_bytes))
 
 
 def _ptr(t: torch.Tensor | None):

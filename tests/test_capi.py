@@ -88,3 +88,21 @@ def test_ops_validate_sizes_on_host():
     assert lib.isis_op_prolong_correct(2, fake, fake, fake, None) == -1
     assert lib.isis_op_sweeps(C.byref(p), 1.0, 8, 1.0, fake, fake, fake, None, 1, 5, None) == -1
     assert lib.isis_op_cold_start(C.byref(p), 1.0, 0, None, None, None) == 0
+
+
+def test_ops_reject_misaligned_pointers_on_host():
+    """The kernels move z-neighbouring cells as 16-byte pairs: an array that
+    is only 8-byte aligned is refused before anything is launched."""
+    lib = A.lib()
+    p = A.ModelParamsC(A.ISIS_LINEAR, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0)
+    ok, bad = C.c_void_p(4096), C.c_void_p(4096 + 8)  # never dereferenced
+    assert lib.isis_op_defect(C.byref(p), 1.0, 8, 1.0, ok, bad, None, ok, None) == -1
+    assert b"aligned" in lib.isis_mg_last_error(None)
+    assert lib.isis_op_restrict(8, bad, ok, None) == -1
+    assert lib.isis_op_prolong_correct(8, ok, ok, bad, None) == -1
+    assert lib.isis_op_halfsweep(C.byref(p), 1.0, 8, 1.0, ok, ok, bad, 0, None) == -1
+    assert lib.isis_op_sweeps(C.byref(p), 1.0, 8, 1.0, ok, bad, ok, None, 1, 0, None) == -1
+    assert lib.isis_op_fas_descend(C.byref(p), 1.0, 8, 1.0, ok, ok, None, ok, ok, ok, ok, bad,
+                                   None) == -1
+    assert lib.isis_op_coarse_solve(C.byref(p), 1.0, 1.0, bad, ok, None, 4, None) == -1
+    assert lib.isis_op_cold_start(C.byref(p), 1.0, 8, ok, bad, None) == -1

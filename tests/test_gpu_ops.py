@@ -63,7 +63,9 @@ def test_restrict(orc, n):
     assert np.max(np.abs(got - orc.restrict(f))) <= 1e-15 * np.abs(f).max()
 
 
-@pytest.mark.parametrize("n", [4, 8, 12, 36])
+# 128, 256: the LDS-staged kernel (coarse side a power of two, multiple of 64);
+# 384: coarse side 192 is a multiple of 64 but not a power of two (pair kernel)
+@pytest.mark.parametrize("n", [4, 8, 12, 36, 128, 256, 384])
 def test_prolong_correct(orc, n):
     from paper_1307_6748_amd import solver as S
     rng = np.random.default_rng(n)
@@ -77,7 +79,7 @@ def test_prolong_correct(orc, n):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("n", [4, 12, 32])
+@pytest.mark.parametrize("n", [4, 12, 32, 64])
 @pytest.mark.parametrize("with_sigma", [False, True])
 def test_fas_descend(orc, name, n, with_sigma):
     """phi_c = phihat_c = R phi_f; sigma_c = L_c(R phi_f) - R(L_f(phi_f) - sigma_f)."""

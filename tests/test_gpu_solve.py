@@ -146,11 +146,19 @@ def test_domain_wall(orc):
     assert np.max(np.abs(cubic(phi, n) - ro.phi)) < 1e-11
 
 
-def test_residual_api(orc):
+@pytest.mark.parametrize("name,n", [("fofr", 32), ("fofr", 64), ("fofr_a07", 128),
+                                    ("symmetron_a1", 64), ("fofr", 256), ("fofr", 512)])
+def test_residual_api(orc, name, n):
+    """FP64 defect and its RMS against the oracle.  f(R) grids that are
+    multiples of 64 take the LDS-tiled kernel (at 512^3 each workgroup walks
+    several tiles), smaller ones the per-pair kernel."""
     from paper_1307_6748_amd import synth
-    om, sp, a = models("fofr")
-    n, box = 32, 64.0
-    eta = synth.lognormal(n, box, 2.0, 7)
+    om, sp, a = models(name)
+    box = 2.0 * n
+    if n <= 64:
+        eta = synth.lognormal(n, box, 2.0, 7)
+    else:  # cheaper at large n: exp of a white-noise field
+        eta = np.exp(np.random.default_rng(n).standard_normal((n, n, n)))
     u = orc.cold_start(om, eta) + 0.1 * synth.random_field(n, 8)
     s = _solver(n, box)
     out = dev(np.zeros((n, n, n)))
@@ -158,6 +166,8 @@ def test_residual_api(orc):
     ref = orc.defect(om, box / n, u, eta)
     assert abs(rms - orc.rms(ref)) <= 1e-12 * orc.rms(ref)
     assert np.max(np.abs(cubic(out, n) - ref)) <= 1e-12 * np.abs(ref).max()
+    # without the output array (the solver's stop test)
+    assert s.residual(dev(eta), dev(u), sp, a) == pytest.approx(rms, rel=1e-13)
 
 
 @pytest.mark.parametrize("name,wl,n", [("symmetron_a1", "small_symmetron", 32),
