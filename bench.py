@@ -140,6 +140,9 @@ def main() -> int:
     ap.add_argument("--temporal-block", type=int, default=-1,
                     help="sweep fusion of the production path (-1: best available)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--fp32-floor", type=float, default=0.0,
+                    help="mixed mode: relative residual where FP32 cycles hand over to FP64 "
+                         "(0: the library default)")
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="skip the CPU oracle (full-size parity and cpu_baseline)")
     ap.add_argument("--no-warm-start", action="store_true")
@@ -177,7 +180,8 @@ def main() -> int:
     mods = models()
     phis = {k: torch.empty_like(eta) for k in mods}
 
-    prod = S.Solver(n, box, precision=args.precision, temporal_block=tb, max_cycles=100)
+    prod = S.Solver(n, box, precision=args.precision, temporal_block=tb, max_cycles=100,
+                    fp32_floor=args.fp32_floor)
     prod.set_profiling(True)
 
     def step(record=None):
@@ -332,7 +336,8 @@ def main() -> int:
                          "a_ssb=0.5, a=1) and Hu-Sawicki f(R) (n=1, |fR0|=1e-5, Om=0.27, a=1), "
                          "each solved to relative residual 1e-8"),
             "grid": n, "box": box, "tol": TOL, "precision": args.precision,
-            "temporal_block": tb, "parallelism": "single GPU", "eta_sha256": eta_sha,
+            "temporal_block": tb, "fp32_floor": args.fp32_floor or None,
+            "parallelism": "single GPU", "eta_sha256": eta_sha,
         },
         "cell_updates_per_s": {
             "end_to_end": updates / elapsed,

@@ -90,6 +90,9 @@ typedef struct {
     int nu_coarse;     /* red-black sweeps on the 4^3 grid (>= 1; default 32)       */
     int max_cycles;    /* V-cycle limit (1 .. ISIS_MG_MAX_HIST-1; default 50)       */
     int precision;     /* isis_precision                                           */
+    double fp32_floor; /* ISIS_MIXED: relative residual at which the FP32 phase
+                          hands over to FP64 cycles (see isis_mg_solve); 0 (the
+                          default) means 3 tol; else in [1e-12, 1]              */
     int temporal_block;/* 0: one HBM pass per red or black half-sweep;
                           1: one pass per full red-black sweep (fused);
                           2: two full sweeps per pass (temporal blocking)           */
@@ -147,9 +150,12 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
  * Symmetron: the positive branch is the one reached from the cold start.
  * ISIS_MIXED: FP32 V-cycles (FP32 fields, FP32 smoothing and coarse-grid
  * work; the f(R) source in FP64), each followed by the FP64 defect of the
- * FP32 iterate on the finest level; while that residual falls by at least
- * 0.6x per cycle and is above 3e-6 relative (the FP32 round-off floor is
- * ~1e-6), then FP64 V-cycles from the promoted iterate to tol.
+ * FP32 iterate on the finest level, while that residual falls by at least
+ * 0.6x per cycle (it stops falling at the FP32 round-off floor, which depends
+ * on the problem: ~4e-7 relative for the symmetron, below 1e-8 for f(R) on
+ * the 512^3 halo workload) and is above desc.fp32_floor (default 3 tol); then
+ * FP64 V-cycles from the promoted iterate to tol.  The FP64 defect decides
+ * convergence in both phases.
  * Returns ISIS_OK, ISIS_ERR_NOT_CONVERGED (field = last iterate) or
  * ISIS_ERR_DIVERGED (field = last iterate, may be non-finite). */
 int isis_mg_solve(isis_mg_t* h, const double* density, double* field,

@@ -29,7 +29,7 @@ class ModelParamsC(C.Structure):
 class DescC(C.Structure):
     _fields_ = [("N", C.c_int), ("box", C.c_double), ("nu_pre", C.c_int), ("nu_post", C.c_int),
                 ("nu_coarse", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int),
-                ("temporal_block", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("fp32_floor", C.c_double), ("temporal_block", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t)]
 
 

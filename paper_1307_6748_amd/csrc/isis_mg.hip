@@ -385,6 +385,10 @@ bool valid_desc(const isis_mg_desc* d, char* err)
         fmt_err(err, "temporal_block must be 0, 1 or 2");
         return false;
     }
+    if (!(d->fp32_floor == 0.0 || (d->fp32_floor >= 1e-12 && d->fp32_floor <= 1.0))) {
+        fmt_err(err, "fp32_floor must be 0 (default) or in [1e-12, 1]");
+        return false;
+    }
     return true;
 }
 
@@ -580,6 +584,11 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                            n3, field, H->L32[0].phi);
         LAUNCH_CHECK(H->err, "k_convert");
         H->L32[0].sigma = nullptr;
+        // Default hand-over at 3 tol: the last cycles run in FP64, so the answer
+        // carries FP64-cycle error (an FP32-only solve meeting the same tol is
+        // ~10% less accurate in phi for f(R)); an earlier stall of the FP32
+        // cycles at their round-off floor also hands over.
+        const double fp32_floor = d.fp32_floor > 0.0 ? d.fp32_floor : 3.0 * tol;
         double rprev = r0;
         while (cyc < d.max_cycles) {
             if ((r = vcycle<float, M32>(H, m32, H->L32, 0, &updates))) return r;
@@ -598,8 +607,9 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                 status = ISIS_OK;
                 break;
             }
-            // FP32 round-off floor reached (or the FP32 phase stalls): refine in FP64.
-            if (rc > 0.6 * rprev || rc <= 3e-6 * rnorm) break;
+            // The FP32 phase stalls at its round-off floor (or the caller's
+            // hand-over level is reached): refine in FP64.
+            if (rc > 0.6 * rprev || rc <= fp32_floor * rnorm) break;
             rprev = rc;
         }
         hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,

@@ -14,7 +14,7 @@
 namespace isis {
 
 constexpr int kBlock = 256;
-constexpr int kReduceBlocks = 1024;  // partial sums per reduction (fixed: deterministic)
+constexpr int kReduceBlocks = 8192;  // partial sums per reduction (fixed: deterministic)
 
 // Native two-element vectors (16- or 8-byte loads and stores).  Clang's
 // ext_vector_type keeps them in registers; HIP's struct-based double2 is

@@ -119,12 +119,12 @@ class Solver:
 
     def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = 2,
                  nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
-                 temporal_block: int = 0):
+                 temporal_block: int = 0, fp32_floor: float = 0.0):
         self.N, self.box = int(N), float(box)
         self._h = None
         lib = A.lib()
         d = A.DescC(self.N, self.box, nu_pre, nu_post, nu_coarse, max_cycles,
-                    PRECISIONS[precision], temporal_block, _stream(), None, 0)
+                    PRECISIONS[precision], float(fp32_floor), temporal_block, _stream(), None, 0)
         nbytes = lib.isis_mg_workspace_size(C.byref(d))
         if nbytes == 0:
             raise ValueError("invalid solver description (N, box, nu_*, max_cycles, precision, "

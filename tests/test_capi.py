@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def _desc(**kw):
-    d = A.DescC(64, 64.0, 2, 2, 32, 50, A.ISIS_FP64, 0, None, None, 0)
+    d = A.DescC(64, 64.0, 2, 2, 32, 50, A.ISIS_FP64, 0.0, 0, None, None, 0)
     for k, v in kw.items():
         setattr(d, k, v)
     return d
@@ -47,9 +47,13 @@ def test_workspace_size_validation():
     assert ok > 0
     # bigger with the FP32 hierarchy of the mixed mode
     assert lib.isis_mg_workspace_size(C.byref(_desc(precision=A.ISIS_MIXED))) > ok
+    assert lib.isis_mg_workspace_size(C.byref(_desc(precision=A.ISIS_MIXED,
+                                                    fp32_floor=1e-7))) > ok
     for bad in (dict(N=12), dict(N=4), dict(box=0.0), dict(box=float("nan")),
                 dict(nu_coarse=0), dict(max_cycles=0), dict(max_cycles=A.MAX_HIST),
-                dict(precision=7), dict(temporal_block=3), dict(nu_pre=0, nu_post=0)):
+                dict(precision=7), dict(temporal_block=3), dict(nu_pre=0, nu_post=0),
+                dict(fp32_floor=-1e-6), dict(fp32_floor=2.0), dict(fp32_floor=1e-13),
+                dict(fp32_floor=float("nan"))):
         assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad
 
 
