@@ -63,26 +63,6 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
-template <class G, class T>
-__device__ __forceinline__ void load_plane_regs(const T* __restrict__ src, int n, int x, int y0,
-                                                int z0, typename Vec2<T>::type* regs)
-{
-    using V = typename Vec2<T>::type;
-    const int msk = n - 1;
-    const long xoff = (long)(x & msk) * n;
-    // Unconditional, branch-free loads (the tail is clamped to a valid pair):
-    // the compiler can then count outstanding loads exactly and wait only
-    // for the ones a use needs, instead of draining all of them.
-#pragma unroll
-    for (int q = 0; q < G::LPT; ++q) {
-        int it = min((int)threadIdx.x + q * G::NT, G::PAIRS - 1);
-        int r = it / G::NP, cp = it - r * G::NP;
-        int y = (y0 - G::H + r) & msk;
-        int z = (z0 - G::H + 2 * cp) & msk;  // even: the pair (z, z+1) is contiguous
-        regs[q] = *reinterpret_cast<const V*>(src + (xoff + y) * n + z);
-    }
-}
-
 // Shared-memory footprint of one workgroup, in bytes.
 template <class T, class M, int TB, int TY, int TZ>
 constexpr int fused_lds_bytes()
@@ -90,6 +70,19 @@ constexpr int fused_lds_bytes()
     using G = FusedGeom<T, TB, TY, TZ, 256>;
     int planes = G::NR * (StageOp<T, M>::kStaged ? 2 : 1);
     return planes * G::PLANE * (int)sizeof(T);
+}
+
+// Element at byte offset `off` from `base` (32-bit offsets from a uniform
+// base let loads use the scalar-base addressing mode).
+template <class T>
+__device__ __forceinline__ const T& at_bytes(const T* base, unsigned off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <class T>
+__device__ __forceinline__ T& at_bytes(T* base, unsigned off)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
 }
 
 template <class T, class M, int TB, int TY, int TZ, int NT, bool SIG>
@@ -100,8 +93,14 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
 {
     using G = FusedGeom<T, TB, TY, TZ, NT>;
     using V = typename Vec2<T>::type;
-    constexpr bool STAGED = StageOp<T, M>::kStaged;
+    using SO = StageOp<T, M>;
+    constexpr bool STAGED = SO::kStaged;
     constexpr int NK = 2 * TB;
+    constexpr int SZ = (int)sizeof(T);
+    // For TB = 1 the black stage's density (and source) of a plane is loaded
+    // in the same step as the red stage's, two steps before use, so both
+    // colours of a cache line are fetched together.
+    constexpr bool LATE2 = (TB == 1);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* ring = reinterpret_cast<T*>(smem_raw);  // NR planes of phi
     T* xring = ring + G::NR * G::PLANE;        // NR planes of e^phi (f(R) only)
@@ -116,8 +115,11 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
     const int yt = (b / ntz) % nty;
     const int xt = b / (ntz * nty);
     const int x0 = xt * xc, y0 = yt * TY, z0 = zt * TZ;
+    // xc and H are even, so sbeg is even: the unrolled steps below alternate
+    // even and odd planes, which fixes every parity at compile time.
     const int sbeg = x0 - G::H, send = x0 + xc - 1 + G::H;
     const int msk = n - 1;
+    const size_t n2 = (size_t)n * n;
     const int tid = threadIdx.x;
 
     auto slot = [&](int p) __attribute__((always_inline)) { return (p - sbeg) % G::NR; };
@@ -129,37 +131,77 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
     auto lds = [&](int r, int c) __attribute__((always_inline)) {
         return r * G::EZ + (c & 1) * G::HZ + (c >> 1);
     };
-    // Row and column of the it-th cell updated by stage k on plane p.
-    auto item_rc = [&](int p, int k, int it, int& r, int& c) __attribute__((always_inline)) {
-        const int colour = (k - 1) & 1;  // stages 1, 3: red; 2, 4: black
-        const int pairs = (G::EZ - 2 * k) / 2;
-        const int rr = it / pairs, cp = it - rr * pairs;
-        r = k + rr;
-        const int par = (p + y0 + z0 + k + colour + r) & 1;
-        c = k + 2 * cp + par;
-    };
+
+    // ---- Per-thread address tables (byte offsets; independent of the plane) ----
+    // Pair loads of a plane (the tail clamped to a valid pair: branch-free
+    // loads let the compiler count outstanding loads exactly).
+    unsigned poff[G::LPT];
+    int doff[G::LPT];  // LDS element offset of the pair's even column
+#pragma unroll
+    for (int q = 0; q < G::LPT; ++q) {
+        const int it = min(tid + q * NT, G::PAIRS - 1);
+        const int r = it / G::NP, cp = it - r * G::NP;
+        poff[q] = (unsigned)((((y0 - G::H + r) & msk) * n + ((z0 - G::H + 2 * cp) & msk)) * SZ);
+        doff[q] = r * G::EZ + cp;
+    }
+    // Cells updated by stage k (1-based), per item q, for plane parity pb:
+    // global byte offset in the plane (items clamped: the load is always
+    // valid) and LDS element offset.
+    unsigned goff[NK][G::MAXI][2];
+    int loff[NK][G::MAXI][2];
+    int zoff[NK][G::MAXI][2];  // LDS offset of the z- neighbour; z+ is the next word
+    static_for<0, NK>([&](auto kc) {
+        constexpr int k = decltype(kc)::value + 1;
+        constexpr int colour = (k - 1) & 1;  // stages 1, 3: red; 2, 4: black
+        constexpr int pairs = (G::EZ - 2 * k) / 2;
+        static_for<0, G::ipt(k)>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int it = min(tid + q * NT, G::items(k) - 1);
+            const int rr = it / pairs, cp = it - rr * pairs;
+            const int r = k + rr;
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) {
+                const int par = (pb + y0 + z0 + k + colour + r) & 1;
+                const int c = k + 2 * cp + par;
+                goff[k - 1][q][pb] = (unsigned)((((y0 - G::H + r) & msk) * n +
+                                                 ((z0 - G::H + c) & msk)) * SZ);
+                loff[k - 1][q][pb] = lds(r, c);
+                zoff[k - 1][q][pb] = lds(r, c - 1);  // lds(r, c + 1) == lds(r, c - 1) + 1
+            }
+        });
+    });
+    constexpr int OP = TZ / 2;                         // output pairs per row
+    constexpr int WPT = (TY * OP + NT - 1) / NT;       // output pairs per thread
+    unsigned woff[WPT];
+    int wl[WPT];
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        const int it = min(tid + j * NT, TY * OP - 1);
+        const int rr = it / OP, cp = it - rr * OP;
+        woff[j] = (unsigned)(((y0 + rr) * n + z0 + 2 * cp) * SZ);
+        wl[j] = lds(G::H + rr, G::H + 2 * cp);  // even column (H is even)
+    }
 
     V pA[G::LPT], pB[G::LPT];
     T eA[NK][G::MAXI], eB[NK][G::MAXI];
     T sA[SIG ? NK : 1][SIG ? G::MAXI : 1], sB[SIG ? NK : 1][SIG ? G::MAXI : 1];
 
-    // Density (and FAS source) of the cells this thread updates at step s.
-    // Loaded unconditionally (clamped items, wrapped planes; unused values are
-    // discarded) so that the loads carry no branches -- see load_plane_regs.
-    auto fetch_cells = [&](int s, T (&e)[NK][G::MAXI], T (&sg)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
-        static_for<0, NK>([&](auto kc) {
-            constexpr int k = decltype(kc)::value + 1;
-            const int p = s - k;
-            const long xoff = (long)(p & msk) * n;
-            static_for<0, G::ipt(k)>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                const int it = min(tid + q * NT, G::items(k) - 1);
-                int r, c;
-                item_rc(p, k, it, r, c);
-                const long g = (xoff + ((y0 - G::H + r) & msk)) * n + ((z0 - G::H + c) & msk);
-                e[k - 1][q] = eta[g];
-                if constexpr (SIG) sg[k - 1][q] = sigma[g];
-            });
+    auto load_plane = [&](int x, V (&regs)[G::LPT]) __attribute__((always_inline)) {
+        const T* src = in + (size_t)(x & msk) * n2;
+#pragma unroll
+        for (int q = 0; q < G::LPT; ++q) regs[q] = at_bytes(reinterpret_cast<const V*>(src), poff[q]);
+    };
+    // Density (and FAS source) of stage k's cells on plane p (parity PB).
+    auto fetch_stage = [&](auto kc, auto pbc, int p, T (&e)[NK][G::MAXI],
+                           T (&sg)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int PB = decltype(pbc)::value;
+        const T* ep = eta + (size_t)(p & msk) * n2;
+        const T* sp = SIG ? sigma + (size_t)(p & msk) * n2 : nullptr;
+        static_for<0, G::ipt(k)>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            e[k - 1][q] = at_bytes(ep, goff[k - 1][q][PB]);
+            if constexpr (SIG) sg[k - 1][q] = at_bytes(sp, goff[k - 1][q][PB]);
         });
     };
 
@@ -168,25 +210,26 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
         T* xd = xring + slot(s) * G::PLANE;
 #pragma unroll
         for (int q = 0; q < G::LPT; ++q) {
-            int it = tid + q * NT;
-            if (it < G::PAIRS) {
-                int r = it / G::NP, cp = it - r * G::NP;
-                const int oe = r * G::EZ + cp;  // column 2cp (even half)
-                const int oo = oe + G::HZ;        // column 2cp+1 (odd half)
+            if ((q + 1) * NT <= G::PAIRS || tid + q * NT < G::PAIRS) {
+                const int oe = doff[q];      // column 2cp (even half)
+                const int oo = oe + G::HZ;   // column 2cp+1 (odd half)
                 dst[oe] = regs[q].x;
                 dst[oo] = regs[q].y;
                 if constexpr (STAGED) {
-                    xd[oe] = StageOp<T, M>::stage(regs[q].x);
-                    xd[oo] = StageOp<T, M>::stage(regs[q].y);
+                    xd[oe] = SO::stage(regs[q].x);
+                    xd[oo] = SO::stage(regs[q].y);
                 }
             }
         }
     };
 
-    auto stages = [&](int s, const T (&e)[NK][G::MAXI],
+    // Stages of step s (parity S2 of s fixed at compile time).
+    auto stages = [&](auto s2c, int s, const T (&e)[NK][G::MAXI],
                       const T (&sg)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
+        constexpr int S2 = decltype(s2c)::value;
         static_for<0, NK>([&](auto kc) {
             constexpr int k = decltype(kc)::value + 1;
+            constexpr int PB = (S2 + k) & 1;  // parity of plane s - k
             const int p = s - k;
             if (stage_valid(p, k)) {
                 T* cur = ring + slot(p) * G::PLANE;
@@ -197,17 +240,14 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                 const T* xnxt = xring + slot(p + 1) * G::PLANE;
                 static_for<0, G::ipt(k)>([&](auto qc) {
                     constexpr int q = decltype(qc)::value;
-                    const int it = tid + q * NT;
-                    if (it < G::items(k)) {
-                        int r, c;
-                        item_rc(p, k, it, r, c);
-                        const int o = lds(r, c);
-                        const int ozm = lds(r, c - 1), ozp = lds(r, c + 1);
+                    if ((q + 1) * NT <= G::items(k) || tid + q * NT < G::items(k)) {
+                        const int o = loff[k - 1][q][PB];
                         T nb[6];
                         nb[0] = prv[o];
                         nb[1] = nxt[o];
                         nb[2] = cur[o - G::EZ];
                         nb[3] = cur[o + G::EZ];
+                        const int ozm = zoff[k - 1][q][PB], ozp = ozm + 1;
                         nb[4] = cur[ozm];
                         nb[5] = cur[ozp];
                         const T pc = cur[o];
@@ -220,16 +260,16 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                             enb[3] = xcur[o + G::EZ];
                             enb[4] = xcur[ozm];
                             enb[5] = xcur[ozp];
-                            StageOp<T, M>::eval(m, pc, nb, xcur[o], enb, e[k - 1][q], ih2, L, D);
+                            SO::eval(m, pc, nb, xcur[o], enb, e[k - 1][q], ih2, L, D);
                         } else {
-                            StageOp<T, M>::eval(m, pc, nb, T(0), nullptr, e[k - 1][q], ih2, L, D);
+                            SO::eval(m, pc, nb, T(0), nullptr, e[k - 1][q], ih2, L, D);
                         }
                         T eps = L;
                         if constexpr (SIG) eps -= sg[k - 1][q];
                         const T nv = pc - eps / D;
                         cur[o] = nv;
                         if constexpr (STAGED) {
-                            if (k < NK) xcur[o] = StageOp<T, M>::stage(nv);
+                            if (k < NK) xcur[o] = SO::stage(nv);
                         }
                     }
                 });
@@ -242,42 +282,71 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
         const int pw = s - NK;
         if (pw >= x0 && pw < x0 + xc) {
             const T* src = ring + slot(pw) * G::PLANE;
-            const long xoff = (long)(pw & msk) * n;
-            constexpr int OP = TZ / 2;  // output pairs per row
-            for (int it = tid; it < TY * OP; it += NT) {
-                const int rr = it / OP, cp = it - rr * OP;
-                const int o = lds(G::H + rr, G::H + 2 * cp);  // even column (H is even)
-                V v;
-                v.x = src[o];
-                v.y = src[o + G::HZ];
-                *reinterpret_cast<V*>(out + (xoff + y0 + rr) * n + z0 + 2 * cp) = v;
+            T* dst = out + (size_t)(pw & msk) * n2;
+#pragma unroll
+            for (int j = 0; j < WPT; ++j) {
+                if ((j + 1) * NT <= TY * OP || tid + j * NT < TY * OP) {
+                    V v;
+                    v.x = src[wl[j]];
+                    v.y = src[wl[j] + G::HZ];
+                    at_bytes(reinterpret_cast<V*>(dst), woff[j]) = v;
+                }
             }
         }
     };
 
     // One step: planes up to s are in LDS, plane s+1 is in `ready`; `spare`
     // (which held plane s) receives plane s+2.  ec/sc hold this step's cell
-    // data, en/sn receive the next step's.
-    auto step = [&](int s, V (&spare)[G::LPT], const V (&ready)[G::LPT],
-                    const T (&ec)[NK][G::MAXI], const T (&sc)[SIG ? NK : 1][SIG ? G::MAXI : 1],
+    // data, en/sn receive the next step's (with LATE2, the black stage's
+    // entries of ec/sc are consumed here and refilled for step s+2).
+    auto step = [&](auto s2c, int s, V (&spare)[G::LPT], const V (&ready)[G::LPT],
+                    T (&ec)[NK][G::MAXI], T (&sc)[SIG ? NK : 1][SIG ? G::MAXI : 1],
                     T (&en)[NK][G::MAXI], T (&sn)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
+        constexpr int S2 = decltype(s2c)::value;
         // (past the chunk end these load wrapped, unused planes: branch-free)
-        load_plane_regs<G, T>(in, n, s + 2, y0, z0, spare);
-        fetch_cells(s + 1, en, sn);
-        stages(s, ec, sc);  // ends with a barrier: the slot of plane s+1-NR is free
+        load_plane(s + 2, spare);
+        // next step's stage k works on plane s + 1 - k
+        static_for<0, NK>([&](auto kc) {
+            constexpr int k = decltype(kc)::value + 1;
+            if constexpr (!(LATE2 && k == 2))
+                fetch_stage(std::integral_constant<int, k>{},
+                            std::integral_constant<int, (S2 + 1 + k) & 1>{}, s + 1 - k, en, sn);
+        });
+        stages(s2c, s, ec, sc);  // ends with a barrier: the slot of plane s+1-NR is free
+        if constexpr (LATE2)     // black stage of plane s, used at step s+2
+            fetch_stage(std::integral_constant<int, 2>{}, std::integral_constant<int, S2>{}, s,
+                        ec, sc);
         write_out(s);
         if (s + 1 <= send) deposit(s + 1, ready);
         __syncthreads();
     };
 
-    load_plane_regs<G, T>(in, n, sbeg, y0, z0, pA);
-    load_plane_regs<G, T>(in, n, sbeg + 1, y0, z0, pB);
+    // Prologue: planes sbeg, sbeg+1 in flight; step sbeg's red-stage data;
+    // the black-stage data of the first two steps belong to invalid stages.
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+#pragma unroll
+        for (int q = 0; q < G::MAXI; ++q) {
+            eA[k][q] = T(1);
+            eB[k][q] = T(1);
+            if constexpr (SIG) {
+                sA[k][q] = T(0);
+                sB[k][q] = T(0);
+            }
+        }
+    load_plane(sbeg, pA);
+    load_plane(sbeg + 1, pB);
     deposit(sbeg, pA);
-    fetch_cells(sbeg, eA, sA);
+    static_for<0, NK>([&](auto kc) {
+        constexpr int k = decltype(kc)::value + 1;
+        if constexpr (!(LATE2 && k == 2))
+            fetch_stage(std::integral_constant<int, k>{}, std::integral_constant<int, k & 1>{},
+                        sbeg - k, eA, sA);
+    });
     __syncthreads();
     for (int s = sbeg; s <= send; s += 2) {
-        step(s, pA, pB, eA, sA, eB, sB);
-        if (s + 1 <= send) step(s + 1, pB, pA, eB, sB, eA, sA);
+        step(std::integral_constant<int, 0>{}, s, pA, pB, eA, sA, eB, sB);
+        if (s + 1 <= send) step(std::integral_constant<int, 1>{}, s + 1, pB, pA, eB, sB, eA, sA);
     }
 }
 
