@@ -266,7 +266,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                         }
                         T eps = L;
                         if constexpr (SIG) eps -= sg[k - 1][q];
-                        const T nv = pc - eps / D;
+                        const T nv = pc - eps * recip(D);
                         cur[o] = nv;
                         if constexpr (STAGED) {
                             if (k < NK) xcur[o] = SO::stage(nv);

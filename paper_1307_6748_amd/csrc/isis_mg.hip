@@ -400,16 +400,13 @@ int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* r
     const long n3 = (long)n * n * n;
     const double h = H->L64[0].h;
     int g = std::min(kReduceBlocks, grid_for(n3 / 2));
-    bool tiled = false;
-    if constexpr (StageOp<double, M>::kStaged) {
-        using G = NormTileF;
-        tiled = (n & (n - 1)) == 0 && n % G::TZ == 0 && n % G::TY == 0 && n % G::XC == 0;
-        if (tiled) {
-            const long tiles = (long)(n / G::TZ) * (n / G::TY) * (n / G::XC);
-            g = (int)std::min<long>(kReduceBlocks, tiles);
-            hipLaunchKernelGGL((k_defect_norm_tiled<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m,
-                               n, 1.0 / (h * h), phi, eta, res, H->partial);
-        }
+    using NG = NormTileF;
+    const bool tiled = (n & (n - 1)) == 0 && n % NG::TZ == 0 && n % NG::TY == 0 && n % NG::XC == 0;
+    if (tiled) {
+        const long tiles = (long)(n / NG::TZ) * (n / NG::TY) * (n / NG::XC);
+        g = (int)std::min<long>(kReduceBlocks, tiles);
+        hipLaunchKernelGGL((k_defect_norm_tiled<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
+                           1.0 / (h * h), phi, eta, res, H->partial);
     }
     if (!tiled)
         hipLaunchKernelGGL((k_defect_norm_pairs<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,

@@ -46,6 +46,48 @@ struct Symmetron {
 //   cLa3 = cL a^3, c1 = a^3 (1 + cL), cL = 4 Omega_L/Omega_m.
 // Jacobian (Sec. 3.4, eq. dbeq, with the exact factor 1/2 on db/du):
 //   (1/h^2) sum_f [ e^u (u_nb - u)/2 - b_f ] - dS/du.
+// e^x in single precision from the hardware base-2 exponential: with
+// t = fl(x log2 e), the rounding error of t is recovered exactly by an FMA
+// (plus the error of log2 e itself), and 2^(x log2 e) = 2^t (1 + err ln 2) to
+// first order, within about two ulp for |x| < 87 (no overflow handling: the
+// fields here stay far from it).
+__device__ __forceinline__ float exp_fast(float x)
+{
+    constexpr float kLog2e = 1.44269502f;        // log2(e) rounded to float
+    constexpr float kLog2eLo = 1.92596299e-8f;   // log2(e) - kLog2e
+    constexpr float kLn2 = 0.693147182f;
+    const float t = x * kLog2e;
+    float err = fmaf(x, kLog2e, -t);
+    err = fmaf(x, kLog2eLo, err);
+    const float r = __builtin_amdgcn_exp2f(t);
+    return fmaf(r, err * kLn2, r);
+}
+
+template <class T>
+__device__ __forceinline__ T exp_t(T x)
+{
+    if constexpr (sizeof(T) == 4)
+        return exp_fast(x);
+    else
+        return exp(x);
+}
+
+// 1/d for the Newton-Gauss-Seidel step: the hardware reciprocal refined by
+// Newton iterations (one in FP32, two in FP64).  Only the iteration uses it;
+// its fixed point L = Sigma does not depend on how 1/D is rounded.
+template <class T>
+__device__ __forceinline__ T recip(T d)
+{
+    if constexpr (sizeof(T) == 4) {
+        float r = __builtin_amdgcn_rcpf(d);
+        return fmaf(r, fmaf(-d, r, 1.0f), r);
+    } else {
+        double r = __builtin_amdgcn_rcp(d);
+        r = fma(r, fma(-d, r, 1.0), r);
+        return fma(r, fma(-d, r, 1.0), r);
+    }
+}
+
 // Stiff regime of the source: where the field is screened, e^{-u/(n+1)} is
 // large and eta cancels against c1 e^{-u/(n+1)} (both ~1e4 in halo cores), and
 // dS/du dominates the Newton denominator.  There the FP32 operator still
@@ -56,12 +98,15 @@ template <class T>
 struct FofR {
     double Q, cLa3, c1, inv_np1;
     double a3, cL, np1;  // for the cold start
-    int n_is_one;        // n = 1: e^{-u/2} = 1/sqrt(e^u) (double precision only)
+    int n_is_one;        // n = 1: e^{-u/2} = 1/sqrt(e^u)
     // S(u) and dS/du at one cell, given e^u (ep)
     __device__ __forceinline__ void source(T p, T ep, T eta, T& S, T& dS) const
     {
         if constexpr (sizeof(T) == 4) {
-            const float e = expf(-p * float(inv_np1));
+            // (e^u >= 1e-30 for any field these solves meet; the bound only
+            // keeps the reciprocal square root finite)
+            const float e = n_is_one ? __builtin_amdgcn_rsqf(fmaxf(ep, 1e-30f))
+                                     : exp_fast(-p * float(inv_np1));
             if (e <= kFofRStiff) {
                 S = float(Q) * (eta + float(cLa3) - float(c1) * e);
                 dS = float(Q) * float(c1) * e * float(inv_np1);
@@ -98,8 +143,8 @@ struct FofR {
     {
         T enb[6];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) enb[f] = exp(nb[f]);
-        op_staged(p, nb, exp(p), enb, eta, ih2, L, D);
+        for (int f = 0; f < 6; ++f) enb[f] = exp_t(nb[f]);
+        op_staged(p, nb, exp_t(p), enb, eta, ih2, L, D);
     }
     __device__ __forceinline__ T cold(T eta) const
     {
@@ -141,7 +186,7 @@ struct StageOp {
 template <class T>
 struct StageOp<T, FofR<T>> {
     static constexpr bool kStaged = true;
-    __device__ __forceinline__ static T stage(T x) { return exp(x); }
+    __device__ __forceinline__ static T stage(T x) { return exp_t(x); }
     __device__ __forceinline__ static void eval(const FofR<T>& m, T p, const T nb[6], T ep,
                                                 const T enb[6], T eta, T ih2, T& L, T& D)
     {

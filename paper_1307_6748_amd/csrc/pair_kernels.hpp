@@ -337,12 +337,13 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_pairs(M m, int n, double
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Finest-level defect and per-block partial sums of r^2 for staged models
-// (f(R)), computed in double precision: each workgroup streams a TY x TZ
-// tile of the y-z plane along x through a ring of three planes in LDS that
-// hold phi and e^phi, so each exponential is computed once per loaded cell
-// (about 1.3 per cell with the halo) instead of seven times per stencil.
-// Tiles are visited grid-stride; n must be a multiple of TZ, TY and XC.
+// Finest-level defect and per-block partial sums of r^2, computed in double
+// precision: each workgroup streams a TY x TZ tile of the y-z plane along x
+// through a ring of three planes in LDS (phi and, for staged models such as
+// f(R), e^phi), so every value is fetched from HBM about once and each
+// exponential is computed once per loaded cell (about 1.3 per cell with the
+// halo) instead of seven times per stencil.  Tiles are visited grid-stride;
+// n must be a power of two and a multiple of TZ, TY and XC.
 template <int TY_, int TZ_, int XC_>
 struct NormTile {
     static constexpr int TY = TY_, TZ = TZ_, XC = XC_, NT = kBlock;
@@ -367,8 +368,9 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
     using SO = StageOp<double, M>;
     using VF = typename Vec2<TF>::type;
     using VD = typename Vec2<double>::type;
+    constexpr bool STAGED = SO::kStaged;
     __shared__ __align__(16) double ring[3][G::PLANE];
-    __shared__ __align__(16) double xring[3][G::PLANE];
+    __shared__ __align__(16) double xring[STAGED ? 3 : 1][STAGED ? G::PLANE : 2];
     const int tid = threadIdx.x;
     const int msk = n - 1;
     const int ntz = n / G::TZ, nty = n / G::TY, ntx = n / G::XC;
@@ -393,32 +395,39 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
         }
         const int zt = t % ntz, yt = (t / ntz) % nty, xt = t / (ntz * nty);
         const int x0 = xt * G::XC, y0 = yt * G::TY, z0 = zt * G::TZ;
+        const size_t n2 = (size_t)n * n;
+        // in-plane element offsets of this thread's pair loads (clamped tail)
+        unsigned poff[G::LPT];
+#pragma unroll
+        for (int q = 0; q < G::LPT; ++q) {
+            const int k = min(tid + q * G::NT, G::PAIRS - 1);
+            const int r = k / G::NP, c2 = k - r * G::NP;
+            poff[q] = (unsigned)(((y0 - 1 + r) & msk) * n + ((z0 - 2 + 2 * c2) & msk));
+        }
+        const unsigned eoff = (unsigned)((y0 + rr) * n + z0 + 2 * cp);
         VF regs[G::LPT];
         auto load = [&](int x) __attribute__((always_inline)) {
-            const long xoff = (long)(x & msk) * n;
+            const TF* pl = phi + (size_t)(x & msk) * n2;
 #pragma unroll
-            for (int q = 0; q < G::LPT; ++q) {
-                const int k = min(tid + q * G::NT, G::PAIRS - 1);
-                const int r = k / G::NP, c2 = k - r * G::NP;
-                const long g = (xoff + ((y0 - 1 + r) & msk)) * n + ((z0 - 2 + 2 * c2) & msk);
-                regs[q] = *reinterpret_cast<const VF*>(phi + g);
-            }
+            for (int q = 0; q < G::LPT; ++q) regs[q] = *reinterpret_cast<const VF*>(pl + poff[q]);
         };
         auto deposit = [&](int x) __attribute__((always_inline)) {
             double* d = ring[(x - x0 + 3) % 3];
-            double* e = xring[(x - x0 + 3) % 3];
 #pragma unroll
             for (int q = 0; q < G::LPT; ++q) {
                 const int k = tid + q * G::NT;
-                if (k < G::PAIRS) {
+                if ((q + 1) * G::NT <= G::PAIRS || k < G::PAIRS) {
                     const double a = (double)regs[q].x, b = (double)regs[q].y;
                     *reinterpret_cast<VD*>(d + 2 * k) = VD{a, b};
-                    *reinterpret_cast<VD*>(e + 2 * k) = VD{SO::stage(a), SO::stage(b)};
+                    if constexpr (STAGED) {
+                        double* e = xring[(x - x0 + 3) % 3];
+                        *reinterpret_cast<VD*>(e + 2 * k) = VD{SO::stage(a), SO::stage(b)};
+                    }
                 }
             }
         };
         auto eta_at = [&](int x) __attribute__((always_inline)) {
-            return ((long)(x & msk) * n + (y0 + rr)) * n + z0 + 2 * cp;
+            return (size_t)(x & msk) * n2 + eoff;
         };
         load(x0 - 1);
         deposit(x0 - 1);
@@ -433,46 +442,57 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
             // counts stay exact) overlap the stencil work below.
             deposit(x + 1);
             const VD e2 = enext;
-            const long g = eta_at(x);
+            const size_t g = eta_at(x);
             enext = *reinterpret_cast<const VD*>(eta + eta_at(min(x + 1, x0 + G::XC - 1)));
             load(min(x + 2, x0 + G::XC));
             __syncthreads();
             const double* pv = ring[(x - 1 - x0 + 3) % 3];
             const double* cu = ring[(x - x0 + 3) % 3];
             const double* nx = ring[(x + 1 - x0 + 3) % 3];
-            const double* epv = xring[(x - 1 - x0 + 3) % 3];
-            const double* ecu = xring[(x - x0 + 3) % 3];
-            const double* enx = xring[(x + 1 - x0 + 3) % 3];
             const int o = (rr + 1) * G::EZ + 2 + 2 * cp;
             const VD c = *reinterpret_cast<const VD*>(cu + o);
             const VD xm = *reinterpret_cast<const VD*>(pv + o);
             const VD xp = *reinterpret_cast<const VD*>(nx + o);
             const VD ym = *reinterpret_cast<const VD*>(cu + o - G::EZ);
             const VD yp = *reinterpret_cast<const VD*>(cu + o + G::EZ);
-            const VD ec = *reinterpret_cast<const VD*>(ecu + o);
-            const VD exm = *reinterpret_cast<const VD*>(epv + o);
-            const VD exp_ = *reinterpret_cast<const VD*>(enx + o);
-            const VD eym = *reinterpret_cast<const VD*>(ecu + o - G::EZ);
-            const VD eyp = *reinterpret_cast<const VD*>(ecu + o + G::EZ);
-            const double zm = cu[o - 1], zp = cu[o + 2], ezm = ecu[o - 1], ezp = ecu[o + 2];
+            const double zm = cu[o - 1], zp = cu[o + 2];
+            VD ec, exm, exp_, eym, eyp;
+            double ezm = 0.0, ezp = 0.0;
+            if constexpr (STAGED) {
+                const double* epv = xring[(x - 1 - x0 + 3) % 3];
+                const double* ecu = xring[(x - x0 + 3) % 3];
+                const double* enx = xring[(x + 1 - x0 + 3) % 3];
+                ec = *reinterpret_cast<const VD*>(ecu + o);
+                exm = *reinterpret_cast<const VD*>(epv + o);
+                exp_ = *reinterpret_cast<const VD*>(enx + o);
+                eym = *reinterpret_cast<const VD*>(ecu + o - G::EZ);
+                eyp = *reinterpret_cast<const VD*>(ecu + o + G::EZ);
+                ezm = ecu[o - 1];
+                ezp = ecu[o + 2];
+            }
             double L2[2];
 #pragma unroll
             for (int dk = 0; dk < 2; ++dk) {
-                double nbv[6], enb[6];
+                double nbv[6];
                 nbv[0] = xm[dk];
                 nbv[1] = xp[dk];
                 nbv[2] = ym[dk];
                 nbv[3] = yp[dk];
                 nbv[4] = dk ? c[0] : zm;
                 nbv[5] = dk ? zp : c[1];
-                enb[0] = exm[dk];
-                enb[1] = exp_[dk];
-                enb[2] = eym[dk];
-                enb[3] = eyp[dk];
-                enb[4] = dk ? ec[0] : ezm;
-                enb[5] = dk ? ezp : ec[1];
                 double L, D;
-                SO::eval(m, c[dk], nbv, ec[dk], enb, e2[dk], ih2, L, D);
+                if constexpr (STAGED) {
+                    double enb[6];
+                    enb[0] = exm[dk];
+                    enb[1] = exp_[dk];
+                    enb[2] = eym[dk];
+                    enb[3] = eyp[dk];
+                    enb[4] = dk ? ec[0] : ezm;
+                    enb[5] = dk ? ezp : ec[1];
+                    SO::eval(m, c[dk], nbv, ec[dk], enb, e2[dk], ih2, L, D);
+                } else {
+                    m.op(c[dk], nbv, e2[dk], ih2, L, D);
+                }
                 L2[dk] = L;
                 acc += L * L;
             }
