@@ -151,11 +151,11 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
  * ISIS_MIXED: FP32 V-cycles (FP32 fields, FP32 smoothing and coarse-grid
  * work; the f(R) source in FP64), each followed by the FP64 defect of the
  * FP32 iterate on the finest level, while that residual falls by at least
- * 0.6x per cycle (it stops falling at the FP32 round-off floor, which depends
- * on the problem: ~4e-7 relative for the symmetron, below 1e-8 for f(R) on
- * the 512^3 halo workload) and is above desc.fp32_floor (default 3 tol); then
- * FP64 V-cycles from the promoted iterate to tol.  The FP64 defect decides
- * convergence in both phases.
+ * 0.6x per cycle, no cycle's factor exceeds both 0.2 and 3x the previous
+ * one's (the FP32 round-off floor coming into view: ~2e-7 relative for the
+ * symmetron, below 1e-8 for f(R) on the 512^3 halo workload) and it is above
+ * desc.fp32_floor (default 3 tol); then FP64 V-cycles from the promoted
+ * iterate to tol.  The FP64 defect decides convergence in both phases.
  * Returns ISIS_OK, ISIS_ERR_NOT_CONVERGED (field = last iterate) or
  * ISIS_ERR_DIVERGED (field = last iterate, may be non-finite). */
 int isis_mg_solve(isis_mg_t* h, const double* density, double* field,

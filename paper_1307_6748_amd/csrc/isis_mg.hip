@@ -205,6 +205,24 @@ int launch_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta, c
     return ISIS_OK;
 }
 
+template <class T, class M, bool SIG>
+int launch_restrict_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
+                          const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, int blocks, int lds,
+                          hipStream_t s, char* err)
+{
+    auto kern = k_defect_restrict_tiled<T, M, SIG>;
+    static bool attr_done = false;  // per instantiation
+    if (!attr_done) {
+        HIP_TRY(err, hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), lds, s, m, nf, ih2f, phi_f, eta_f,
+                       sigma_f, phi_c, phihat_c, rr_c);
+    LAUNCH_CHECK(err, "k_defect_restrict_tiled");
+    return ISIS_OK;
+}
+
 template <class T, class M>
 int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f,
                    const T* sigma_f, const T* eta_c, T* phi_c, T* phihat_c, T* sigma_c, T* rr_c,
@@ -215,7 +233,17 @@ int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f
     T ih2f = (T)(1.0 / (hf * hf));
     double hc = 2.0 * hf;
     T ih2c = (T)(1.0 / (hc * hc));
-    if (nf >= 4)
+    using RG = RestrictTileF;
+    if ((nf & (nf - 1)) == 0 && nf % RG::TZ == 0 && nf % RG::TY == 0 && nc % RG::XC == 0) {
+        const int blocks = (nf / RG::TZ) * (nf / RG::TY) * (nc / RG::XC);
+        constexpr int lds = restrict_tiled_lds_bytes<T, M>();
+        int r = sigma_f ? launch_restrict_tiled<T, M, true>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                            phi_c, phihat_c, rr_c, blocks, lds, s, err)
+                        : launch_restrict_tiled<T, M, false>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                             phi_c, phihat_c, rr_c, blocks, lds, s,
+                                                             err);
+        if (r) return r;
+    } else if (nf >= 4)
         hipLaunchKernelGGL((k_defect_restrict_pairs<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s,
                            m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c);
     else
@@ -586,7 +614,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         // ~10% less accurate in phi for f(R)); an earlier stall of the FP32
         // cycles at their round-off floor also hands over.
         const double fp32_floor = d.fp32_floor > 0.0 ? d.fp32_floor : 3.0 * tol;
-        double rprev = r0;
+        double rprev = r0, rho_prev = 1.0;
         while (cyc < d.max_cycles) {
             if ((r = vcycle<float, M32>(H, m32, H->L32, 0, &updates))) return r;
             if (singular && (r = sub_mean<float>(H, H->L32[0].phi, n3))) return r;
@@ -604,9 +632,15 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                 status = ISIS_OK;
                 break;
             }
-            // The FP32 phase stalls at its round-off floor (or the caller's
-            // hand-over level is reached): refine in FP64.
-            if (rc > 0.6 * rprev || rc <= fp32_floor * rnorm) break;
+            // Refine in FP64 once the FP32 cycles reach their round-off floor:
+            // a cycle reduces the residual by less than 0.6x, or its factor
+            // jumps to more than 3x the previous cycle's (and above 0.2) as
+            // the floor comes into view; or at the caller's hand-over level.
+            const double rho = rc / rprev;
+            if (rc > 0.6 * rprev || (rho > 0.2 && rho > 3.0 * rho_prev) ||
+                rc <= fp32_floor * rnorm)
+                break;
+            rho_prev = rho;
             rprev = rc;
         }
         hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,

@@ -13,6 +13,17 @@
 
 namespace isis {
 
+// 7-point Laplacian (Sec. 3.1) summed as neighbour differences: each
+// difference of nearby values is exact (Sterbenz), so a smooth field loses no
+// digits to the cancellation of sum(nb) against 6 phi -- in FP32 this lowers
+// the round-off floor of the mixed-precision cycles.
+template <class T>
+__device__ __forceinline__ T lap7(T p, const T nb[6], T ih2)
+{
+    return (((nb[0] - p) + (nb[1] - p)) + ((nb[2] - p) + (nb[3] - p)) +
+            ((nb[4] - p) + (nb[5] - p))) * ih2;
+}
+
 // Symmetron, Sec. 4.1 (dimensionless equation):
 //   lap chi = K [ (A eta - 1) chi + chi^3 ],  K = a^2/(2 lambda0^2),
 //   A = (a_ssb/a)^3.
@@ -25,8 +36,7 @@ struct Symmetron {
     T K, A;
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
-        T sum = nb[0] + nb[1] + nb[2] + nb[3] + nb[4] + nb[5];
-        T lap = (sum - T(6) * p) * ih2;
+        T lap = lap7(p, nb, ih2);
         T S = K * (A * eta * p - p + p * p * p);
         T dS = K * (A * eta - T(1) + T(3) * p * p);
         L = lap - S;
@@ -124,16 +134,22 @@ struct FofR {
     // L and D from the cell value p, its e^p (ep) and the neighbours' values
     // and exponentials: the exponentials may be computed once per cell and
     // shared by all stencils that use them.
+    // With d_f = u_f - u: sum_f b_f d_f = (e^u sum d_f + sum e^{u_f} d_f)/2 and
+    // sum_f [e^u d_f/2 - b_f] = (e^u sum d_f - 6 e^u - sum e^{u_f})/2.
     __device__ __forceinline__ void op_staged(T p, const T nb[6], T ep, const T enb[6], T eta,
                                               T ih2, T& L, T& D) const
     {
-        T flux = T(0), dflux = T(0);
+        T sd = T(0), sed = T(0), se = T(0);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            T bf = T(0.5) * (ep + enb[f]);
-            flux += bf * (nb[f] - p);
-            dflux += T(0.5) * ep * (nb[f] - p) - bf;
+            const T d = nb[f] - p;
+            sd += d;
+            sed += enb[f] * d;
+            se += enb[f];
         }
+        const T esd = ep * sd;
+        const T flux = T(0.5) * (esd + sed);
+        const T dflux = T(0.5) * (esd - T(6) * ep - se);
         T S, dS;
         source(p, ep, eta, S, dS);
         L = flux * ih2 - S;
@@ -160,8 +176,7 @@ struct Linear {
     T kappa, m2;
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
-        T sum = nb[0] + nb[1] + nb[2] + nb[3] + nb[4] + nb[5];
-        T lap = (sum - T(6) * p) * ih2;
+        T lap = lap7(p, nb, ih2);
         T S = m2 * p + kappa * (eta - T(1));
         L = lap - S;
         D = -T(6) * ih2 - m2;

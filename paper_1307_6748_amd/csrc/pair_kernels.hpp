@@ -180,6 +180,183 @@ __global__ __launch_bounds__(kBlock) void k_prolong_pairs(int nf, T* __restrict_
     }
 }
 
+// FAS descent, first half (see k_defect_restrict), LDS-staged: each workgroup
+// owns a 16 x 64 tile of fine (y, z) cells -- 8 x 32 coarse cells, one per
+// thread -- and streams along x over XC coarse planes.  Fine planes pass
+// through a ring of four (2I-1 .. 2I+2 for coarse plane I; two new ones per
+// step), with e^phi beside them for staged models, so each fine value is read
+// from HBM about 1.2 times and each exponential computed about 1.2 times per
+// fine cell.  The 8 children are summed in the order of k_defect_restrict.
+template <int XC_>
+struct RestrictTile {
+    static constexpr int TY = 16, TZ = 64, XC = XC_, NT = kBlock;  // fine tile; XC coarse planes
+    static constexpr int EY = TY + 2;          // fine rows y0-1 .. y0+16
+    static constexpr int EZ = TZ + 4;          // fine columns z0-2 .. z0+65 (pairs aligned)
+    static constexpr int NP = EZ / 2;
+    static constexpr int PAIRS = EY * NP;
+    static constexpr int LPT = (PAIRS + NT - 1) / NT;
+    static constexpr int PLANE = EY * EZ;
+    static_assert((TY / 2) * (TZ / 2) == NT, "one coarse cell per thread");
+};
+using RestrictTileF = RestrictTile<8>;
+
+template <class T, class M>
+constexpr int restrict_tiled_lds_bytes()
+{
+    return 4 * RestrictTileF::PLANE * (int)sizeof(T) * (StageOp<T, M>::kStaged ? 2 : 1);
+}
+
+template <class T, class M, bool SIG>
+__global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
+    M m, int nf, T ih2, const T* __restrict__ phi, const T* __restrict__ eta,
+    const T* __restrict__ sigma, T* __restrict__ phi_c, T* __restrict__ phihat_c,
+    T* __restrict__ rr_c)
+{
+    using G = RestrictTileF;
+    using V = typename Vec2<T>::type;
+    using SO = StageOp<T, M>;
+    constexpr bool STAGED = SO::kStaged;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* ring = reinterpret_cast<T*>(smem_raw);  // 4 fine planes of phi
+    T* xring = ring + 4 * G::PLANE;            // 4 planes of e^phi (staged models)
+    const int nc = nf >> 1;
+    const int msk = nf - 1;
+    const size_t nf2 = (size_t)nf * nf;
+    const int tid = threadIdx.x;
+    const int ntz = nf / G::TZ, nty = nf / G::TY;
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous tiles per XCD
+    const int zt = b % ntz, yt = (b / ntz) % nty, it = b / (ntz * nty);
+    const int y0 = yt * G::TY, z0 = zt * G::TZ, I0 = it * G::XC;
+    const int jj = tid / (G::TZ / 2), kk = tid - jj * (G::TZ / 2);  // coarse cell in the tile
+
+    unsigned poff[G::LPT];
+    int doff[G::LPT];
+#pragma unroll
+    for (int q = 0; q < G::LPT; ++q) {
+        const int e = min(tid + q * G::NT, G::PAIRS - 1);
+        const int r = e / G::NP, c2 = e - r * G::NP;
+        poff[q] = (unsigned)(((y0 - 1 + r) & msk) * nf + ((z0 - 2 + 2 * c2) & msk));
+        doff[q] = r * G::EZ + 2 * c2;
+    }
+    // this thread's 8 children: fine rows 2jj, 2jj+1 of the tile, columns 2kk, 2kk+1
+    const unsigned coff0 = (unsigned)((y0 + 2 * jj) * nf + z0 + 2 * kk);  // row 2jj
+    const unsigned coff1 = coff0 + (unsigned)nf;                          // row 2jj+1
+    V ra[G::LPT], rb[G::LPT];
+    auto load2 = [&](int x) __attribute__((always_inline)) {  // fine planes x, x+1
+        const T* pa = phi + (size_t)(x & msk) * nf2;
+        const T* pb = phi + (size_t)((x + 1) & msk) * nf2;
+#pragma unroll
+        for (int q = 0; q < G::LPT; ++q) {
+            ra[q] = *reinterpret_cast<const V*>(pa + poff[q]);
+            rb[q] = *reinterpret_cast<const V*>(pb + poff[q]);
+        }
+    };
+    auto deposit1 = [&](int x, const V (&regs)[G::LPT]) __attribute__((always_inline)) {
+        T* d = ring + (x & 3) * G::PLANE;
+        T* e = xring + (x & 3) * G::PLANE;
+#pragma unroll
+        for (int q = 0; q < G::LPT; ++q) {
+            if ((q + 1) * G::NT <= G::PAIRS || tid + q * G::NT < G::PAIRS) {
+                *reinterpret_cast<V*>(d + doff[q]) = regs[q];
+                if constexpr (STAGED)
+                    *reinterpret_cast<V*>(e + doff[q]) =
+                        V{SO::stage(regs[q].x), SO::stage(regs[q].y)};
+            }
+        }
+    };
+    // prologue: fine planes 2I0-1, 2I0 in LDS, 2I0+1, 2I0+2 in registers
+    load2(2 * I0 - 1);
+    deposit1(2 * I0 - 1, ra);
+    deposit1(2 * I0, rb);
+    load2(2 * I0 + 1);
+    const int o00 = (2 * jj + 1) * G::EZ + 2 + 2 * kk;  // LDS offset of child (row 2jj, col 2kk)
+    for (int I = I0; I < I0 + G::XC; ++I) {
+        deposit1(2 * I + 1, ra);
+        deposit1(2 * I + 2, rb);
+        // this step's densities (and sources), then the next two planes
+        V e2[2][2], s2[2][2];
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+            const size_t xo = (size_t)((2 * I + di) & msk) * nf2;
+            e2[di][0] = *reinterpret_cast<const V*>(eta + xo + coff0);
+            e2[di][1] = *reinterpret_cast<const V*>(eta + xo + coff1);
+            if constexpr (SIG) {
+                s2[di][0] = *reinterpret_cast<const V*>(sigma + xo + coff0);
+                s2[di][1] = *reinterpret_cast<const V*>(sigma + xo + coff1);
+            } else {
+                s2[di][0] = s2[di][1] = V{T(0), T(0)};
+            }
+        }
+        load2(min(2 * I + 3, 2 * (I0 + G::XC) - 1));  // clamped: branch-free
+        __syncthreads();
+        T sr = T(0), sp = T(0);
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+            const int x = 2 * I + di;
+            const T* cu = ring + (x & 3) * G::PLANE;
+            const T* pv = ring + ((x - 1) & 3) * G::PLANE;
+            const T* nx = ring + ((x + 1) & 3) * G::PLANE;
+            const T* ecu = xring + (x & 3) * G::PLANE;
+            const T* epv = xring + ((x - 1) & 3) * G::PLANE;
+            const T* enx = xring + ((x + 1) & 3) * G::PLANE;
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const int o = o00 + dj * G::EZ;
+                const V c = *reinterpret_cast<const V*>(cu + o);
+                const V xm = *reinterpret_cast<const V*>(pv + o);
+                const V xp = *reinterpret_cast<const V*>(nx + o);
+                const V ym = *reinterpret_cast<const V*>(cu + o - G::EZ);
+                const V yp = *reinterpret_cast<const V*>(cu + o + G::EZ);
+                const T zm = cu[o - 1], zp = cu[o + 2];
+                V ec, exm, exq, eym, eyp;
+                T ezm = T(0), ezp = T(0);
+                if constexpr (STAGED) {
+                    ec = *reinterpret_cast<const V*>(ecu + o);
+                    exm = *reinterpret_cast<const V*>(epv + o);
+                    exq = *reinterpret_cast<const V*>(enx + o);
+                    eym = *reinterpret_cast<const V*>(ecu + o - G::EZ);
+                    eyp = *reinterpret_cast<const V*>(ecu + o + G::EZ);
+                    ezm = ecu[o - 1];
+                    ezp = ecu[o + 2];
+                }
+#pragma unroll
+                for (int dk = 0; dk < 2; ++dk) {
+                    T nbv[6];
+                    nbv[0] = xm[dk];
+                    nbv[1] = xp[dk];
+                    nbv[2] = ym[dk];
+                    nbv[3] = yp[dk];
+                    nbv[4] = dk ? c[0] : zm;
+                    nbv[5] = dk ? zp : c[1];
+                    T L, D;
+                    if constexpr (STAGED) {
+                        T enb[6];
+                        enb[0] = exm[dk];
+                        enb[1] = exq[dk];
+                        enb[2] = eym[dk];
+                        enb[3] = eyp[dk];
+                        enb[4] = dk ? ec[0] : ezm;
+                        enb[5] = dk ? ezp : ec[1];
+                        SO::eval(m, c[dk], nbv, ec[dk], enb, e2[di][dj][dk], ih2, L, D);
+                    } else {
+                        m.op(c[dk], nbv, e2[di][dj][dk], ih2, L, D);
+                    }
+                    sr += L - s2[di][dj][dk];
+                    sp += c[dk];
+                }
+            }
+        }
+        const size_t q = ((size_t)I * nc + (y0 / 2 + jj)) * nc + z0 / 2 + kk;
+        const T pc = sp / T(8);
+        phi_c[q] = pc;
+        phihat_c[q] = pc;
+        rr_c[q] = sr / T(8);
+        __syncthreads();  // the slots of planes 2I-1, 2I are refilled next
+    }
+}
+
 // fine += P(coarse - coarse_hat), LDS-staged: each workgroup owns a TJ x TK
 // tile of coarse (y, z) cells and streams along coarse x over XC planes.  The
 // coarse differences pass through a ring of three planes (tile plus a
