@@ -43,6 +43,7 @@
  *       root up to rounding and the tolerance is absolute.
  *   R10 Symmetron Newton denominator is safeguarded as -6/h^2 - |dS/dphi|.
  *   R11 LINEAR with m2 = 0 is singular; its mean is removed after each cycle.
+ *   R12 Forces on the grid use second-order central differences, periodic.
  *
  * Built with -O2 -ffp-contract=off (no fused multiply-add, no fast-math).
  * OpenMP parallelises loops whose iterations are independent (one colour of
@@ -81,6 +82,7 @@ typedef struct {
     double omega_l; /* cosmological-constant density parameter               */
     double kappa;   /* LINEAR: S = m2 phi + kappa (eta - 1)                  */
     double m2;
+    double beta;    /* symmetron coupling (enters the fifth force only)      */
 } orc_model;
 
 typedef struct {
@@ -541,4 +543,59 @@ int orc_vcycles(const orc_model* m, const orc_cfg* cfg, int n, double box, const
     if (s == ORC_INVALID) return s;
     for (int q = 0; q <= st.cycles; ++q) rel[q] = st.rel_hist[q];
     return st.cycles;
+}
+
+/* ------------------------------------------------------------------ */
+/* Force on the grid (the step after the solve in the paper's pipeline) */
+/* ------------------------------------------------------------------ */
+
+/* Second-order central difference of f along axis `ax` at cell (i,j,k),
+ * periodic (reading R12: the paper does not state the gradient stencil). */
+static double cdiff(long n, double h, const double* f, long i, long j, long k, int ax)
+{
+    long ip = i, im = i, jp = j, jm = j, kp = k, km = k;
+    if (ax == 0) { ip = wrap(i + 1, n); im = wrap(i - 1, n); }
+    if (ax == 1) { jp = wrap(j + 1, n); jm = wrap(j - 1, n); }
+    if (ax == 2) { kp = wrap(k + 1, n); km = wrap(k - 1, n); }
+    return (f[cidx(n, ip, jp, kp)] - f[cidx(n, im, jm, km)]) / (2.0 * h);
+}
+
+/* Acceleration d^2x/dtau^2 in super-comoving variables at every cell:
+ *   - grad(potential)                        (if potential != NULL; the
+ *                                              caller's potential is a^2 Phi)
+ *   minus the scalar-field term of the geodesic equation:
+ *   symmetron, Sec. 4.1 (eq. symmetron_geodesics_tilde_chi), chi~ = a chi:
+ *       6 Omega_m H0^2 (beta lambda0)^2 / a_ssb^3 * chi~ grad chi~
+ *   Hu-Sawicki f(R), Sec. 4.2 (geodesic equation), with the paper's variable
+ *   e^{u_paper} = a^2 |f_R0| e^u (reading R5), grad u_paper = grad u:
+ *       (1/2) a^2 |f_R0| e^u grad u
+ *   LINEAR: no scalar-field term.
+ * fx, fy, fz: n^3 each, component along x, y, z. */
+void orc_force(const orc_model* m, int n, double h, const double* field, const double* potential,
+               double* fx, double* fy, double* fz)
+{
+    const long N = n;
+    double* out[3] = {fx, fy, fz};
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; ++i)
+        for (long j = 0; j < N; ++j)
+            for (long k = 0; k < N; ++k) {
+                const long c = cidx(N, i, j, k);
+                for (int ax = 0; ax < 3; ++ax) {
+                    double acc = 0.0;
+                    if (potential) acc -= cdiff(N, h, potential, i, j, k, ax);
+                    if (m->model == ORC_SYMMETRON) {
+                        const double chit = m->a * field[c];
+                        const double gchit = m->a * cdiff(N, h, field, i, j, k, ax);
+                        const double bl = m->beta * m->lambda0;
+                        const double coef = 6.0 * m->omega_m * ORC_H0 * ORC_H0 * bl * bl /
+                                            (m->a_ssb * m->a_ssb * m->a_ssb);
+                        acc -= coef * chit * gchit;
+                    } else if (m->model == ORC_FR_HS) {
+                        const double eup = m->a * m->a * m->fR0_abs * exp(field[c]);
+                        acc -= 0.5 * eup * cdiff(N, h, field, i, j, k, ax);
+                    }
+                    out[ax][c] = acc;
+                }
+            }
 }

@@ -48,7 +48,7 @@ class _Model(C.Structure):
     _fields_ = [("model", C.c_int), ("a", C.c_double), ("lambda0", C.c_double),
                 ("a_ssb", C.c_double), ("n", C.c_double), ("fR0_abs", C.c_double),
                 ("omega_m", C.c_double), ("omega_l", C.c_double), ("kappa", C.c_double),
-                ("m2", C.c_double)]
+                ("m2", C.c_double), ("beta", C.c_double)]
 
 
 class _Cfg(C.Structure):
@@ -74,10 +74,11 @@ class Model:
     omega_l: float = 0.73
     kappa: float = 1.0
     m2: float = 0.0
+    beta: float = 1.0
 
     def _c(self) -> _Model:
         return _Model(int(self.model), self.a, self.lambda0, self.a_ssb, self.n, self.fR0_abs,
-                      self.omega_m, self.omega_l, self.kappa, self.m2)
+                      self.omega_m, self.omega_l, self.kappa, self.m2, self.beta)
 
 
 @dataclass
@@ -128,6 +129,8 @@ def lib():
         L.orc_num_levels.argtypes = [C.c_int]
         L.orc_solve.argtypes = [C.POINTER(_Model), C.POINTER(_Cfg), C.c_int, C.c_double, dp,
                                 dp, C.c_int, C.c_double, C.POINTER(_Stats)]
+        L.orc_force.argtypes = [C.POINTER(_Model), C.c_int, C.c_double, dp, C.c_void_p, dp, dp,
+                                dp]
         _lib = L
     return _lib
 
@@ -168,6 +171,18 @@ def defect(m: Model, h: float, phi, eta, sigma=None) -> np.ndarray:
     mc = m._c()
     lib().orc_defect(C.byref(mc), n, h, phi, eta, _ptr_or_null(sig), out)
     return out
+
+
+def force(m: Model, h: float, field, potential=None):
+    """Acceleration (fx, fy, fz) in super-comoving variables: -grad(potential)
+    (if given) minus the scalar-field term of the model's geodesic equation
+    (Sec. 4.1 symmetron, Sec. 4.2 f(R)), second-order central differences."""
+    field = _f64(field)
+    pot = None if potential is None else _f64(potential)
+    fx, fy, fz = (np.empty_like(field) for _ in range(3))
+    mc = m._c()
+    lib().orc_force(C.byref(mc), field.shape[0], h, field, _ptr_or_null(pot), fx, fy, fz)
+    return fx, fy, fz
 
 
 def newton_diag(m: Model, h: float, phi, eta) -> np.ndarray:

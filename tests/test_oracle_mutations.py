@@ -35,7 +35,17 @@ MUTATIONS = {
                                  "double lap = (sum - 5.0 * p) * ih2;"),
     "neighbour_index": ("nb[3] = phi[cidx(n, i, wrap(j + 1, n), k)];",
                         "nb[3] = phi[cidx(n, i, wrap(j - 1, n), k)];"),
+    "force_difference_sign": ("return (f[cidx(n, ip, jp, kp)] - f[cidx(n, im, jm, km)]) / (2.0 * h);",
+                              "return (f[cidx(n, im, jm, km)] - f[cidx(n, ip, jp, kp)]) / (2.0 * h);"),
+    "force_fr_half_dropped": ("acc -= 0.5 * eup * cdiff(N, h, field, i, j, k, ax);",
+                              "acc -= eup * cdiff(N, h, field, i, j, k, ax);"),
+    "force_beta_not_squared": ("bl * bl /", "bl /"),
+    "force_chi_tilde_missing_a": ("const double chit = m->a * field[c];",
+                                  "const double chit = field[c];"),
+    "force_axis_swap": ("if (ax == 1) { jp = wrap(j + 1, n); jm = wrap(j - 1, n); }",
+                        "if (ax == 1) { kp = wrap(k + 1, n); km = wrap(k - 1, n); }"),
 }
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -49,8 +59,8 @@ def test_planted_mistake_fails_a_pin(tmp_path, name):
     so = str(tmp_path / "libmutant.so")
     O.build(force=True, src=str(mut), out=so)
     env = dict(os.environ, ORACLE_LIB=so, OMP_NUM_THREADS="4")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] +
+                       [os.path.join(ROOT, "tests", f) for f in PIN_FILES],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"{name}: pins did not fail\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout
