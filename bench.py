@@ -13,8 +13,9 @@ models of the timed steps).  Also reported: Newton-GS cell updates/s, the
 finest-level smoother's achieved HBM bandwidth measured with HIP events on the
 solver stream (roofline), the plain FP64 GPU solve for comparison, a full-size
 residual check of the GPU solutions by the CPU oracle, and the CPU oracle timed
-solving the same two problems (cpu_baseline), and the learned warm start
-(U-Net prediction + solve, symmetron) as a separate leg.
+solving the same two problems (cpu_baseline), the learned warm start
+(U-Net prediction + solve, symmetron) as a separate leg, and the step after the
+solve (Newtonian potential on the same grid, force kernel) as another.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -147,6 +148,8 @@ def main() -> int:
                     help="skip the CPU oracle (full-size parity and cpu_baseline)")
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-force", action="store_true",
+                    help="skip the Newtonian potential solve and the force kernel")
     ap.add_argument("--points-per-halo", type=int, default=200_000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device twice (calibrates the HBM "
@@ -244,6 +247,43 @@ def main() -> int:
             del ph
         plain.close()
         del plain
+
+    # The step after the solve: the Newtonian potential on the same grid (the
+    # Poisson equation of Sec. 3.1 as the linear model) and the total force
+    # -grad(a^2 Phi) - F_scalar for each model's solution (isis_force).
+    force_leg = None
+    if not args.no_force:
+        a_n = 1.0
+        pN = S.newtonian(0.27, a_n)
+        phiN = torch.empty_like(eta)
+        prod.solve(eta, pN, a_n, TOL, phi=phiN)  # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, stN = prod.solve(eta, pN, a_n, TOL, phi=phiN)
+        torch.cuda.synchronize()
+        t_pot = time.perf_counter() - t1
+        pot = phiN * (a_n * a_n)
+        out = tuple(torch.empty_like(eta) for _ in range(3))
+        reps = 5
+        kern = {}
+        for name, (p, a) in mods.items():
+            S.force(p, a, box, field=phis[name], potential=pot, out=out)  # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                S.force(p, a, box, field=phis[name], potential=pot, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = 40.0 * n ** 3  # read field + potential, write three components (FP64)
+            kern[name] = dict(ms=ms, achieved_gbs=nbytes / (ms * 1e-3) / 1e9,
+                              frac=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        force_leg = dict(potential_solve_s=t_pot, potential_cycles=stN.cycles,
+                         potential_rel_res=stN.rel_res, force_kernel=kern,
+                         bytes_per_launch=40.0 * n ** 3)
+        log(f"newtonian potential: {t_pot:.4f}s ({stN.cycles} cycles); force kernel "
+            + ", ".join(f"{k} {v['ms']:.3f} ms ({v['achieved_gbs']:.0f} GB/s)" for k, v in kern.items()))
+        del out, pot, phiN
 
     warm = None
     if not args.no_warm_start:
@@ -352,6 +392,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "parity": parity or None,
         "warm_start": warm,
+        "force": force_leg,
     }
     print(json.dumps(out), flush=True)
     return 0

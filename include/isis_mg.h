@@ -297,6 +297,24 @@ int isis_conv3_bwd_weight(const uint16_t* x, int n, int cin, const uint16_t* dy,
                           float* dw, float* db, void* workspace, size_t workspace_bytes,
                           void* stream);
 
+/* Acceleration on the grid, the step after the solve in the paper's
+ * pipeline: f = -grad(potential) - F, F the scalar-field term of the model's
+ * geodesic equation in super-comoving variables:
+ *   ISIS_SYMMETRON (Sec. 4.1, eq. symmetron_geodesics_tilde_chi):
+ *       F = 6 Omega_m H0^2 (beta lambda0)^2 / a_ssb^3 chi~ grad chi~, chi~ = a field;
+ *   ISIS_FR_HS (Sec. 4.2, geodesic equation): F = (1/2) e^{u_paper} grad u_paper
+ *       = (1/2) a^2 |f_R0| e^u grad u, u = field = ln(f_R/f_R0);
+ *   ISIS_LINEAR: F = 0 (field unused, may be NULL).
+ * Gradients are second-order periodic central differences (the paper does not
+ * state the stencil).  field, potential: device n^3 doubles (potential may be
+ * NULL; for the Newtonian force pass a^2 Phi with Phi from an ISIS_LINEAR
+ * solve of the Poisson equation of Sec. 3.1, kappa = 1.5 Omega_m H0^2 / a,
+ * m2 = 0); fx, fy, fz: device n^3 doubles, written.  n even >= 2, h = box/n.
+ * ISIS_ERR_INVALID_ARG on bad sizes, parameters (the symmetron also needs
+ * Omega_m > 0 and a finite beta) or pointers. */
+int isis_force(const isis_model_params* p, double a, int n, double h, const double* field,
+               const double* potential, double* fx, double* fy, double* fz, void* stream);
+
 /* Pointwise homogeneous root (cold start): symmetron sqrt(max(0, 1 -
  * (a_ssb/a)^3 eta)); f(R) -(n+1) ln[(eta/a^3 + cL)/(1 + cL)]; LINEAR 0. */
 int isis_op_cold_start(const isis_model_params* p, double a, long ncell, const double* eta,

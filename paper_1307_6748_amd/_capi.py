@@ -57,6 +57,7 @@ SIGNATURES = [
     ("isis_mg_last_error", C.c_char_p, [_P]),
     ("isis_mg_set_profiling", _I, [_P, _I]),
     ("isis_op_halfsweep", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _I, _P]),
+    ("isis_force", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P, _P]),
     ("isis_op_sweeps", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _I, _I, _P]),
     ("isis_op_defect", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P]),
     ("isis_op_restrict", _I, [_I, _P, _P, _P]),

@@ -19,6 +19,7 @@
 #include <new>
 
 #include "../../include/isis_mg.h"
+#include "force.hpp"
 #include "fused_sweep.hpp"
 #include "kernels.hpp"
 #include "pair_kernels.hpp"
@@ -698,6 +699,37 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
 // C ABI.
 // ---------------------------------------------------------------------------
 
+namespace {
+
+template <ScalarForce SF, bool POT>
+int launch_force_t(int n, double h, double c, const double* field, const double* pot, double* fx,
+                   double* fy, double* fz, hipStream_t s, char* err)
+{
+    using FG = ForceTileF;
+    const double inv2h = 0.5 / h;
+    if ((n & (n - 1)) == 0 && n % FG::TZ == 0 && n % FG::TY == 0 && n % FG::XC == 0) {
+        const long tiles = (long)(n / FG::TZ) * (n / FG::TY) * (n / FG::XC);
+        const int g = (int)std::min<long>(8192, tiles);
+        hipLaunchKernelGGL((k_force_tiled<SF, POT>), dim3(g), dim3(kBlock), 0, s, n, inv2h, c,
+                           field, pot, fx, fy, fz);
+    } else {
+        hipLaunchKernelGGL((k_force_cells<SF, POT>), dim3(grid_for((long)n * n * n)),
+                           dim3(kBlock), 0, s, n, inv2h, c, field, pot, fx, fy, fz);
+    }
+    LAUNCH_CHECK(err, "k_force");
+    return ISIS_OK;
+}
+
+template <ScalarForce SF>
+int launch_force(int n, double h, double c, const double* field, const double* pot, double* fx,
+                 double* fy, double* fz, hipStream_t s, char* err)
+{
+    return pot ? launch_force_t<SF, true>(n, h, c, field, pot, fx, fy, fz, s, err)
+               : launch_force_t<SF, false>(n, h, c, field, pot, fx, fy, fz, s, err);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t isis_mg_workspace_size(const isis_mg_desc* desc)
@@ -969,6 +1001,37 @@ int isis_op_coarse_solve(const isis_model_params* p, double a, double h, double*
         return launch_coarse<double, decltype(m)>(m, h, phi, eta, sigma, nu_c,
                                                   (hipStream_t)stream, g_err);
     });
+}
+
+int isis_force(const isis_model_params* p, double a, int n, double h, const double* field,
+               const double* potential, double* fx, double* fy, double* fz, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    const bool scalar = p->model != ISIS_LINEAR;
+    if (!op_grid_ok(n, 2) || !finite_pos(h) || !fx || !fy || !fz || (scalar && !field)) {
+        fmt_err(g_err, "force: need even n >= 2, h > 0, fx/fy/fz non-NULL and the field for "
+                       "a scalar-field model");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (p->model == ISIS_SYMMETRON && (!finite_pos(p->omega_m) || !std::isfinite(p->beta))) {
+        fmt_err(g_err, "symmetron force needs Omega_m > 0 and a finite beta");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!ptrs_aligned({field, potential, fx, fy, fz})) return ISIS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->model == ISIS_SYMMETRON) {
+        const double bla = p->beta * p->lambda0 * a;
+        const double c = 6.0 * p->omega_m * kH0 * kH0 * bla * bla /
+                         (p->a_ssb * p->a_ssb * p->a_ssb);
+        return launch_force<ScalarForce::kChiGradChi>(n, h, c, field, potential, fx, fy, fz, s,
+                                                      g_err);
+    }
+    if (p->model == ISIS_FR_HS) {
+        const double c = 0.5 * a * a * p->fR0_abs;
+        return launch_force<ScalarForce::kExpGrad>(n, h, c, field, potential, fx, fy, fz, s,
+                                                   g_err);
+    }
+    return launch_force<ScalarForce::kNone>(n, h, 0.0, field, potential, fx, fy, fz, s, g_err);
 }
 
 int isis_op_cold_start(const isis_model_params* p, double a, long ncell, const double* eta,

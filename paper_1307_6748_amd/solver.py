@@ -54,8 +54,10 @@ class ModelParams:
                               self.fR0_abs, self.omega_m, self.omega_l, self.kappa, self.m2)
 
 
-def symmetron(lambda0=1.0, a_ssb=0.5, beta=1.0) -> ModelParams:
-    return ModelParams(model=A.ISIS_SYMMETRON, lambda0=lambda0, a_ssb=a_ssb, beta=beta)
+def symmetron(lambda0=1.0, a_ssb=0.5, beta=1.0, omega_m=0.27) -> ModelParams:
+    """omega_m enters only the fifth force (force())."""
+    return ModelParams(model=A.ISIS_SYMMETRON, lambda0=lambda0, a_ssb=a_ssb, beta=beta,
+                       omega_m=omega_m)
 
 
 def fofr(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=None) -> ModelParams:
@@ -65,6 +67,15 @@ def fofr(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=None) -> ModelParams:
 
 def linear(kappa=1.0, m2=0.0) -> ModelParams:
     return ModelParams(model=A.ISIS_LINEAR, kappa=kappa, m2=m2)
+
+
+H0 = 1.0 / 2997.92458  # h/Mpc with c = 1
+
+
+def newtonian(omega_m: float, a: float) -> ModelParams:
+    """The Poisson equation of Sec. 3.1, lap Phi = 1.5 Omega_m H0^2 (eta - 1) / a,
+    as the linear model (kappa = 1.5 Omega_m H0^2 / a, m2 = 0)."""
+    return linear(kappa=1.5 * omega_m * H0 * H0 / a, m2=0.0)
 
 
 @dataclass
@@ -291,4 +302,17 @@ def cold_start(params: ModelParams, a: float, eta, out=None):
     pc = params.c()
     _ok(A.lib().isis_op_cold_start(C.byref(pc), float(a), eta.numel(), _ptr(eta), _ptr(out),
                                    _stream()))
+    return out
+
+
+def force(params: ModelParams, a: float, box: float, field=None, potential=None, out=None):
+    """Acceleration (fx, fy, fz) on the grid: -grad(potential) minus the
+    scalar-field term of the model's geodesic equation (see isis_force)."""
+    ref = field if field is not None else potential
+    n = _side(ref)
+    if out is None:
+        out = tuple(torch.empty_like(ref) for _ in range(3))
+    pc = params.c()
+    _ok(A.lib().isis_force(C.byref(pc), float(a), n, float(box) / n, _ptr(field),
+                           _ptr(potential), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream()))
     return out

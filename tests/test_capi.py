@@ -110,3 +110,17 @@ def test_ops_reject_misaligned_pointers_on_host():
                                    None) == -1
     assert lib.isis_op_coarse_solve(C.byref(p), 1.0, 1.0, bad, ok, None, 4, None) == -1
     assert lib.isis_op_cold_start(C.byref(p), 1.0, 8, ok, bad, None) == -1
+
+
+def test_force_validates_on_host():
+    lib = A.lib()
+    ok, bad = C.c_void_p(4096), C.c_void_p(4096 + 8)  # never dereferenced
+    lin = A.ModelParamsC(A.ISIS_LINEAR, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0)
+    sym0 = A.ModelParamsC(A.ISIS_SYMMETRON, 1.0, 0.5, 1, 1, 1e-5, 0.0, 0.73, 1, 0)
+    fr = A.ModelParamsC(A.ISIS_FR_HS, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0)
+    assert lib.isis_force(C.byref(lin), 1.0, 7, 1.0, None, ok, ok, ok, ok, None) == -1
+    assert lib.isis_force(C.byref(lin), 1.0, 8, 0.0, None, ok, ok, ok, ok, None) == -1
+    assert lib.isis_force(C.byref(sym0), 1.0, 8, 1.0, ok, None, ok, ok, ok, None) == -1
+    assert b"Omega_m" in lib.isis_mg_last_error(None)
+    assert lib.isis_force(C.byref(fr), 1.0, 8, 1.0, None, ok, ok, ok, ok, None) == -1
+    assert lib.isis_force(C.byref(fr), 1.0, 8, 1.0, ok, None, ok, bad, ok, None) == -1
