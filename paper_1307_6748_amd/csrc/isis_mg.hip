@@ -551,8 +551,9 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                                          H->err)))
             return r;
 
-    // r_ref from the cold start, whatever the initial guess.
-    double* cold = H->L64[0].tmp;
+    // r_ref from the cold start, whatever the initial guess.  Without a
+    // guess the cold start is built in the field itself.
+    double* cold = use_guess ? H->L64[0].tmp : field;
     hipLaunchKernelGGL((k_cold_start<double, M64>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
                        m64, n3, density, cold);
     LAUNCH_CHECK(H->err, "k_cold_start");
@@ -569,14 +570,11 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     if ((r = field_rms<double>(H, cold, n3, &cold_rms))) return r;
     const double h0 = H->L64[0].h;
     const double cold_scale = 1e-14 * 6.0 / (h0 * h0) * cold_rms;
-    if (!use_guess)
-        HIP_TRY(H->err, hipMemcpyAsync(field, cold, sizeof(double) * n3,
-                                       hipMemcpyDeviceToDevice, H->s));
     if (singular && (r = sub_mean<double>(H, field, n3))) return r;
     const double rnorm = r_ref > cold_scale ? r_ref : 1.0;
     LevP<double>& F = H->L64[0];  // F.phi: the current finest field (may move to tmp0)
-    double r0;
-    if ((r = fine_rms<double, M64>(H, m64, field, density, nullptr, &r0))) return r;
+    double r0 = r_ref;            // the field is the cold start (zero-mean for LINEAR m2 = 0)
+    if (use_guess && (r = fine_rms<double, M64>(H, m64, field, density, nullptr, &r0))) return r;
     if (use_guess == 2 && !(r0 < r_ref)) {
         // the supplied guess is no better than the cold start: use the latter
         HIP_TRY(H->err, hipMemcpyAsync(field, cold, sizeof(double) * n3,

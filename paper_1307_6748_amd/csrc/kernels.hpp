@@ -174,8 +174,17 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(long total, const T* __restric
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partial, int count,
                                                    double* __restrict__ out)
 {
+    // Each thread sums fixed runs of 8 consecutive partials (loads issued
+    // together, added in order): deterministic, and a few load latencies
+    // instead of count / blockDim dependent ones.
     double acc = 0.0;
-    for (int q = threadIdx.x; q < count; q += blockDim.x) acc += partial[q];
+    for (int q0 = threadIdx.x * 8; q0 < count; q0 += blockDim.x * 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = q0 + j < count ? partial[q0 + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += v[j];
+    }
     double s = block_sum(acc);
     if (threadIdx.x == 0) out[0] = s;
 }
