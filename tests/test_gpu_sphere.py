@@ -1,0 +1,60 @@
+"""The paper's static top-hat sphere test (Sec. 5.1) on the GPU solver: a
+sphere of radius R and density jump delta = 5000 at the centre of a periodic
+box, solved in 3D and compared with the radial reference of
+oracle/sphere_ref.py (a 1D boundary-value solve; the paper compared with 1D
+solutions too).  Symmetron: R = 3, B = 40 Mpc/h, lambda0 = 1 Mpc/h,
+a_ssb = 0.6 at z = 0 and z = 1.  f(R): R = 5, B = 100 Mpc/h, n = 1,
+|f_R0| = 1e-6.  The grid is uniform (the paper used 128^3 plus two
+refinement levels); the error outside a band around the surface must fall
+under refinement: second order for the symmetron; first order for f(R),
+whose coefficient e^u jumps by ~1e4 at the surface, which the arithmetic
+face average and the cell-averaged surface resolve to O(h)."""
+import numpy as np
+import pytest
+
+from gpucase import cubic, dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _errors(sp, a, model, R, B, rmax, band, ns):
+    from oracle import sphere_ref as SR
+    from paper_1307_6748_amd import solver as S
+    rr, pp = SR.solve_fd_profile(model, R, B, 5000.0, rmax, m=40000)
+    prof = SR.solve_bvp_profile(model, R, B, 5000.0, rmax, tol=1e-6, guess=(rr, pp))
+    out = []
+    for n in ns:
+        eta = SR.grid_density(n, B, R, 5000.0)
+        rad = SR.cell_radius(n, B)
+        s = S.Solver(n, B, precision="mixed", temporal_block=1, max_cycles=120)
+        phi, st = s.solve(dev(eta), sp, a, 1e-10)
+        assert st.status == 0
+        got = cubic(phi, n)
+        s.close()
+        ref = prof(np.minimum(rad, rmax))
+        sel = (rad <= B / 4) & (np.abs(rad - R) > band)
+        err = np.abs(got - ref)[sel]
+        out.append((np.sqrt(np.mean(err ** 2)), err.max()))
+    return out
+
+
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_symmetron_sphere(a):
+    from oracle import sphere_ref as SR
+    from paper_1307_6748_amd import solver as S
+    (rms1, max1), (rms2, max2) = _errors(S.symmetron(1.0, 0.6), a, SR.symmetron_model(a, 1.0, 0.6),
+                                         3.0, 40.0, 15.0, 0.75, (128, 256))
+    print(f"symmetron a={a}: rms {rms1:.2e} -> {rms2:.2e}, max {max1:.2e} -> {max2:.2e}")
+    assert rms2 < rms1 / 2.5
+    assert max2 < 6e-3
+
+
+def test_fofr_sphere():
+    from oracle import sphere_ref as SR
+    from paper_1307_6748_amd import solver as S
+    (rms1, max1), (rms2, max2) = _errors(S.fofr(1.0, 1e-6, 0.27, 0.73), 1.0,
+                                         SR.fofr_model(1.0, 1.0, 1e-6, 0.27, 0.73),
+                                         5.0, 100.0, 40.0, 2.5, (128, 256))
+    print(f"f(R): rms {rms1:.2e} -> {rms2:.2e}, max {max1:.2e} -> {max2:.2e}")
+    assert rms2 < rms1 / 1.7
+    assert max2 < 0.06
