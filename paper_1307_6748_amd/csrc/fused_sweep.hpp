@@ -122,7 +122,10 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
     const size_t n2 = (size_t)n * n;
     const int tid = threadIdx.x;
 
-    auto slot = [&](int p) __attribute__((always_inline)) { return (p - sbeg) % G::NR; };
+    // Ring slot of plane s + d at step index J = (s - sbeg) mod NR: the loop
+    // below is unrolled over NR steps, so every slot is a compile-time
+    // constant and LDS addresses fold into the instructions' offsets.
+    auto slotc = [](int J, int d) constexpr { return ((J + d) % G::NR + G::NR) % G::NR; };
     auto stage_valid = [&](int p, int k) __attribute__((always_inline)) { return p >= sbeg + k && p <= send - k; };
     // Plane row r, column c of a plane in LDS.  Rows are stored colour-split
     // (even columns, then odd columns): the cells one stage updates have one
@@ -205,9 +208,10 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
         });
     };
 
-    auto deposit = [&](int s, const V (&regs)[G::LPT]) __attribute__((always_inline)) {
-        T* dst = ring + slot(s) * G::PLANE;
-        T* xd = xring + slot(s) * G::PLANE;
+    auto deposit = [&](auto slc, const V (&regs)[G::LPT]) __attribute__((always_inline)) {
+        constexpr int SL = decltype(slc)::value;
+        T* dst = ring + SL * G::PLANE;
+        T* xd = xring + SL * G::PLANE;
 #pragma unroll
         for (int q = 0; q < G::LPT; ++q) {
             if ((q + 1) * NT <= G::PAIRS || tid + q * NT < G::PAIRS) {
@@ -223,21 +227,24 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
         }
     };
 
-    // Stages of step s (parity S2 of s fixed at compile time).
-    auto stages = [&](auto s2c, int s, const T (&e)[NK][G::MAXI],
+    // Stages of step s (step index J = (s - sbeg) mod NR, fixed at compile
+    // time; its parity is that of s since sbeg is even).
+    auto stages = [&](auto jc, int s, const T (&e)[NK][G::MAXI],
                       const T (&sg)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
-        constexpr int S2 = decltype(s2c)::value;
+        constexpr int J = decltype(jc)::value;
+        constexpr int S2 = J & 1;
         static_for<0, NK>([&](auto kc) {
             constexpr int k = decltype(kc)::value + 1;
             constexpr int PB = (S2 + k) & 1;  // parity of plane s - k
+            constexpr int SC = slotc(J, -k), SP = slotc(J, -k - 1), SN = slotc(J, -k + 1);
             const int p = s - k;
             if (stage_valid(p, k)) {
-                T* cur = ring + slot(p) * G::PLANE;
-                const T* prv = ring + slot(p - 1) * G::PLANE;
-                const T* nxt = ring + slot(p + 1) * G::PLANE;
-                T* xcur = xring + slot(p) * G::PLANE;
-                const T* xprv = xring + slot(p - 1) * G::PLANE;
-                const T* xnxt = xring + slot(p + 1) * G::PLANE;
+                T* cur = ring + SC * G::PLANE;
+                const T* prv = ring + SP * G::PLANE;
+                const T* nxt = ring + SN * G::PLANE;
+                T* xcur = xring + SC * G::PLANE;
+                const T* xprv = xring + SP * G::PLANE;
+                const T* xnxt = xring + SN * G::PLANE;
                 static_for<0, G::ipt(k)>([&](auto qc) {
                     constexpr int q = decltype(qc)::value;
                     if ((q + 1) * NT <= G::items(k) || tid + q * NT < G::items(k)) {
@@ -278,10 +285,11 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
         });
     };
 
-    auto write_out = [&](int s) __attribute__((always_inline)) {
+    auto write_out = [&](auto jc, int s) __attribute__((always_inline)) {
+        constexpr int J = decltype(jc)::value;
         const int pw = s - NK;
         if (pw >= x0 && pw < x0 + xc) {
-            const T* src = ring + slot(pw) * G::PLANE;
+            const T* src = ring + slotc(J, -NK) * G::PLANE;
             T* dst = out + (size_t)(pw & msk) * n2;
 #pragma unroll
             for (int j = 0; j < WPT; ++j) {
@@ -299,10 +307,11 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
     // (which held plane s) receives plane s+2.  ec/sc hold this step's cell
     // data, en/sn receive the next step's (with LATE2, the black stage's
     // entries of ec/sc are consumed here and refilled for step s+2).
-    auto step = [&](auto s2c, int s, V (&spare)[G::LPT], const V (&ready)[G::LPT],
+    auto step = [&](auto jc, int s, V (&spare)[G::LPT], const V (&ready)[G::LPT],
                     T (&ec)[NK][G::MAXI], T (&sc)[SIG ? NK : 1][SIG ? G::MAXI : 1],
                     T (&en)[NK][G::MAXI], T (&sn)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
-        constexpr int S2 = decltype(s2c)::value;
+        constexpr int J = decltype(jc)::value;
+        constexpr int S2 = J & 1;
         // (past the chunk end these load wrapped, unused planes: branch-free)
         load_plane(s + 2, spare);
         // next step's stage k works on plane s + 1 - k
@@ -312,12 +321,12 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                 fetch_stage(std::integral_constant<int, k>{},
                             std::integral_constant<int, (S2 + 1 + k) & 1>{}, s + 1 - k, en, sn);
         });
-        stages(s2c, s, ec, sc);  // ends with a barrier: the slot of plane s+1-NR is free
-        if constexpr (LATE2)     // black stage of plane s, used at step s+2
+        stages(jc, s, ec, sc);  // ends with a barrier: the slot of plane s+1-NR is free
+        if constexpr (LATE2)    // black stage of plane s, used at step s+2
             fetch_stage(std::integral_constant<int, 2>{}, std::integral_constant<int, S2>{}, s,
                         ec, sc);
-        write_out(s);
-        if (s + 1 <= send) deposit(s + 1, ready);
+        write_out(jc, s);
+        if (s + 1 <= send) deposit(std::integral_constant<int, slotc(J, 1)>{}, ready);
         __syncthreads();
     };
 
@@ -336,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
         }
     load_plane(sbeg, pA);
     load_plane(sbeg + 1, pB);
-    deposit(sbeg, pA);
+    deposit(std::integral_constant<int, 0>{}, pA);
     static_for<0, NK>([&](auto kc) {
         constexpr int k = decltype(kc)::value + 1;
         if constexpr (!(LATE2 && k == 2))
@@ -344,9 +353,17 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
                         sbeg - k, eA, sA);
     });
     __syncthreads();
-    for (int s = sbeg; s <= send; s += 2) {
-        step(std::integral_constant<int, 0>{}, s, pA, pB, eA, sA, eB, sB);
-        if (s + 1 <= send) step(std::integral_constant<int, 1>{}, s + 1, pB, pA, eB, sB, eA, sA);
+    for (int s0 = sbeg; s0 <= send; s0 += G::NR) {
+        static_for<0, G::NR>([&](auto jc) {
+            constexpr int J = decltype(jc)::value;
+            const int s = s0 + J;
+            if (s <= send) {
+                if constexpr ((J & 1) == 0)
+                    step(jc, s, pA, pB, eA, sA, eB, sB);
+                else
+                    step(jc, s, pB, pA, eB, sB, eA, sA);
+            }
+        });
     }
 }
 
@@ -393,14 +410,10 @@ int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T*
     const int xc = fused_chunk(n);
     const int blocks = (n / TZ) * (n / TY) * (n / xc);
     auto kern = k_sweep_fused<T, M, TB, TY, TZ, NT, SIG>;
-    static bool attr_done = false;  // per instantiation
-    if (!attr_done) {
-        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                lds) != hipSuccess) {
-            snprintf(err, 512, "hipFuncSetAttribute(shared %d B) failed", lds);
-            return -4;
-        }
-        attr_done = true;
+    static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
+    if (ensure_dynamic_lds((const void*)kern, lds, lds_done) != hipSuccess) {
+        snprintf(err, 512, "hipFuncSetAttribute(shared %d B) failed", lds);
+        return -4;
     }
     T ih2 = (T)(1.0 / (h * h));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, s, m, n, xc, ih2, in, out, eta, sigma);

@@ -212,12 +212,8 @@ int launch_restrict_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* e
                           hipStream_t s, char* err)
 {
     auto kern = k_defect_restrict_tiled<T, M, SIG>;
-    static bool attr_done = false;  // per instantiation
-    if (!attr_done) {
-        HIP_TRY(err, hipFuncSetAttribute((const void*)kern,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        attr_done = true;
-    }
+    static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
+    HIP_TRY(err, ensure_dynamic_lds((const void*)kern, lds, lds_done));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), lds, s, m, nf, ih2f, phi_f, eta_f,
                        sigma_f, phi_c, phihat_c, rr_c);
     LAUNCH_CHECK(err, "k_defect_restrict_tiled");

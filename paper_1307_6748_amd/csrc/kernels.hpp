@@ -9,12 +9,29 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "model.hpp"
 
 namespace isis {
 
 constexpr int kBlock = 256;
 constexpr int kReduceBlocks = 8192;  // partial sums per reduction (fixed: deterministic)
+
+// Raises a kernel's dynamic LDS limit to `bytes` on the current device, once
+// per device (the attribute is per device); `done` is the kernel's bitmask of
+// devices already set up.
+inline hipError_t ensure_dynamic_lds(const void* kern, int bytes, std::atomic<unsigned>& done)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const unsigned bit = dev < 32 ? 1u << dev : 0u;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
+    return e;
+}
 
 // Native two-element vectors (16- or 8-byte loads and stores).  Clang's
 // ext_vector_type keeps them in registers; HIP's struct-based double2 is
