@@ -92,7 +92,8 @@ typedef struct {
     int precision;     /* isis_precision                                           */
     double fp32_floor; /* ISIS_MIXED: relative residual at which the FP32 phase
                           hands over to FP64 cycles (see isis_mg_solve); 0 (the
-                          default) means 3 tol; else in [1e-12, 1]              */
+                          default): once one more cycle at the last factor is
+                          expected to reach tol; else in [1e-12, 1]             */
     int temporal_block;/* 0: one HBM pass per red or black half-sweep;
                           1: one pass per full red-black sweep (fused);
                           2: two full sweeps per pass (temporal blocking)           */
@@ -153,9 +154,11 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
  * FP32 iterate on the finest level, while that residual falls by at least
  * 0.6x per cycle, no cycle's factor exceeds both 0.2 and 3x the previous
  * one's (the FP32 round-off floor coming into view: ~2e-7 relative for the
- * symmetron, below 1e-8 for f(R) on the 512^3 halo workload) and it is above
- * desc.fp32_floor (default 3 tol); then FP64 V-cycles from the promoted
- * iterate to tol.  The FP64 defect decides convergence in both phases.
+ * symmetron, below 1e-8 for f(R) on the 512^3 halo workload) and, by
+ * default, one more cycle at the last factor rho is not expected to reach tol
+ * (residual * rho > 0.7 tol; with desc.fp32_floor set: the residual is above
+ * that level); then FP64 V-cycles from the promoted iterate to tol, by default
+ * a single one.  The FP64 defect decides convergence in both phases.
  * Returns ISIS_OK, ISIS_ERR_NOT_CONVERGED (field = last iterate) or
  * ISIS_ERR_DIVERGED (field = last iterate, may be non-finite). */
 int isis_mg_solve(isis_mg_t* h, const double* density, double* field,

@@ -604,11 +604,15 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                            n3, field, H->L32[0].phi);
         LAUNCH_CHECK(H->err, "k_convert");
         H->L32[0].sigma = nullptr;
-        // Default hand-over at 3 tol: the last cycles run in FP64, so the answer
-        // carries FP64-cycle error (an FP32-only solve meeting the same tol is
-        // ~10% less accurate in phi for f(R)); an earlier stall of the FP32
-        // cycles at their round-off floor also hands over.
-        const double fp32_floor = d.fp32_floor > 0.0 ? d.fp32_floor : 3.0 * tol;
+        // The last cycle runs in FP64, so the answer carries FP64-cycle error
+        // (an FP32-only solve meeting the same tol is ~10% less accurate in phi
+        // for f(R)).  Default hand-over: as soon as one more cycle at the last
+        // factor is expected to reach tol (with a 0.7 margin), so that a single
+        // FP64 cycle finishes the solve; with desc.fp32_floor set, at that
+        // level instead.  An earlier stall of the FP32 cycles at their
+        // round-off floor also hands over.
+        const bool predict = !(d.fp32_floor > 0.0);
+        const double fp32_floor = predict ? 0.0 : d.fp32_floor;
         double rprev = r0, rho_prev = 1.0;
         while (cyc < d.max_cycles) {
             if ((r = vcycle<float, M32>(H, m32, H->L32, 0, &updates))) return r;
@@ -630,10 +634,11 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             // Refine in FP64 once the FP32 cycles reach their round-off floor:
             // a cycle reduces the residual by less than 0.6x, or its factor
             // jumps to more than 3x the previous cycle's (and above 0.2) as
-            // the floor comes into view; or at the caller's hand-over level.
+            // the floor comes into view; or once one more cycle is expected
+            // to finish (default), or at the caller's hand-over level.
             const double rho = rc / rprev;
             if (rc > 0.6 * rprev || (rho > 0.2 && rho > 3.0 * rho_prev) ||
-                rc <= fp32_floor * rnorm)
+                (predict ? rc * rho <= 0.7 * tol * rnorm : rc <= fp32_floor * rnorm))
                 break;
             rho_prev = rho;
             rprev = rc;
