@@ -2,7 +2,8 @@
 // stages) per pass over HBM, out of place (in -> out).
 //
 // Each workgroup owns a TY x TZ tile of the y-z plane and streams along x over
-// a chunk of XC planes.  Planes of phi (with a y/z halo of H = 2*TB cells)
+// one of NXC chunks of about n / NXC planes (chunk ends even; the host picks
+// NXC, see fused_chunks).  Planes of phi (with a y/z halo of H = 2*TB cells)
 // pass through a ring of NR = 2*TB + 2 planes in LDS.  At step s the
 // workgroup holds planes s-NR+1 .. s and applies, in this order,
 //   stage 1 (red)   to plane s-1,
@@ -86,7 +87,7 @@ __device__ __forceinline__ T& at_bytes(T* base, unsigned off)
 }
 
 template <class T, class M, int TB, int TY, int TZ, int NT, bool SIG>
-__global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
+__global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                                                     const T* __restrict__ in, T* __restrict__ out,
                                                     const T* __restrict__ eta,
                                                     const T* __restrict__ sigma)
@@ -114,10 +115,12 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
     const int zt = b % ntz;
     const int yt = (b / ntz) % nty;
     const int xt = b / (ntz * nty);
-    const int x0 = xt * xc, y0 = yt * TY, z0 = zt * TZ;
-    // xc and H are even, so sbeg is even: the unrolled steps below alternate
+    // chunk [x0, x1) with both ends even (n is even)
+    const int x0 = (xt * n / nxc) & ~1, x1 = ((xt + 1) * n / nxc) & ~1;
+    const int y0 = yt * TY, z0 = zt * TZ;
+    // x0 and H are even, so sbeg is even: the unrolled steps below alternate
     // even and odd planes, which fixes every parity at compile time.
-    const int sbeg = x0 - G::H, send = x0 + xc - 1 + G::H;
+    const int sbeg = x0 - G::H, send = x1 - 1 + G::H;
     const int msk = n - 1;
     const size_t n2 = (size_t)n * n;
     const int tid = threadIdx.x;
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int xc, T ih2,
     auto write_out = [&](auto jc, int s) __attribute__((always_inline)) {
         constexpr int J = decltype(jc)::value;
         const int pw = s - NK;
-        if (pw >= x0 && pw < x0 + xc) {
+        if (pw >= x0 && pw < x1) {
             const T* src = ring + slotc(J, -NK) * G::PLANE;
             T* dst = out + (size_t)(pw & msk) * n2;
 #pragma unroll
@@ -400,6 +403,19 @@ inline int fused_chunk(int n)
     return n >= 512 ? 64 : (n >= 256 ? 32 : 16);
 }
 
+// Chunks along x per tile column.  When the device holds a small whole number
+// (<= 4) of workgroups per tile column at once, one round of that many long
+// chunks: no partly filled last round and the least pipeline fill (measured
+// at 512^3: 3-5% faster for the kernels held 3 per CU).  Otherwise, or when
+// the occupancy is unknown (resident <= 0), fused_chunk() planes per chunk.
+inline int fused_chunks(int n, int tiles, int resident)
+{
+    if (resident > 0 && resident % tiles == 0 && resident / tiles <= 4 &&
+        resident / tiles <= n / 16)
+        return resident / tiles;
+    return n / fused_chunk(n);
+}
+
 template <class T, class M, int TB, bool SIG>
 int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T* eta,
                       const T* sigma, hipStream_t s, char* err)
@@ -407,16 +423,19 @@ int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T*
     using Tile = FusedTile<T, M, TB>;
     constexpr int TY = Tile::TY, TZ = Tile::TZ, NT = Tile::NT;
     constexpr int lds = fused_lds_bytes<T, M, TB, TY, TZ>();
-    const int xc = fused_chunk(n);
-    const int blocks = (n / TZ) * (n / TY) * (n / xc);
     auto kern = k_sweep_fused<T, M, TB, TY, TZ, NT, SIG>;
     static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
     if (ensure_dynamic_lds((const void*)kern, lds, lds_done) != hipSuccess) {
         snprintf(err, 512, "hipFuncSetAttribute(shared %d B) failed", lds);
         return -4;
     }
+    static std::atomic<int> resident[kMaxDevices];  // per instantiation and device
+    const int res = resident_blocks((const void*)kern, NT, lds, resident);
+    const int tiles = (n / TZ) * (n / TY);
+    const int nxc = fused_chunks(n, tiles, res);
+    const int blocks = tiles * nxc;
     T ih2 = (T)(1.0 / (h * h));
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, s, m, n, xc, ih2, in, out, eta, sigma);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, s, m, n, nxc, ih2, in, out, eta, sigma);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         snprintf(err, 512, "k_sweep_fused: %s", hipGetErrorString(e));

@@ -33,6 +33,34 @@ inline hipError_t ensure_dynamic_lds(const void* kern, int bytes, std::atomic<un
     return e;
 }
 
+// Workgroups of `kern` (nt threads, `lds` bytes of dynamic LDS) that the
+// current device holds at once: workgroups per CU times the CU count.  Cached
+// per device in cache[dev] (0 = not yet queried); 0 on failure, with the
+// runtime's last-error state cleared so that later launch checks are not
+// confused by it.
+constexpr int kMaxDevices = 64;
+inline int resident_blocks(const void* kern, int nt, int lds, std::atomic<int>* cache)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (dev < kMaxDevices) {
+        const int v = cache[dev].load(std::memory_order_acquire);
+        if (v > 0) return v;
+    }
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, (size_t)lds) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int v = per_cu * ncu;
+    if (dev < kMaxDevices && v > 0) cache[dev].store(v, std::memory_order_release);
+    return v;
+}
+
 // Native two-element vectors (16- or 8-byte loads and stores).  Clang's
 // ext_vector_type keeps them in registers; HIP's struct-based double2 is
 // copied with memcpy, which pins arrays of it to scratch memory.
