@@ -105,6 +105,11 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* ring = reinterpret_cast<T*>(smem_raw);  // NR planes of phi
     T* xring = ring + G::NR * G::PLANE;        // NR planes of e^phi (f(R) only)
+    __shared__ double exptab[SO::kTable ? kExpTable : 1];
+    if constexpr (SO::kTable) {
+        exp_table_fill(exptab);
+        __syncthreads();
+    }
 
     // XCD-aware tile order: ids are dealt round-robin to 8 XCDs; give each
     // XCD a contiguous range of tiles.
@@ -223,8 +228,8 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                 dst[oe] = regs[q].x;
                 dst[oo] = regs[q].y;
                 if constexpr (STAGED) {
-                    xd[oe] = SO::stage(regs[q].x);
-                    xd[oo] = SO::stage(regs[q].y);
+                    xd[oe] = SO::stage(regs[q].x, exptab);
+                    xd[oo] = SO::stage(regs[q].y, exptab);
                 }
             }
         }
@@ -279,7 +284,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                         const T nv = pc - eps * recip(D);
                         cur[o] = nv;
                         if constexpr (STAGED) {
-                            if (k < NK) xcur[o] = SO::stage(nv);
+                            if (k < NK) xcur[o] = SO::stage(nv, exptab);
                         }
                     }
                 });
@@ -300,7 +305,9 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                     V v;
                     v.x = src[wl[j]];
                     v.y = src[wl[j] + G::HZ];
-                    at_bytes(reinterpret_cast<V*>(dst), woff[j]) = v;
+                    // streaming store: keeps L2 for the halo rows that
+                    // neighbouring tiles still have to read
+                    __builtin_nontemporal_store(v, &at_bytes(reinterpret_cast<V*>(dst), woff[j]));
                 }
             }
         }

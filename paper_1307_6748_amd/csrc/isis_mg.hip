@@ -122,6 +122,7 @@ FofR<T> make_fofr(const isis_model_params& p, double a)
     m.a3 = a3;
     m.cL = cL;
     m.np1 = p.n + 1.0;
+    m.qc1n = m.Q * m.c1 * m.inv_np1;
     m.n_is_one = p.n == 1.0 ? 1 : 0;
     return m;
 }

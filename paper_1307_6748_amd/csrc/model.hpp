@@ -73,6 +73,41 @@ __device__ __forceinline__ float exp_fast(float x)
     return fmaf(r, err * kLn2, r);
 }
 
+// e^x in double precision by the table-driven method of P. T. P. Tang (ACM
+// TOMS 15 (1989) 144): x = (64 k + j) ln2/64 + r with |r| <= ln2/128, so
+// e^x = 2^k 2^(j/64) e^r, and e^r - 1 is its Taylor series through r^5 (the
+// first omitted term is below 4e-17).  ln2/64 is split in two so that r is
+// exact to ~1e-18.  tab[j] = 2^(j/64), j < 64 (exp_table_fill).  Outside
+// |x| <= 708 (never met by these fields) the result saturates branch-free:
+// +inf above, 0 below (e^x < 3.3e-308 there), NaN stays NaN.
+constexpr int kExpTable = 64;
+__device__ __forceinline__ double exp_tab(double x, const double* tab)
+{
+    constexpr double kInvStep = 92.33248261689366;         // 64 / ln 2
+    constexpr double kStepHi = 0x1.62e42fefa39efp-7;       // ln2/64 rounded
+    constexpr double kStepLo = 0x1.abc9e3b39803fp-62;      // ln2/64 - kStepHi
+    constexpr double kMax = 708.0;
+    const double xc = fmin(fmax(x, -kMax), kMax);
+    const double nd = rint(xc * kInvStep);
+    const int ni = (int)nd;
+    double r = fma(-nd, kStepHi, xc);
+    r = fma(-nd, kStepLo, r);
+    double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    q = fma(r, q, 1.0 / 6.0);
+    q = fma(r, q, 0.5);
+    q = fma(r, q, 1.0);
+    const double t = tab[ni & (kExpTable - 1)];
+    const double y = ldexp(fma(t, r * q, t), ni >> 6);  // ni >> 6 = floor(ni / 64)
+    return fabs(x) <= kMax ? y : (x > 0.0 ? __builtin_inf() : (x < 0.0 ? 0.0 : x));
+}
+
+// Fill tab[0..63] with 2^(j/64) (all threads of the block take part; the
+// caller synchronises before use).
+__device__ __forceinline__ void exp_table_fill(double* tab)
+{
+    for (int j = threadIdx.x; j < kExpTable; j += blockDim.x) tab[j] = exp2(j * (1.0 / kExpTable));
+}
+
 template <class T>
 __device__ __forceinline__ T exp_t(T x)
 {
@@ -82,15 +117,14 @@ __device__ __forceinline__ T exp_t(T x)
         return exp(x);
 }
 
-// 1/d for the Newton-Gauss-Seidel step: the hardware reciprocal refined by
-// Newton iterations (one in FP32, two in FP64).  Only the iteration uses it;
+// 1/d for the Newton-Gauss-Seidel step: the hardware reciprocal (FP32), or
+// the hardware estimate refined by two Newton iterations (FP64).  Only the iteration uses it;
 // its fixed point L = Sigma does not depend on how 1/D is rounded.
 template <class T>
 __device__ __forceinline__ T recip(T d)
 {
     if constexpr (sizeof(T) == 4) {
-        float r = __builtin_amdgcn_rcpf(d);
-        return fmaf(r, fmaf(-d, r, 1.0f), r);
+        return __builtin_amdgcn_rcpf(d);  // within 1 ulp
     } else {
         double r = __builtin_amdgcn_rcp(d);
         r = fma(r, fma(-d, r, 1.0), r);
@@ -108,6 +142,7 @@ template <class T>
 struct FofR {
     double Q, cLa3, c1, inv_np1;
     double a3, cL, np1;  // for the cold start
+    double qc1n;         // Q c1 / (n+1): dS/du = qc1n e^{-u/(n+1)}
     int n_is_one;        // n = 1: e^{-u/2} = 1/sqrt(e^u)
     // S(u) and dS/du at one cell, given e^u (ep)
     __device__ __forceinline__ void source(T p, T ep, T eta, T& S, T& dS) const
@@ -118,17 +153,18 @@ struct FofR {
             const float e = n_is_one ? __builtin_amdgcn_rsqf(fmaxf(ep, 1e-30f))
                                      : exp_fast(-p * float(inv_np1));
             if (e <= kFofRStiff) {
-                S = float(Q) * (eta + float(cLa3) - float(c1) * e);
-                dS = float(Q) * float(c1) * e * float(inv_np1);
+                // Q eta + Q cLa3 - Q c1 e: no cancellation to speak of here
+                S = fmaf(float(Q), eta, fmaf(-float(Q * c1), e, float(Q * cLa3)));
+                dS = float(qc1n) * e;
                 return;
             }
             const double ed = exp(-(double)p * inv_np1);
             S = (T)(Q * ((double)eta + cLa3 - c1 * ed));
-            dS = (T)(Q * c1 * ed * inv_np1);
+            dS = (T)(qc1n * ed);
         } else {
             const T e = n_is_one ? rsqrt(ep) : exp(-p * inv_np1);
             S = Q * (eta + cLa3 - c1 * e);
-            dS = Q * c1 * e * inv_np1;
+            dS = qc1n * e;
         }
     }
     // L and D from the cell value p, its e^p (ep) and the neighbours' values
@@ -139,21 +175,21 @@ struct FofR {
     __device__ __forceinline__ void op_staged(T p, const T nb[6], T ep, const T enb[6], T eta,
                                               T ih2, T& L, T& D) const
     {
-        T sd = T(0), sed = T(0), se = T(0);
+        T sd = nb[0] - p;
+        T sed = enb[0] * sd, se = enb[0];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
+        for (int f = 1; f < 6; ++f) {
             const T d = nb[f] - p;
             sd += d;
             sed += enb[f] * d;
             se += enb[f];
         }
         const T esd = ep * sd;
-        const T flux = T(0.5) * (esd + sed);
-        const T dflux = T(0.5) * (esd - T(6) * ep - se);
+        const T hih2 = T(0.5) * ih2;  // the 1/2 of b_f, exactly
         T S, dS;
         source(p, ep, eta, S, dS);
-        L = flux * ih2 - S;
-        D = dflux * ih2 - dS;
+        L = (esd + sed) * hih2 - S;
+        D = (esd - T(6) * ep - se) * hih2 - dS;
     }
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
@@ -187,10 +223,13 @@ struct Linear {
 // Per-model form of the operator for kernels that share per-cell work between
 // neighbouring stencils.  Staged models (f(R)) take a per-cell quantity
 // computed once, stage(phi) = e^phi, next to each value; others ignore it.
+// Kernels that stage in double precision hold the exp_tab table in LDS
+// (kTable) and pass it to stage().
 template <class T, class M>
 struct StageOp {
-    static constexpr bool kStaged = false;
+    static constexpr bool kStaged = false, kTable = false;
     __device__ __forceinline__ static T stage(T) { return T(0); }
+    __device__ __forceinline__ static T stage(T, const double*) { return T(0); }
     __device__ __forceinline__ static void eval(const M& m, T p, const T nb[6], T, const T*,
                                                 T eta, T ih2, T& L, T& D)
     {
@@ -200,8 +239,15 @@ struct StageOp {
 
 template <class T>
 struct StageOp<T, FofR<T>> {
-    static constexpr bool kStaged = true;
+    static constexpr bool kStaged = true, kTable = sizeof(T) == 8;
     __device__ __forceinline__ static T stage(T x) { return exp_t(x); }
+    __device__ __forceinline__ static T stage(T x, const double* tab)
+    {
+        if constexpr (sizeof(T) == 8)
+            return exp_tab(x, tab);
+        else
+            return exp_fast(x);
+    }
     __device__ __forceinline__ static void eval(const FofR<T>& m, T p, const T nb[6], T ep,
                                                 const T enb[6], T eta, T ih2, T& L, T& D)
     {

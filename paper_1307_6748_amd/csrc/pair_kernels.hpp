@@ -219,6 +219,11 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* ring = reinterpret_cast<T*>(smem_raw);  // 4 fine planes of phi
     T* xring = ring + 4 * G::PLANE;            // 4 planes of e^phi (staged models)
+    __shared__ double exptab[SO::kTable ? kExpTable : 1];
+    if constexpr (SO::kTable) {
+        exp_table_fill(exptab);
+        __syncthreads();
+    }
     const int nc = nf >> 1;
     const int msk = nf - 1;
     const size_t nf2 = (size_t)nf * nf;
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
                 *reinterpret_cast<V*>(d + doff[q]) = regs[q];
                 if constexpr (STAGED)
                     *reinterpret_cast<V*>(e + doff[q]) =
-                        V{SO::stage(regs[q].x), SO::stage(regs[q].y)};
+                        V{SO::stage(regs[q].x, exptab), SO::stage(regs[q].y, exptab)};
             }
         }
     };
@@ -456,7 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tiled(int nf, T* __restrict_
                 }
                 const long o = ((long)(2 * I + di) * nf + (2 * (J0 + jj) + dj)) * nf +
                                2 * (K0 + kk);
-                *reinterpret_cast<V*>(fine + o) = f[di][dj];
+                // streamed out: nothing reads it again before it leaves L2
+                __builtin_nontemporal_store(f[di][dj], reinterpret_cast<V*>(fine + o));
             }
         __syncthreads();  // the slot of plane I-1 is refilled next
     }
@@ -548,6 +554,11 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
     constexpr bool STAGED = SO::kStaged;
     __shared__ __align__(16) double ring[3][G::PLANE];
     __shared__ __align__(16) double xring[STAGED ? 3 : 1][STAGED ? G::PLANE : 2];
+    __shared__ double exptab[SO::kTable ? kExpTable : 1];
+    if constexpr (SO::kTable) {
+        exp_table_fill(exptab);
+        __syncthreads();
+    }
     const int tid = threadIdx.x;
     const int msk = n - 1;
     const int ntz = n / G::TZ, nty = n / G::TY, ntx = n / G::XC;
@@ -598,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
                     *reinterpret_cast<VD*>(d + 2 * k) = VD{a, b};
                     if constexpr (STAGED) {
                         double* e = xring[(x - x0 + 3) % 3];
-                        *reinterpret_cast<VD*>(e + 2 * k) = VD{SO::stage(a), SO::stage(b)};
+                        *reinterpret_cast<VD*>(e + 2 * k) = VD{SO::stage(a, exptab), SO::stage(b, exptab)};
                     }
                 }
             }
