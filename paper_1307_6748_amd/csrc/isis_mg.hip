@@ -420,7 +420,8 @@ bool valid_desc(const isis_mg_desc* d, char* err)
 
 // sqrt(mean(L_0(phi)^2)) of the finest level, in double; res may be NULL.
 template <class TF, class M>
-int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* res, double* out)
+int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* res, double* out,
+             double uscale = 1.0)
 {
     const int n = H->d.N;
     const long n3 = (long)n * n * n;
@@ -432,11 +433,11 @@ int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* r
         const long tiles = (long)(n / NG::TZ) * (n / NG::TY) * (n / NG::XC);
         g = (int)std::min<long>(kReduceBlocks, tiles);
         hipLaunchKernelGGL((k_defect_norm_tiled<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
-                           1.0 / (h * h), phi, eta, res, H->partial);
+                           1.0 / (h * h), uscale, phi, eta, res, H->partial);
     }
     if (!tiled)
         hipLaunchKernelGGL((k_defect_norm_pairs<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
-                           1.0 / (h * h), phi, eta, res, H->partial);
+                           1.0 / (h * h), uscale, phi, eta, res, H->partial);
     LAUNCH_CHECK(H->err, "k_defect_norm");
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
     LAUNCH_CHECK(H->err, "k_reduce");
@@ -598,11 +599,12 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         for (int l = 0; l < H->nlev; ++l) {
             long c3 = (long)H->L32[l].n * H->L32[l].n * H->L32[l].n;
             hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(c3)), dim3(kBlock), 0,
-                               H->s, c3, H->L64[l].eta, H->L32[l].eta);
+                               H->s, c3, H->L64[l].eta, H->L32[l].eta, 1.0);
             LAUNCH_CHECK(H->err, "k_convert");
         }
+        // the FP32 models may carry a scaled variable (f(R): u / ln 2)
         hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                           n3, field, H->L32[0].phi);
+                           n3, field, H->L32[0].phi, M32::kVar);
         LAUNCH_CHECK(H->err, "k_convert");
         H->L32[0].sigma = nullptr;
         // The last cycle runs in FP64, so the answer carries FP64-cycle error
@@ -621,7 +623,9 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             ++cyc;
             ++cyc32;
             double rc;
-            if ((r = fine_rms<float, M64>(H, m64, H->L32[0].phi, density, nullptr, &rc))) return r;
+            if ((r = fine_rms<float, M64>(H, m64, H->L32[0].phi, density, nullptr, &rc,
+                                          M32::kVarInv)))
+                return r;
             if (st) st->rel_hist[cyc] = rc / rnorm;
             rcur = rc;
             if (!std::isfinite(rc) || rc > 1e3 * r0) {
@@ -645,7 +649,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             rprev = rc;
         }
         hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                           n3, H->L32[0].phi, F.phi);
+                           n3, H->L32[0].phi, F.phi, M32::kVarInv);
         LAUNCH_CHECK(H->err, "k_convert");
     }
 

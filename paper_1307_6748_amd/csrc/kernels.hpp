@@ -415,11 +415,11 @@ __global__ __launch_bounds__(kBlock) void k_cold_start(M m, long total,
 
 template <class TO, class TI>
 __global__ __launch_bounds__(kBlock) void k_convert(long total, const TI* __restrict__ in,
-                                                    TO* __restrict__ out)
+                                                    TO* __restrict__ out, double scale)
 {
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < total;
          c += (long)gridDim.x * blockDim.x)
-        out[c] = (TO)in[c];
+        out[c] = (TO)((double)in[c] * scale);
 }
 
 }  // namespace isis

@@ -33,6 +33,7 @@ __device__ __forceinline__ T lap7(T p, const T nb[6], T ih2)
 // this changes only the iteration, not the root.
 template <class T>
 struct Symmetron {
+    static constexpr double kVar = 1.0, kVarInv = 1.0;  // stored value = phi
     T K, A;
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
@@ -56,21 +57,19 @@ struct Symmetron {
 //   cLa3 = cL a^3, c1 = a^3 (1 + cL), cL = 4 Omega_L/Omega_m.
 // Jacobian (Sec. 3.4, eq. dbeq, with the exact factor 1/2 on db/du):
 //   (1/h^2) sum_f [ e^u (u_nb - u)/2 - b_f ] - dS/du.
-// e^x in single precision from the hardware base-2 exponential: with
-// t = fl(x log2 e), the rounding error of t is recovered exactly by an FMA
-// (plus the error of log2 e itself), and 2^(x log2 e) = 2^t (1 + err ln 2) to
-// first order, within about two ulp for |x| < 87 (no overflow handling: the
+constexpr double kLn2 = 0.6931471805599453;    // ln 2
+constexpr double kLog2e = 1.4426950408889634;  // 1 / ln 2
+
+// 2^(x c) in single precision from the hardware base-2 exponential: the
+// rounding error of t = fl(x c) is recovered exactly by an FMA, and
+// 2^(x c) = 2^t (1 + err ln 2) to first order (no overflow handling: the
 // fields here stay far from it).
-__device__ __forceinline__ float exp_fast(float x)
+__device__ __forceinline__ float exp2_scaled(float x, float c)
 {
-    constexpr float kLog2e = 1.44269502f;        // log2(e) rounded to float
-    constexpr float kLog2eLo = 1.92596299e-8f;   // log2(e) - kLog2e
-    constexpr float kLn2 = 0.693147182f;
-    const float t = x * kLog2e;
-    float err = fmaf(x, kLog2e, -t);
-    err = fmaf(x, kLog2eLo, err);
+    const float t = x * c;
+    const float err = fmaf(x, c, -t);
     const float r = __builtin_amdgcn_exp2f(t);
-    return fmaf(r, err * kLn2, r);
+    return fmaf(r, err * float(kLn2), r);
 }
 
 // e^x in double precision by the table-driven method of P. T. P. Tang (ACM
@@ -108,15 +107,6 @@ __device__ __forceinline__ void exp_table_fill(double* tab)
     for (int j = threadIdx.x; j < kExpTable; j += blockDim.x) tab[j] = exp2(j * (1.0 / kExpTable));
 }
 
-template <class T>
-__device__ __forceinline__ T exp_t(T x)
-{
-    if constexpr (sizeof(T) == 4)
-        return exp_fast(x);
-    else
-        return exp(x);
-}
-
 // 1/d for the Newton-Gauss-Seidel step: the hardware reciprocal (FP32), or
 // the hardware estimate refined by two Newton iterations (FP64).  Only the iteration uses it;
 // its fixed point L = Sigma does not depend on how 1/D is rounded.
@@ -138,27 +128,44 @@ __device__ __forceinline__ T recip(T d)
 // evaluates the source in FP64; elsewhere in FP32.
 constexpr float kFofRStiff = 8.0f;  // e^{-u/(n+1)} above which the source is stiff
 
+//
+// In single precision the field is carried as w = u / ln 2 (kVar converts):
+// then e^u = 2^w is one hardware exponential, exact to its own rounding,
+// with no rounding of a scaled argument to correct.  The operator below
+// evaluates the same residual L(u) from w, and the Newton denominator is
+// dL/dw = ln2 dL/du.
 template <class T>
 struct FofR {
+    static constexpr bool kW = sizeof(T) == 4;    // carried as w = u / ln 2
+    static constexpr double kVar = kW ? kLog2e : 1.0;     // stored value = u * kVar
+    static constexpr double kVarInv = kW ? kLn2 : 1.0;    // u = stored value * kVarInv
     double Q, cLa3, c1, inv_np1;
     double a3, cL, np1;  // for the cold start
     double qc1n;         // Q c1 / (n+1): dS/du = qc1n e^{-u/(n+1)}
     int n_is_one;        // n = 1: e^{-u/2} = 1/sqrt(e^u)
-    // S(u) and dS/du at one cell, given e^u (ep)
+    // e^u from the stored value (2^w in single precision)
+    __device__ __forceinline__ static T expv(T p)
+    {
+        if constexpr (kW)
+            return __builtin_amdgcn_exp2f(p);
+        else
+            return exp(p);
+    }
+    // S(u) and dS/du at one cell, given the stored value p and e^u (ep)
     __device__ __forceinline__ void source(T p, T ep, T eta, T& S, T& dS) const
     {
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (kW) {
             // (e^u >= 1e-30 for any field these solves meet; the bound only
             // keeps the reciprocal square root finite)
             const float e = n_is_one ? __builtin_amdgcn_rsqf(fmaxf(ep, 1e-30f))
-                                     : exp_fast(-p * float(inv_np1));
+                                     : exp2_scaled(-p, float(inv_np1));
             if (e <= kFofRStiff) {
                 // Q eta + Q cLa3 - Q c1 e: no cancellation to speak of here
                 S = fmaf(float(Q), eta, fmaf(-float(Q * c1), e, float(Q * cLa3)));
                 dS = float(qc1n) * e;
                 return;
             }
-            const double ed = exp(-(double)p * inv_np1);
+            const double ed = exp2(-(double)p * inv_np1);
             S = (T)(Q * ((double)eta + cLa3 - c1 * ed));
             dS = (T)(qc1n * ed);
         } else {
@@ -188,20 +195,27 @@ struct FofR {
         const T hih2 = T(0.5) * ih2;  // the 1/2 of b_f, exactly
         T S, dS;
         source(p, ep, eta, S, dS);
-        L = (esd + sed) * hih2 - S;
-        D = (esd - T(6) * ep - se) * hih2 - dS;
+        if constexpr (kW) {
+            // differences are in w: u_f - u = ln2 (w_f - w)
+            constexpr float l2 = float(kLn2);
+            L = (esd + sed) * (hih2 * l2) - S;
+            D = l2 * ((l2 * esd - T(6) * ep - se) * hih2 - dS);
+        } else {
+            L = (esd + sed) * hih2 - S;
+            D = (esd - T(6) * ep - se) * hih2 - dS;
+        }
     }
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
         T enb[6];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) enb[f] = exp_t(nb[f]);
-        op_staged(p, nb, exp_t(p), enb, eta, ih2, L, D);
+        for (int f = 0; f < 6; ++f) enb[f] = expv(nb[f]);
+        op_staged(p, nb, expv(p), enb, eta, ih2, L, D);
     }
     __device__ __forceinline__ T cold(T eta) const
     {
         // u = -(n+1) ln[(eta/a^3 + cL)/(1 + cL)]
-        return (T)(-np1 * log(((double)eta / a3 + cL) / (1.0 + cL)));
+        return (T)(-np1 * log(((double)eta / a3 + cL) / (1.0 + cL)) * kVar);
     }
 };
 
@@ -209,6 +223,7 @@ struct FofR {
 //   lap phi = m2 phi + kappa (eta - 1),  Jacobian -6/h^2 - m2.
 template <class T>
 struct Linear {
+    static constexpr double kVar = 1.0, kVarInv = 1.0;  // stored value = phi
     T kappa, m2;
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
@@ -240,13 +255,13 @@ struct StageOp {
 template <class T>
 struct StageOp<T, FofR<T>> {
     static constexpr bool kStaged = true, kTable = sizeof(T) == 8;
-    __device__ __forceinline__ static T stage(T x) { return exp_t(x); }
+    __device__ __forceinline__ static T stage(T x) { return FofR<T>::expv(x); }
     __device__ __forceinline__ static T stage(T x, const double* tab)
     {
         if constexpr (sizeof(T) == 8)
             return exp_tab(x, tab);
         else
-            return exp_fast(x);
+            return FofR<T>::expv(x);
     }
     __device__ __forceinline__ static void eval(const FofR<T>& m, T p, const T nb[6], T ep,
                                                 const T enb[6], T eta, T ih2, T& L, T& D)
