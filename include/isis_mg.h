@@ -60,7 +60,14 @@ typedef enum {
     ISIS_ERR_UNSUPPORTED = -5   /* option not available for this model / size       */
 } isis_status;
 
-typedef enum { ISIS_SYMMETRON = 0, ISIS_FR_HS = 1, ISIS_LINEAR = 2 } isis_model;
+/* ISIS_CHAMELEON: the chameleon equation of Sec. 6,
+ * lap phi = beta rho / M_pl - M^{4+n} / phi^{1+n}, with the source in code
+ * units as lap phi = cham_alpha eta - cham_mu phi^{-(1+n)} (n = cham_n).  Its
+ * field is psi = ln phi (phi = e^psi > 0), the field redefinition Sec. 4.2
+ * uses for f(R): lap e^psi = div(e^psi grad psi) is discretised in the
+ * non-canonical form of Sec. 3.4 with b = e^psi, and
+ * S(psi) = cham_alpha eta - cham_mu e^{-(1+n) psi}.  Needs eta > 0. */
+typedef enum { ISIS_SYMMETRON = 0, ISIS_FR_HS = 1, ISIS_LINEAR = 2, ISIS_CHAMELEON = 3 } isis_model;
 
 typedef enum {
     ISIS_FP64 = 0,  /* every step in double precision                               */
@@ -80,6 +87,13 @@ typedef struct {
     double kappa;     /* LINEAR: source coefficient                                */
     double m2;        /* LINEAR: mass term (>= 0; 0 = singular Poisson, needs a
                          zero-mean source; the mean of phi is then removed)        */
+    double cham_alpha;/* CHAMELEON: density coefficient (> 0)                      */
+    double cham_mu;   /* CHAMELEON: potential coefficient (> 0)                    */
+    double cham_n;    /* CHAMELEON: exponent n (> -1)                              */
+    int paper_u;      /* f(R): 0 = field u = ln(f_R/f_R0); 1 = the paper's own
+                         variable u = ln(a^2 |f_R|) (Sec. 4.2, f_R = -a^-2 e^u),
+                         with the equation as the paper writes it (its residual is
+                         a^2 |f_R0| times the other form's).  Other models: 0.    */
 } isis_model_params;
 
 typedef struct {

@@ -44,6 +44,18 @@
  *   R10 Symmetron Newton denominator is safeguarded as -6/h^2 - |dS/dphi|.
  *   R11 LINEAR with m2 = 0 is singular; its mean is removed after each cycle.
  *   R12 Forces on the grid use second-order central differences, periodic.
+ *   R13 The chameleon (Sec. 6: lap phi = beta rho / M_pl - M^{4+n} / phi^{1+n}),
+ *       with the free source written in code units as
+ *       lap phi = alpha eta - mu phi^{-(1+n)}, is solved for psi = ln phi, the
+ *       field redefinition of Sec. 4.2: lap e^psi = div(e^psi grad psi), so
+ *       the non-canonical discretisation of Sec. 3.4 applies with b = e^psi,
+ *       and S = alpha eta - mu e^{-(1+n) psi}.  phi = e^psi > 0 throughout.
+ *   R14 f(R) in the paper's own variable (Sec. 4.2, f_R = -a^-2 e^u) uses
+ *       the right-hand side exactly as the paper prints it.
+ *   R15 A chameleon Gauss-Seidel step is bounded to |d psi| <= 2.  Where psi
+ *       sits far above its local root, dS/dpsi is exponentially small and a
+ *       full Newton step overshoots until e^{-(1+n) psi} overflows.  The bound
+ *       changes the iteration only, not its fixed point.
  *
  * Built with -O2 -ffp-contract=off (no fused multiply-add, no fast-math).
  * OpenMP parallelises loops whose iterations are independent (one colour of
@@ -60,6 +72,10 @@
 #define ORC_SYMMETRON 0
 #define ORC_FR_HS 1
 #define ORC_LINEAR 2
+#define ORC_CHAMELEON 3
+
+/* Bound on one chameleon Gauss-Seidel step in psi (reading R15). */
+#define ORC_CHAM_MAX_STEP 2.0
 
 #define ORC_OK 0
 #define ORC_INVALID (-1)
@@ -83,6 +99,10 @@ typedef struct {
     double kappa;   /* LINEAR: S = m2 phi + kappa (eta - 1)                  */
     double m2;
     double beta;    /* symmetron coupling (enters the fifth force only)      */
+    double cham_alpha; /* CHAMELEON: S = alpha eta - mu phi^{-(1+n)}          */
+    double cham_mu;
+    double cham_n;     /* exponent n (> -1)                                   */
+    int paper_u;       /* FR_HS: field in the paper's u = ln(a^2 |f_R|)       */
 } orc_model;
 
 typedef struct {
@@ -126,6 +146,31 @@ static void src_fr(const orc_model* m, double u, double eta, double* S, double* 
     *dS = Q * a3 * (1.0 + cL) * e / (m->n + 1.0);
 }
 
+/* Hu-Sawicki f(R) in the paper's own variable u, f_R = -a^-2 e^u (reading
+ * R14): the right-hand side of the non-canonical equation of Sec. 4.2 term
+ * by term,
+ *   Omega_m a H0^2 (eta - 1)
+ *   - Omega_m a^4 H0^2 (1 + 4 Omega_L/Omega_m) (|f_R0| a^2)^{1/(n+1)} e^{-u/(n+1)}
+ *   + Omega_m a H0^2 (1 + 4 a^3 Omega_L/Omega_m). */
+static void src_fr_paper(const orc_model* m, double u, double eta, double* S, double* dS)
+{
+    double a = m->a, H2 = ORC_H0 * ORC_H0, om = m->omega_m;
+    double g = 1.0 + 4.0 * m->omega_l / om;
+    double c = pow(m->fR0_abs * a * a, 1.0 / (m->n + 1.0));
+    double e = exp(-u / (m->n + 1.0));
+    *S = om * a * H2 * (eta - 1.0) - om * a * a * a * a * H2 * g * c * e +
+         om * a * H2 * (1.0 + 4.0 * a * a * a * m->omega_l / om);
+    *dS = om * a * a * a * a * H2 * g * c * e / (m->n + 1.0);
+}
+
+/* Chameleon (reading R13) in psi = ln phi: S = alpha eta - mu e^{-(1+n) psi}. */
+static void src_cham(const orc_model* m, double psi, double eta, double* S, double* dS)
+{
+    double e = exp(-(1.0 + m->cham_n) * psi);
+    *S = m->cham_alpha * eta - m->cham_mu * e;
+    *dS = (1.0 + m->cham_n) * m->cham_mu * e;
+}
+
 /* LINEAR test model (the Poisson problem of Sec. 3.1 plus a mass term). */
 static void src_linear(const orc_model* m, double phi, double eta, double* S, double* dS)
 {
@@ -137,8 +182,12 @@ void orc_source(const orc_model* m, double phi, double eta, double* S, double* d
 {
     if (m->model == ORC_SYMMETRON)
         src_symmetron(m, phi, eta, S, dS);
+    else if (m->model == ORC_FR_HS && m->paper_u)
+        src_fr_paper(m, phi, eta, S, dS);
     else if (m->model == ORC_FR_HS)
         src_fr(m, phi, eta, S, dS);
+    else if (m->model == ORC_CHAMELEON)
+        src_cham(m, phi, eta, S, dS);
     else
         src_linear(m, phi, eta, S, dS);
 }
@@ -174,7 +223,7 @@ static double op_cell(const orc_model* m, long n, double h, const double* phi, c
     double S, dS;
     orc_source(m, p, eta[c], &S, &dS);
 
-    if (m->model == ORC_FR_HS) {
+    if (m->model == ORC_FR_HS || m->model == ORC_CHAMELEON) {
         /* Sec. 3.4: sum over faces of b_f (u_nb - u), b_f = (b(u) + b(u_nb))/2,
          * b = e^u; Jacobian: sum over faces of [ (db/du)/2 (u_nb - u) - b_f ]
          * (readings R3, R4), minus dS/du. */
@@ -247,7 +296,10 @@ void orc_halfsweep(const orc_model* m, int n, double h, double* phi, const doubl
                 double D;
                 double L = op_cell(m, nn, h, phi, eta, i, j, k, &D);
                 double eps = L - (sigma ? sigma[c] : 0.0);
-                phi[c] = phi[c] - eps / D;
+                double step = eps / D;
+                if (m->model == ORC_CHAMELEON) /* reading R15 */
+                    step = fmax(-ORC_CHAM_MAX_STEP, fmin(ORC_CHAM_MAX_STEP, step));
+                phi[c] = phi[c] - step;
             }
 }
 
@@ -315,7 +367,9 @@ void orc_prolong_correct(int n_fine, double* fine, const double* coarse, const d
 
 /* Pointwise homogeneous root, the field for which S(phi, eta) = 0 in every
  * cell (reading R9): symmetron chi = sqrt(max(0, 1 - (a_ssb/a)^3 eta));
- * f(R) u = -(n+1) ln[(eta a^-3 + cL)/(1 + cL)]; LINEAR phi = 0. */
+ * f(R) u = -(n+1) ln[(eta a^-3 + cL)/(1 + cL)], plus ln(a^2 |f_R0|) in the
+ * paper's variable; chameleon psi = ln(mu / (alpha eta)) / (1+n) (eta > 0);
+ * LINEAR phi = 0. */
 void orc_cold_start(const orc_model* m, long ncell, const double* eta, double* phi)
 {
 #pragma omp parallel for schedule(static)
@@ -328,6 +382,9 @@ void orc_cold_start(const orc_model* m, long ncell, const double* eta, double* p
             double cL = 4.0 * m->omega_l / m->omega_m;
             double a3 = m->a * m->a * m->a;
             phi[c] = -(m->n + 1.0) * log((eta[c] / a3 + cL) / (1.0 + cL));
+            if (m->paper_u) phi[c] += log(m->a * m->a * m->fR0_abs);
+        } else if (m->model == ORC_CHAMELEON) {
+            phi[c] = log(m->cham_mu / (m->cham_alpha * eta[c])) / (1.0 + m->cham_n);
         } else {
             phi[c] = 0.0;
         }
@@ -422,6 +479,9 @@ static int valid_model(const orc_model* m)
     if (m->model == ORC_FR_HS)
         return m->n > 0.0 && m->fR0_abs > 0.0 && m->omega_m > 0.0 && m->omega_l >= 0.0;
     if (m->model == ORC_LINEAR) return isfinite(m->kappa) && m->m2 >= 0.0;
+    if (m->model == ORC_CHAMELEON)
+        return m->cham_alpha > 0.0 && isfinite(m->cham_alpha) && m->cham_mu > 0.0 &&
+               isfinite(m->cham_mu) && m->cham_n > -1.0 && isfinite(m->cham_n);
     return 0;
 }
 
@@ -592,7 +652,9 @@ void orc_force(const orc_model* m, int n, double h, const double* field, const d
                                             (m->a_ssb * m->a_ssb * m->a_ssb);
                         acc -= coef * chit * gchit;
                     } else if (m->model == ORC_FR_HS) {
-                        const double eup = m->a * m->a * m->fR0_abs * exp(field[c]);
+                        /* e^u of the paper's variable (Sec. 4.2 geodesic equation) */
+                        const double eup = m->paper_u ? exp(field[c])
+                                                      : m->a * m->a * m->fR0_abs * exp(field[c]);
                         acc -= 0.5 * eup * cdiff(N, h, field, i, j, k, ax);
                     }
                     out[ax][c] = acc;

@@ -28,7 +28,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # mistakes in a copy of the source) can be loaded by setting ORACLE_LIB.
 _LIB_OVERRIDE = os.environ.get("ORACLE_LIB")
 
-SYMMETRON, FR_HS, LINEAR = 0, 1, 2
+SYMMETRON, FR_HS, LINEAR, CHAMELEON = 0, 1, 2, 3
 OK, INVALID, NOT_CONVERGED, DIVERGED = 0, -1, -2, -3
 MAX_HIST = 256
 
@@ -48,7 +48,8 @@ class _Model(C.Structure):
     _fields_ = [("model", C.c_int), ("a", C.c_double), ("lambda0", C.c_double),
                 ("a_ssb", C.c_double), ("n", C.c_double), ("fR0_abs", C.c_double),
                 ("omega_m", C.c_double), ("omega_l", C.c_double), ("kappa", C.c_double),
-                ("m2", C.c_double), ("beta", C.c_double)]
+                ("m2", C.c_double), ("beta", C.c_double), ("cham_alpha", C.c_double),
+                ("cham_mu", C.c_double), ("cham_n", C.c_double), ("paper_u", C.c_int)]
 
 
 class _Cfg(C.Structure):
@@ -75,10 +76,15 @@ class Model:
     kappa: float = 1.0
     m2: float = 0.0
     beta: float = 1.0
+    cham_alpha: float = 1.0  # chameleon: lap phi = alpha eta - mu phi^-(1+n), phi = e^psi
+    cham_mu: float = 1.0
+    cham_n: float = 1.0
+    paper_u: bool = False    # f(R): field in the paper's u = ln(a^2 |f_R|)
 
     def _c(self) -> _Model:
         return _Model(int(self.model), self.a, self.lambda0, self.a_ssb, self.n, self.fR0_abs,
-                      self.omega_m, self.omega_l, self.kappa, self.m2, self.beta)
+                      self.omega_m, self.omega_l, self.kappa, self.m2, self.beta,
+                      self.cham_alpha, self.cham_mu, self.cham_n, int(bool(self.paper_u)))
 
 
 @dataclass

@@ -14,7 +14,7 @@ ISIS_ERR_DIVERGED = -3
 ISIS_ERR_HIP = -4
 ISIS_ERR_UNSUPPORTED = -5
 
-ISIS_SYMMETRON, ISIS_FR_HS, ISIS_LINEAR = 0, 1, 2
+ISIS_SYMMETRON, ISIS_FR_HS, ISIS_LINEAR, ISIS_CHAMELEON = 0, 1, 2, 3
 ISIS_FP64, ISIS_MIXED = 0, 1
 MAX_HIST = 128
 
@@ -23,7 +23,8 @@ class ModelParamsC(C.Structure):
     _fields_ = [("model", C.c_int), ("lambda0", C.c_double), ("a_ssb", C.c_double),
                 ("beta", C.c_double), ("n", C.c_double), ("fR0_abs", C.c_double),
                 ("omega_m", C.c_double), ("omega_l", C.c_double), ("kappa", C.c_double),
-                ("m2", C.c_double)]
+                ("m2", C.c_double), ("cham_alpha", C.c_double), ("cham_mu", C.c_double),
+                ("cham_n", C.c_double), ("paper_u", C.c_int)]
 
 
 class DescC(C.Structure):

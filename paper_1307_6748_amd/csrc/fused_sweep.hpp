@@ -281,7 +281,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                         }
                         T eps = L;
                         if constexpr (SIG) eps -= sg[k - 1][q];
-                        const T nv = pc - eps * recip(D);
+                        const T nv = pc - m.limit(eps * recip(D));
                         cur[o] = nv;
                         if constexpr (STAGED) {
                             if (k < NK) xcur[o] = SO::stage(nv, exptab);

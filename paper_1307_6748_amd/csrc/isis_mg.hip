@@ -80,24 +80,36 @@ bool valid_params(const isis_model_params* p, double a, char* err)
             fmt_err(err, "symmetron needs lambda0 > 0 and a_ssb > 0");
             return false;
         }
-        return true;
+        break;
     case ISIS_FR_HS:
         if (!finite_pos(p->n) || !finite_pos(p->fR0_abs) || !finite_pos(p->omega_m) ||
             !std::isfinite(p->omega_l) || p->omega_l < 0.0) {
             fmt_err(err, "f(R) needs n > 0, |fR0| > 0, Omega_m > 0, Omega_L >= 0");
             return false;
         }
-        return true;
+        break;
     case ISIS_LINEAR:
         if (!std::isfinite(p->kappa) || !std::isfinite(p->m2) || p->m2 < 0.0) {
             fmt_err(err, "linear model needs finite kappa and m2 >= 0");
             return false;
         }
-        return true;
+        break;
+    case ISIS_CHAMELEON:
+        if (!finite_pos(p->cham_alpha) || !finite_pos(p->cham_mu) || !std::isfinite(p->cham_n) ||
+            !(p->cham_n > -1.0)) {
+            fmt_err(err, "chameleon needs alpha > 0, mu > 0 and n > -1");
+            return false;
+        }
+        break;
     default:
         fmt_err(err, "unknown model %d", p->model);
         return false;
     }
+    if (!(p->paper_u == 0 || (p->paper_u == 1 && p->model == ISIS_FR_HS))) {
+        fmt_err(err, "paper_u must be 0, or 1 for the f(R) model");
+        return false;
+    }
+    return true;
 }
 
 template <class T>
@@ -109,6 +121,11 @@ Symmetron<T> make_symmetron(const isis_model_params& p, double a)
     return Symmetron<T>{(T)K, (T)A};
 }
 
+// Hu-Sawicki f(R), Sec. 4.2.  In u = ln(f_R/f_R0):
+//   S = Q [eta + cL a^3 - a^3 (1 + cL) e^{-u/(n+1)}],  Q = Omega_m H0^2/(a |f_R0|).
+// In the paper's u_p = u + c, c = ln(a^2 |f_R0|), the paper's equation is the
+// same one times e^c: Q -> Omega_m H0^2 a, c1 -> c1 e^{c/(n+1)}, and the cold
+// start and the stiff threshold on e^{-u_p/(n+1)} shift accordingly.
 template <class T>
 FofR<T> make_fofr(const isis_model_params& p, double a)
 {
@@ -122,8 +139,46 @@ FofR<T> make_fofr(const isis_model_params& p, double a)
     m.a3 = a3;
     m.cL = cL;
     m.np1 = p.n + 1.0;
+    m.ushift = 0.0;
+    m.stiff_e = kFofRStiff;
+    m.max_step = (T)0;  // unused: no step bound for f(R)
+    if (p.paper_u) {
+        const double c = std::log(a * a * p.fR0_abs);
+        m.Q = p.omega_m * kH0 * kH0 * a;
+        m.c1 *= std::exp(c * m.inv_np1);
+        m.ushift = c;
+        m.stiff_e = (float)(kFofRStiff * std::exp(-c * m.inv_np1));
+    }
     m.qc1n = m.Q * m.c1 * m.inv_np1;
     m.n_is_one = p.n == 1.0 ? 1 : 0;
+    return m;
+}
+
+// Chameleon (Sec. 6) in psi = ln phi: the same non-canonical operator with
+// S = alpha eta - mu e^{-(1+n) psi}, i.e. Q = alpha, cL = 0, c1 = mu/alpha,
+// 1/(n_f+1) = 1+n.  Cold start psi = ln(mu/(alpha eta))/(1+n), which is the
+// f(R) form -np1 ln((eta/a3 + cL)/(1 + cL)) with a3 = c1, cL = 0,
+// np1 = 1/(1+n).  Stiff where the potential term exceeds 100 alpha.
+// Gauss-Seidel steps are bounded to |d psi| <= 2: where psi sits far above
+// its local root the source's derivative is tiny and a full Newton step would
+// overshoot by orders of magnitude (e^{-(1+n) psi} then overflows).
+constexpr double kChameleonMaxStep = 2.0;
+template <class T>
+FofR<T, true> make_chameleon(const isis_model_params& p)
+{
+    FofR<T, true> m;
+    m.Q = p.cham_alpha;
+    m.cLa3 = 0.0;
+    m.c1 = p.cham_mu / p.cham_alpha;
+    m.inv_np1 = 1.0 + p.cham_n;
+    m.a3 = m.c1;
+    m.cL = 0.0;
+    m.np1 = 1.0 / m.inv_np1;
+    m.ushift = 0.0;
+    m.stiff_e = (float)(100.0 / m.c1);
+    m.max_step = (T)(kChameleonMaxStep * FofR<T, true>::kVar);  // in the stored variable
+    m.qc1n = m.Q * m.c1 * m.inv_np1;
+    m.n_is_one = m.inv_np1 == 0.5 ? 1 : 0;
     return m;
 }
 
@@ -142,6 +197,8 @@ int with_model(const isis_model_params& p, double a, F&& f)
         return f(make_symmetron<T>(p, a));
     case ISIS_FR_HS:
         return f(make_fofr<T>(p, a));
+    case ISIS_CHAMELEON:
+        return f(make_chameleon<T>(p));
     default:
         return f(make_linear<T>(p));
     }
@@ -840,6 +897,10 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
         r = solve_impl(H, make_fofr<double>(*params, a), make_fofr<float>(*params, a), *params,
                        density, field, tol, use_guess, stats);
         break;
+    case ISIS_CHAMELEON:
+        r = solve_impl(H, make_chameleon<double>(*params), make_chameleon<float>(*params),
+                       *params, density, field, tol, use_guess, stats);
+        break;
     default:
         r = solve_impl(H, make_linear<double>(*params), make_linear<float>(*params), *params,
                        density, field, tol, use_guess, stats);
@@ -1011,6 +1072,10 @@ int isis_force(const isis_model_params* p, double a, int n, double h, const doub
                const double* potential, double* fx, double* fy, double* fz, void* stream)
 {
     if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (p->model == ISIS_CHAMELEON) {
+        fmt_err(g_err, "force: not provided for the chameleon model");
+        return ISIS_ERR_UNSUPPORTED;
+    }
     const bool scalar = p->model != ISIS_LINEAR;
     if (!op_grid_ok(n, 2) || !finite_pos(h) || !fx || !fy || !fz || (scalar && !field)) {
         fmt_err(g_err, "force: need even n >= 2, h > 0, fx/fy/fz non-NULL and the field for "
@@ -1031,7 +1096,8 @@ int isis_force(const isis_model_params* p, double a, int n, double h, const doub
                                                       g_err);
     }
     if (p->model == ISIS_FR_HS) {
-        const double c = 0.5 * a * a * p->fR0_abs;
+        // 1/2 e^{u_p} grad u_p with u_p = u + ln(a^2 |f_R0|)
+        const double c = p->paper_u ? 0.5 : 0.5 * a * a * p->fR0_abs;
         return launch_force<ScalarForce::kExpGrad>(n, h, c, field, potential, fx, fy, fz, s,
                                                    g_err);
     }

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_halfsweep(M m, int n, T ih2, T* __re
         T L, D;
         m.op(p, nb, eta[c], ih2, L, D);
         T eps = L - (sigma ? sigma[c] : T(0));
-        phi[c] = p - eps / D;
+        phi[c] = p - m.limit(eps / D);
     }
 }
 
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(64) void k_coarse_solve(M m, T ih2, T* __restrict__
                 T p = gather(f, 4, i, j, k, nb);
                 T L, D;
                 m.op(p, nb, e, ih2, L, D);
-                f[t] = p - (L - s) / D;
+                f[t] = p - m.limit((L - s) / D);
             }
             __syncthreads();
         }

@@ -35,6 +35,7 @@ template <class T>
 struct Symmetron {
     static constexpr double kVar = 1.0, kVarInv = 1.0;  // stored value = phi
     T K, A;
+    __device__ __forceinline__ T limit(T step) const { return step; }
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
         T lap = lap7(p, nb, ih2);
@@ -134,14 +135,29 @@ constexpr float kFofRStiff = 8.0f;  // e^{-u/(n+1)} above which the source is st
 // with no rounding of a scaled argument to correct.  The operator below
 // evaluates the same residual L(u) from w, and the Newton denominator is
 // dL/dw = ln2 dL/du.
-template <class T>
+//
+// LIM: Gauss-Seidel steps are bounded by max_step (a compile-time choice, so
+// that models without the bound carry no extra instruction).
+template <class T, bool LIM = false>
 struct FofR {
     static constexpr bool kW = sizeof(T) == 4;    // carried as w = u / ln 2
     static constexpr double kVar = kW ? kLog2e : 1.0;     // stored value = u * kVar
     static constexpr double kVarInv = kW ? kLn2 : 1.0;    // u = stored value * kVarInv
     double Q, cLa3, c1, inv_np1;
     double a3, cL, np1;  // for the cold start
+    double ushift;       // added to the cold start (variable offset)
     double qc1n;         // Q c1 / (n+1): dS/du = qc1n e^{-u/(n+1)}
+    float stiff_e;       // e^{-u/(n+1)} above which the FP32 source is evaluated in FP64
+    T max_step;          // LIM: bound on one Gauss-Seidel step of the stored value
+    // The Gauss-Seidel step, bounded by max_step when LIM: changes only the
+    // iteration (where L = Sigma the step is zero), not its fixed point.
+    __device__ __forceinline__ T limit(T step) const
+    {
+        if constexpr (LIM)
+            return fmin(fmax(step, -max_step), max_step);
+        else
+            return step;
+    }
     int n_is_one;        // n = 1: e^{-u/2} = 1/sqrt(e^u)
     // e^u from the stored value (2^w in single precision)
     __device__ __forceinline__ static T expv(T p)
@@ -159,7 +175,7 @@ struct FofR {
             // keeps the reciprocal square root finite)
             const float e = n_is_one ? __builtin_amdgcn_rsqf(fmaxf(ep, 1e-30f))
                                      : exp2_scaled(-p, float(inv_np1));
-            if (e <= kFofRStiff) {
+            if (e <= stiff_e) {
                 // Q eta + Q cLa3 - Q c1 e: no cancellation to speak of here
                 S = fmaf(float(Q), eta, fmaf(-float(Q * c1), e, float(Q * cLa3)));
                 dS = float(qc1n) * e;
@@ -215,7 +231,7 @@ struct FofR {
     __device__ __forceinline__ T cold(T eta) const
     {
         // u = -(n+1) ln[(eta/a^3 + cL)/(1 + cL)]
-        return (T)(-np1 * log(((double)eta / a3 + cL) / (1.0 + cL)) * kVar);
+        return (T)((-np1 * log(((double)eta / a3 + cL) / (1.0 + cL)) + ushift) * kVar);
     }
 };
 
@@ -225,6 +241,7 @@ template <class T>
 struct Linear {
     static constexpr double kVar = 1.0, kVarInv = 1.0;  // stored value = phi
     T kappa, m2;
+    __device__ __forceinline__ T limit(T step) const { return step; }
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
         T lap = lap7(p, nb, ih2);
@@ -252,18 +269,18 @@ struct StageOp {
     }
 };
 
-template <class T>
-struct StageOp<T, FofR<T>> {
+template <class T, bool LIM>
+struct StageOp<T, FofR<T, LIM>> {
     static constexpr bool kStaged = true, kTable = sizeof(T) == 8;
-    __device__ __forceinline__ static T stage(T x) { return FofR<T>::expv(x); }
+    __device__ __forceinline__ static T stage(T x) { return FofR<T, LIM>::expv(x); }
     __device__ __forceinline__ static T stage(T x, const double* tab)
     {
         if constexpr (sizeof(T) == 8)
             return exp_tab(x, tab);
         else
-            return FofR<T>::expv(x);
+            return FofR<T, LIM>::expv(x);
     }
-    __device__ __forceinline__ static void eval(const FofR<T>& m, T p, const T nb[6], T ep,
+    __device__ __forceinline__ static void eval(const FofR<T, LIM>& m, T p, const T nb[6], T ep,
                                                 const T enb[6], T eta, T ih2, T& L, T& D)
     {
         m.op_staged(p, nb, ep, enb, eta, ih2, L, D);

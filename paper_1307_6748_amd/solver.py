@@ -48,10 +48,15 @@ class ModelParams:
     omega_l: float = 0.73
     kappa: float = 1.0
     m2: float = 0.0
+    cham_alpha: float = 1.0
+    cham_mu: float = 1.0
+    cham_n: float = 1.0
+    paper_u: bool = False
 
     def c(self) -> A.ModelParamsC:
         return A.ModelParamsC(int(self.model), self.lambda0, self.a_ssb, self.beta, self.n,
-                              self.fR0_abs, self.omega_m, self.omega_l, self.kappa, self.m2)
+                              self.fR0_abs, self.omega_m, self.omega_l, self.kappa, self.m2,
+                              self.cham_alpha, self.cham_mu, self.cham_n, int(bool(self.paper_u)))
 
 
 def symmetron(lambda0=1.0, a_ssb=0.5, beta=1.0, omega_m=0.27) -> ModelParams:
@@ -60,9 +65,18 @@ def symmetron(lambda0=1.0, a_ssb=0.5, beta=1.0, omega_m=0.27) -> ModelParams:
                        omega_m=omega_m)
 
 
-def fofr(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=None) -> ModelParams:
+def fofr(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=None, paper_u=False) -> ModelParams:
+    """Hu-Sawicki f(R), Sec. 4.2.  The field is u = ln(f_R/f_R0), or with
+    paper_u the paper's own u = ln(a^2 |f_R|) (f_R = -a^-2 e^u)."""
     ol = 1.0 - omega_m if omega_l is None else omega_l
-    return ModelParams(model=A.ISIS_FR_HS, n=n, fR0_abs=fR0_abs, omega_m=omega_m, omega_l=ol)
+    return ModelParams(model=A.ISIS_FR_HS, n=n, fR0_abs=fR0_abs, omega_m=omega_m, omega_l=ol,
+                       paper_u=paper_u)
+
+
+def chameleon(alpha=1.0, mu=1.0, n=1.0) -> ModelParams:
+    """Chameleon of Sec. 6, lap phi = alpha eta - mu phi^-(1+n) in code units,
+    solved for psi = ln phi (the field the solver returns; needs eta > 0)."""
+    return ModelParams(model=A.ISIS_CHAMELEON, cham_alpha=alpha, cham_mu=mu, cham_n=n)
 
 
 def linear(kappa=1.0, m2=0.0) -> ModelParams:

@@ -11,6 +11,14 @@ H_CASES = {
              ("fofr", dict(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73)), 1.0),
     "fofr_a07": (dict(model=1, a=0.7, n=2.0, fR0_abs=1e-6, omega_m=0.3, omega_l=0.7),
                  ("fofr", dict(n=2.0, fR0_abs=1e-6, omega_m=0.3, omega_l=0.7)), 0.7),
+    "fofr_paper_u": (dict(model=1, a=0.8, n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73,
+                          paper_u=True),
+                     ("fofr", dict(n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73,
+                                   paper_u=True)), 0.8),
+    "chameleon": (dict(model=3, cham_alpha=2.0, cham_mu=3.0, cham_n=1.0),
+                  ("chameleon", dict(alpha=2.0, mu=3.0, n=1.0)), 1.0),
+    "chameleon_n05": (dict(model=3, cham_alpha=0.7, cham_mu=0.4, cham_n=-0.5),
+                      ("chameleon", dict(alpha=0.7, mu=0.4, n=-0.5)), 1.0),
     "linear": (dict(model=2, kappa=1.3, m2=0.4), ("linear", dict(kappa=1.3, m2=0.4)), 1.0),
     "linear_m0": (dict(model=2, kappa=0.8, m2=0.0), ("linear", dict(kappa=0.8, m2=0.0)), 1.0),
 }
@@ -28,9 +36,22 @@ def field_for(name, n, seed):
     rng = np.random.default_rng(seed)
     if name.startswith("symmetron"):
         return rng.random((n, n, n))
+    if name == "fofr_paper_u":  # u + ln(a^2 |f_R0|)
+        return np.log(0.64e-5) - 3.0 + 4.0 * rng.random((n, n, n))
     if name.startswith("fofr"):
         return -3.0 + 4.0 * rng.random((n, n, n))
+    if name.startswith("chameleon"):  # psi = ln phi
+        return -1.0 + 2.0 * rng.random((n, n, n))
     return rng.standard_normal((n, n, n))
+
+
+def sigma_for(name, n, seed, amp=1.0):
+    """A FAS source of the size of the model's operator: the paper-variable
+    f(R) equation is a^2 |f_R0| times the other one, so its source is scaled
+    (and drawn from the standard f(R) field, without the variable's offset)."""
+    if name == "fofr_paper_u":
+        return amp * 0.64e-5 * field_for("fofr", n, seed)
+    return amp * field_for(name, n, seed)
 
 
 def density(n, seed):

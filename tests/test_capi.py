@@ -74,6 +74,13 @@ def test_create_rejects_bad_workspace_without_gpu():
     (A.ModelParamsC(A.ISIS_FR_HS, 1.0, 0.5, 1, -1.0, 1e-5, 0.27, 0.73, 1, 0), 1.0),
     (A.ModelParamsC(A.ISIS_LINEAR, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, -1.0), 1.0),
     (A.ModelParamsC(9, 1.0, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0), 1.0),
+    # chameleon: alpha > 0, mu > 0, n > -1
+    (A.ModelParamsC(A.ISIS_CHAMELEON, 1, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0, 0.0, 1.0, 1.0), 1.0),
+    (A.ModelParamsC(A.ISIS_CHAMELEON, 1, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0, 1.0, -1.0, 1.0), 1.0),
+    (A.ModelParamsC(A.ISIS_CHAMELEON, 1, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0, 1.0, 1.0, -1.0), 1.0),
+    # the paper's f(R) variable is an f(R) option, 0 or 1
+    (A.ModelParamsC(A.ISIS_SYMMETRON, 1, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0, 1, 1, 1, 1), 1.0),
+    (A.ModelParamsC(A.ISIS_FR_HS, 1, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0, 1, 1, 1, 2), 1.0),
 ])
 def test_ops_validate_params_on_host(params, a):
     lib = A.lib()
@@ -123,4 +130,8 @@ def test_force_validates_on_host():
     assert lib.isis_force(C.byref(sym0), 1.0, 8, 1.0, ok, None, ok, ok, ok, None) == -1
     assert b"Omega_m" in lib.isis_mg_last_error(None)
     assert lib.isis_force(C.byref(fr), 1.0, 8, 1.0, None, ok, ok, ok, ok, None) == -1
+    cham = A.ModelParamsC(A.ISIS_CHAMELEON, 1, 0.5, 1, 1, 1e-5, 0.27, 0.73, 1, 0, 1.0, 1.0, 1.0)
+    assert lib.isis_force(C.byref(cham), 1.0, 8, 1.0, ok, None, ok, ok, ok, None) == \
+        A.ISIS_ERR_UNSUPPORTED
+    assert b"chameleon" in lib.isis_mg_last_error(None)
     assert lib.isis_force(C.byref(fr), 1.0, 8, 1.0, ok, None, ok, bad, ok, None) == -1

@@ -17,7 +17,8 @@ def _check(f_gpu, f_orc, n):
 
 
 # 6, 12, 36: the per-cell kernel (not a multiple of 64); 64, 128: the tiled one
-@pytest.mark.parametrize("name", ["symmetron_a1", "symmetron_a05", "fofr", "fofr_a07", "linear"])
+@pytest.mark.parametrize("name", ["symmetron_a1", "symmetron_a05", "fofr", "fofr_a07",
+                                  "fofr_paper_u", "linear"])
 @pytest.mark.parametrize("n", [6, 12, 36, 64, 128])
 @pytest.mark.parametrize("with_pot", [False, True])
 def test_force_matches_oracle(orc, name, n, with_pot):

@@ -9,7 +9,7 @@ that cancel (|phi| * 12/h^2 for the Laplacian), not bitwise.
 import numpy as np
 import pytest
 
-from gpucase import H_CASES, cubic, density, dev, field_for, models
+from gpucase import H_CASES, cubic, density, dev, field_for, models, sigma_for
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,7 @@ def test_halfsweep(orc, name, n, colour):
     h = 0.7
     phi = field_for(name, n, 1 + n)
     eta = density(n, 2 + n)
-    sigma = 0.1 * field_for(name, n, 3 + n)
+    sigma = sigma_for(name, n, 3 + n, 0.1)
     expect = orc.halfsweep(om, h, phi, eta, sigma, colour)
     gp = dev(phi)
     S.halfsweep(sp, a, h, gp, dev(eta), dev(sigma), colour)
@@ -48,7 +48,7 @@ def test_defect(orc, name, n):
     h = 1.3
     phi = field_for(name, n, 11)
     eta = density(n, 12)
-    for sigma in (None, field_for(name, n, 13)):
+    for sigma in (None, sigma_for(name, n, 13)):
         expect = orc.defect(om, h, phi, eta, sigma)
         got = cubic(S.defect(sp, a, h, dev(phi), dev(eta), None if sigma is None else dev(sigma)), n)
         tol = 1e-14 * (_scale(phi, h) + np.abs(expect).max())
@@ -88,7 +88,7 @@ def test_fas_descend(orc, name, n, with_sigma):
     h = 0.9
     phi = field_for(name, n, 21)
     eta = density(n, 22)
-    sig = field_for(name, n, 23) if with_sigma else None
+    sig = sigma_for(name, n, 23) if with_sigma else None
     eta_c = orc.restrict(eta)
     # oracle: the steps of the descent, as the oracle's V-cycle takes them
     phi_c = orc.restrict(phi)
@@ -110,7 +110,7 @@ def test_coarse_solve(orc, name):
     h = 8.0
     phi = field_for(name, 4, 31)
     eta = density(4, 32)
-    sigma = 0.01 * field_for(name, 4, 33)
+    sigma = sigma_for(name, 4, 33, 0.01)
     expect = orc.sweep(om, h, phi, eta, sigma, count=32)
     g = dev(phi)
     S.coarse_solve(sp, a, h, g, dev(eta), dev(sigma), 32)
@@ -128,7 +128,7 @@ def test_cold_start(orc, name):
     assert np.max(np.abs(got - expect)) <= 1e-14 * (np.abs(expect).max() + 1)
 
 
-@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "linear"])
+@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "linear", "chameleon", "fofr_paper_u"])
 @pytest.mark.parametrize("n", [8, 32, 64])
 @pytest.mark.parametrize("tb", [0, 1, 2])
 def test_sweeps_production_path(orc, name, n, tb):
@@ -139,7 +139,7 @@ def test_sweeps_production_path(orc, name, n, tb):
     h = 0.5
     phi = field_for(name, n, 51)
     eta = density(n, 52)
-    sigma = 0.1 * field_for(name, n, 53)
+    sigma = sigma_for(name, n, 53, 0.1)
     for count in (1, 2, 3):
         expect = orc.sweep(om, h, phi, eta, sigma, count=count)
         g = dev(phi)

@@ -48,7 +48,7 @@ def test_small_symmetron_config(orc, tb):
 
 
 @pytest.mark.parametrize("name", ["symmetron_a1", "symmetron_a05", "fofr", "fofr_a07", "linear",
-                                  "linear_m0"])
+                                  "linear_m0", "chameleon", "fofr_paper_u"])
 @pytest.mark.parametrize("n", [16, 64])
 def test_k_cycles_match(orc, name, n):
     """Exactly k V-cycles from the cold start: identical iterates."""
@@ -147,7 +147,9 @@ def test_domain_wall(orc):
 
 
 @pytest.mark.parametrize("name,n", [("fofr", 32), ("fofr", 64), ("fofr_a07", 128),
-                                    ("symmetron_a1", 64), ("fofr", 256), ("fofr", 512)])
+                                    ("symmetron_a1", 64), ("fofr", 256), ("fofr", 512),
+                                    ("chameleon", 64), ("chameleon_n05", 128),
+                                    ("fofr_paper_u", 256)])
 def test_residual_api(orc, name, n):
     """FP64 defect and its RMS against the oracle.  f(R) grids that are
     multiples of 64 take the LDS-tiled kernel (at 512^3 each workgroup walks

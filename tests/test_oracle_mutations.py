@@ -44,8 +44,28 @@ MUTATIONS = {
                                   "const double chit = field[c];"),
     "force_axis_swap": ("if (ax == 1) { jp = wrap(j + 1, n); jm = wrap(j - 1, n); }",
                         "if (ax == 1) { kp = wrap(k + 1, n); km = wrap(k - 1, n); }"),
+    "chameleon_exponent_missing_one": ("double e = exp(-(1.0 + m->cham_n) * psi);",
+                                       "double e = exp(-m->cham_n * psi);"),
+    "chameleon_potential_sign": ("*S = m->cham_alpha * eta - m->cham_mu * e;",
+                                 "*S = m->cham_alpha * eta + m->cham_mu * e;"),
+    "chameleon_derivative_factor": ("*dS = (1.0 + m->cham_n) * m->cham_mu * e;",
+                                    "*dS = m->cham_mu * e;"),
+    "chameleon_cold_start_exponent": (
+        "phi[c] = log(m->cham_mu / (m->cham_alpha * eta[c])) / (1.0 + m->cham_n);",
+        "phi[c] = log(m->cham_mu / (m->cham_alpha * eta[c]));"),
+    "chameleon_canonical_laplacian_of_psi": (
+        "if (m->model == ORC_FR_HS || m->model == ORC_CHAMELEON) {",
+        "if (m->model == ORC_FR_HS) {"),
+    "chameleon_step_unbounded": ("if (m->model == ORC_CHAMELEON) /* reading R15 */",
+                                 "if (0) /* reading R15 */"),
+    "paper_u_a4_factor": ("- om * a * a * a * a * H2 * g * c * e +",
+                          "- om * a * a * a * H2 * g * c * e +"),
+    "paper_u_cold_shift_missing": ("if (m->paper_u) phi[c] += log(m->a * m->a * m->fR0_abs);",
+                                   "if (m->paper_u) phi[c] += 0.0;"),
+    "paper_u_force_factor": ("const double eup = m->paper_u ? exp(field[c])",
+                             "const double eup = m->paper_u ? m->a * m->fR0_abs * exp(field[c])"),
 }
-PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py"]
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py", "test_oracle_models.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))

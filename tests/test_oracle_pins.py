@@ -121,7 +121,7 @@ def test_flux_operator_small_amplitude_is_laplacian(orc):
         assert rel < 2 * eps
 
 
-@pytest.mark.parametrize("model", ["symmetron", "fr", "linear"])
+@pytest.mark.parametrize("model", ["symmetron", "fr", "linear", "chameleon", "fr_paper_u"])
 def test_newton_denominator_is_jacobian_diagonal(orc, model):
     """Sec. 3.3 / 3.4 (eq. dbeq): the smoother's denominator equals dL_c/dphi_c
     (central finite difference of the oracle's own L) wherever the
@@ -135,6 +135,12 @@ def test_newton_denominator_is_jacobian_diagonal(orc, model):
     elif model == "fr":
         m = orc.Model(model=orc.FR_HS, fR0_abs=1e-5)
         phi = -2.0 + 3.0 * rng.random((n, n, n))
+    elif model == "chameleon":
+        m = orc.Model(model=orc.CHAMELEON, cham_alpha=2.0, cham_mu=3.0, cham_n=0.5)
+        phi = -1.0 + 2.0 * rng.random((n, n, n))
+    elif model == "fr_paper_u":
+        m = orc.Model(model=orc.FR_HS, fR0_abs=1e-5, n=2.0, a=0.7, paper_u=True)
+        phi = np.log(0.49e-5) - 2.0 + 3.0 * rng.random((n, n, n))
     else:
         m = orc.Model(model=orc.LINEAR, kappa=1.0, m2=0.3)
         phi = rng.standard_normal((n, n, n))
