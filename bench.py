@@ -15,7 +15,9 @@ solver stream (roofline), the plain FP64 GPU solve for comparison, a full-size
 residual check of the GPU solutions by the CPU oracle, and the CPU oracle timed
 solving the same two problems (cpu_baseline), the learned warm start
 (U-Net prediction + solve, symmetron) as a separate leg, and the step after the
-solve (Newtonian potential on the same grid, force kernel) as another.
+solve (Newtonian potential on the same grid, force kernel) as another, and the
+model variants (chameleon, f(R) in the paper's variable) on the same density as
+a third.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -150,6 +152,8 @@ def main() -> int:
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-force", action="store_true",
                     help="skip the Newtonian potential solve and the force kernel")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the model-variant leg (chameleon, f(R) in the paper's variable)")
     ap.add_argument("--points-per-halo", type=int, default=200_000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device twice (calibrates the HBM "
@@ -285,6 +289,35 @@ def main() -> int:
             + ", ".join(f"{k} {v['ms']:.3f} ms ({v['achieved_gbs']:.0f} GB/s)" for k, v in kern.items()))
         del out, pot, phiN
 
+    # Model variants on the same density and solver configuration (a separate
+    # leg, not in `value`): the chameleon of Sec. 6 (psi = ln phi, n = 1) and
+    # f(R) in the paper's own variable u = ln(a^2 |f_R|).
+    variants = None
+    if not args.no_variants:
+        vmods = {"chameleon": (S.chameleon(alpha=1e-3, mu=1e-3, n=1.0), 1.0),
+                 "fofr_paper_u": (S.fofr(1.0, 1e-5, 0.27, 0.73, paper_u=True), 1.0)}
+        phiv = torch.empty_like(eta)
+        variants = {}
+        for name, (p, a) in vmods.items():
+            prod.solve(eta, p, a, TOL, phi=phiv)  # warm
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            reps = 2
+            for _ in range(reps):
+                _, stv = prod.solve(eta, p, a, TOL, phi=phiv)
+            torch.cuda.synchronize()
+            t_v = (time.perf_counter() - t1) / reps
+            launches = stv.fine_sweep_launches[1]
+            ms32 = stv.fine_sweep_ms[1] / launches if launches else None
+            variants[name] = dict(
+                seconds=t_v, cycles=stv.cycles, cycles_fp32=stv.cycles_fp32,
+                rel_res=stv.rel_res,
+                fp32_sweep_ms=ms32,
+                fp32_sweep_gbs=(3 * 4 * n ** 3 / (ms32 * 1e-3) / 1e9) if ms32 else None)
+            log(f"variant {name}: {t_v:.4f}s, {stv.cycles} cycles ({stv.cycles_fp32} FP32), "
+                f"rel. residual {stv.rel_res:.3e}")
+        del phiv
+
     warm = None
     if not args.no_warm_start:
         from paper_1307_6748_amd import warmstart as W
@@ -393,6 +426,7 @@ def main() -> int:
         "parity": parity or None,
         "warm_start": warm,
         "force": force_leg,
+        "model_variants": variants,
     }
     print(json.dumps(out), flush=True)
     return 0

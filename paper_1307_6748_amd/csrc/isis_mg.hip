@@ -478,7 +478,7 @@ bool valid_desc(const isis_mg_desc* d, char* err)
 // sqrt(mean(L_0(phi)^2)) of the finest level, in double; res may be NULL.
 template <class TF, class M>
 int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* res, double* out,
-             double uscale = 1.0)
+             double uscale = 1.0, double uoffset = 0.0)
 {
     const int n = H->d.N;
     const long n3 = (long)n * n * n;
@@ -490,11 +490,11 @@ int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* r
         const long tiles = (long)(n / NG::TZ) * (n / NG::TY) * (n / NG::XC);
         g = (int)std::min<long>(kReduceBlocks, tiles);
         hipLaunchKernelGGL((k_defect_norm_tiled<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
-                           1.0 / (h * h), uscale, phi, eta, res, H->partial);
+                           1.0 / (h * h), uscale, uoffset, phi, eta, res, H->partial);
     }
     if (!tiled)
         hipLaunchKernelGGL((k_defect_norm_pairs<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
-                           1.0 / (h * h), uscale, phi, eta, res, H->partial);
+                           1.0 / (h * h), uscale, uoffset, phi, eta, res, H->partial);
     LAUNCH_CHECK(H->err, "k_defect_norm");
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
     LAUNCH_CHECK(H->err, "k_reduce");
@@ -585,10 +585,13 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
 }
 
 // The solve for one model; M64/M32 are its double and float device models.
+// In mixed precision the FP32 field is (field - shift32) * M32::kVar: f(R) in
+// the paper's variable runs its FP32 cycles in ln(f_R/f_R0) (shift32 =
+// ln(a^2 |f_R0|)), whose small magnitude keeps FP32 rounding small.
 template <class M64, class M32>
 int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_params& p,
                const double* density, double* field, double tol, int use_guess,
-               isis_mg_stats* st)
+               isis_mg_stats* st, double shift32 = 0.0)
 {
     const isis_mg_desc& d = H->d;
     const int N = d.N;
@@ -656,12 +659,12 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         for (int l = 0; l < H->nlev; ++l) {
             long c3 = (long)H->L32[l].n * H->L32[l].n * H->L32[l].n;
             hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(c3)), dim3(kBlock), 0,
-                               H->s, c3, H->L64[l].eta, H->L32[l].eta, 1.0);
+                               H->s, c3, H->L64[l].eta, H->L32[l].eta, 1.0, 0.0);
             LAUNCH_CHECK(H->err, "k_convert");
         }
         // the FP32 models may carry a scaled variable (f(R): u / ln 2)
         hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                           n3, field, H->L32[0].phi, M32::kVar);
+                           n3, field, H->L32[0].phi, M32::kVar, -shift32 * M32::kVar);
         LAUNCH_CHECK(H->err, "k_convert");
         H->L32[0].sigma = nullptr;
         // The last cycle runs in FP64, so the answer carries FP64-cycle error
@@ -681,7 +684,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             ++cyc32;
             double rc;
             if ((r = fine_rms<float, M64>(H, m64, H->L32[0].phi, density, nullptr, &rc,
-                                          M32::kVarInv)))
+                                          M32::kVarInv, shift32)))
                 return r;
             if (st) st->rel_hist[cyc] = rc / rnorm;
             rcur = rc;
@@ -706,7 +709,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             rprev = rc;
         }
         hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                           n3, H->L32[0].phi, F.phi, M32::kVarInv);
+                           n3, H->L32[0].phi, F.phi, M32::kVarInv, shift32);
         LAUNCH_CHECK(H->err, "k_convert");
     }
 
@@ -893,10 +896,14 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
         r = solve_impl(H, make_symmetron<double>(*params, a), make_symmetron<float>(*params, a),
                        *params, density, field, tol, use_guess, stats);
         break;
-    case ISIS_FR_HS:
-        r = solve_impl(H, make_fofr<double>(*params, a), make_fofr<float>(*params, a), *params,
-                       density, field, tol, use_guess, stats);
+    case ISIS_FR_HS: {
+        isis_model_params q = *params;  // FP32 cycles in ln(f_R/f_R0) (see solve_impl)
+        q.paper_u = 0;
+        const double shift32 = params->paper_u ? std::log(a * a * params->fR0_abs) : 0.0;
+        r = solve_impl(H, make_fofr<double>(*params, a), make_fofr<float>(q, a), *params, density,
+                       field, tol, use_guess, stats, shift32);
         break;
+    }
     case ISIS_CHAMELEON:
         r = solve_impl(H, make_chameleon<double>(*params), make_chameleon<float>(*params),
                        *params, density, field, tol, use_guess, stats);

@@ -415,11 +415,12 @@ __global__ __launch_bounds__(kBlock) void k_cold_start(M m, long total,
 
 template <class TO, class TI>
 __global__ __launch_bounds__(kBlock) void k_convert(long total, const TI* __restrict__ in,
-                                                    TO* __restrict__ out, double scale)
+                                                    TO* __restrict__ out, double scale,
+                                                    double offset)
 {
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < total;
          c += (long)gridDim.x * blockDim.x)
-        out[c] = (TO)((double)in[c] * scale);
+        out[c] = (TO)((double)in[c] * scale + offset);
 }
 
 }  // namespace isis

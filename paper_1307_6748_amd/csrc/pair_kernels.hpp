@@ -471,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tiled(int nf, T* __restrict_
 // Finest-level defect in double precision and per-block partial sums of r^2
 // (see k_defect_norm): one thread per z-pair of cells.
 template <class TF, class M>
-__global__ __launch_bounds__(kBlock) void k_defect_norm_pairs(M m, int n, double ih2, double uscale,
+__global__ __launch_bounds__(kBlock) void k_defect_norm_pairs(M m, int n, double ih2, double uscale, double uoffset,
                                                               const TF* __restrict__ phi,
                                                               const double* __restrict__ eta,
                                                               double* __restrict__ res,
@@ -496,21 +496,21 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_pairs(M m, int n, double
         const VF xp = *reinterpret_cast<const VF*>(phi + oxp + k0);
         const VF ym = *reinterpret_cast<const VF*>(phi + oym + k0);
         const VF yp = *reinterpret_cast<const VF*>(phi + oyp + k0);
-        const double zm = (double)phi[o + wrap_dec(k0, n)] * uscale;
-        const double zp = (double)phi[o + wrap_inc(k0 + 1, n)] * uscale;
+        const double zm = fma((double)phi[o + wrap_dec(k0, n)], uscale, uoffset);
+        const double zp = fma((double)phi[o + wrap_inc(k0 + 1, n)], uscale, uoffset);
         const VD e = *reinterpret_cast<const VD*>(eta + o + k0);
         double L2[2];
 #pragma unroll
         for (int dk = 0; dk < 2; ++dk) {
             double nb[6];
-            nb[0] = (double)xm[dk] * uscale;
-            nb[1] = (double)xp[dk] * uscale;
-            nb[2] = (double)ym[dk] * uscale;
-            nb[3] = (double)yp[dk] * uscale;
-            nb[4] = dk ? (double)c[0] * uscale : zm;
-            nb[5] = dk ? zp : (double)c[1] * uscale;
+            nb[0] = fma((double)xm[dk], uscale, uoffset);
+            nb[1] = fma((double)xp[dk], uscale, uoffset);
+            nb[2] = fma((double)ym[dk], uscale, uoffset);
+            nb[3] = fma((double)yp[dk], uscale, uoffset);
+            nb[4] = dk ? fma((double)c[0], uscale, uoffset) : zm;
+            nb[5] = dk ? zp : fma((double)c[1], uscale, uoffset);
             double L, D;
-            m.op((double)c[dk] * uscale, nb, e[dk], ih2, L, D);
+            m.op(fma((double)c[dk], uscale, uoffset), nb, e[dk], ih2, L, D);
             L2[dk] = L;
             acc += L * L;
         }
@@ -541,7 +541,7 @@ struct NormTile {
 using NormTileF = NormTile<8, 64, 32>;
 
 template <class TF, class M>
-__global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double ih2, double uscale,
+__global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double ih2, double uscale, double uoffset,
                                                               const TF* __restrict__ phi,
                                                               const double* __restrict__ eta,
                                                               double* __restrict__ res,
@@ -605,7 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
             for (int q = 0; q < G::LPT; ++q) {
                 const int k = tid + q * G::NT;
                 if ((q + 1) * G::NT <= G::PAIRS || k < G::PAIRS) {
-                    const double a = (double)regs[q].x * uscale, b = (double)regs[q].y * uscale;
+                    const double a = fma((double)regs[q].x, uscale, uoffset),
+                                 b = fma((double)regs[q].y, uscale, uoffset);
                     *reinterpret_cast<VD*>(d + 2 * k) = VD{a, b};
                     if constexpr (STAGED) {
                         double* e = xring[(x - x0 + 3) % 3];
