@@ -332,10 +332,12 @@ int launch_prolong(int nf, T* fine, const T* coarse, const T* coarse_hat, hipStr
 }
 
 template <class T>
-int launch_restrict(int nf, const T* fine, T* coarse, hipStream_t s, char* err)
+int launch_restrict(int nf, const T* fine, T* coarse, hipStream_t s, char* err,
+                    float* fine32 = nullptr)
 {
     long c3 = (long)(nf / 2) * (nf / 2) * (nf / 2);
-    hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for(c3)), dim3(kBlock), 0, s, nf, fine, coarse);
+    hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for(c3)), dim3(kBlock), 0, s, nf, fine, coarse,
+                       fine32);
     LAUNCH_CHECK(err, "k_restrict");
     return ISIS_OK;
 }
@@ -604,17 +606,34 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     H->L64[0].tmp = H->tmp0;
     H->L64[0].eta = const_cast<double*>(density);
     H->L64[0].sigma = nullptr;
+    // Density hierarchy; in mixed precision each restriction also writes the
+    // FP32 copy of its fine level (the coarsest is converted below).
     for (int l = 1; l < H->nlev; ++l)
         if ((r = launch_restrict<double>(H->L64[l - 1].n, H->L64[l - 1].eta, H->L64[l].eta, H->s,
-                                         H->err)))
+                                         H->err, mixed ? H->L32[l - 1].eta : nullptr)))
             return r;
 
     // r_ref from the cold start, whatever the initial guess.  Without a
-    // guess the cold start is built in the field itself.
+    // guess the cold start is built in the field itself (in mixed precision
+    // together with the FP32 copy the first cycle starts from), and the same
+    // pass sums its squares for the exact-root test below.
     double* cold = use_guess ? H->L64[0].tmp : field;
-    hipLaunchKernelGGL((k_cold_start<double, M64>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                       m64, n3, density, cold);
-    LAUNCH_CHECK(H->err, "k_cold_start");
+    const bool cold32 = mixed && !use_guess && !singular;
+    {
+        const int g = std::min(kReduceBlocks, grid_for(n3));
+        hipLaunchKernelGGL((k_cold_start_sumsq<M64>), dim3(g), dim3(kBlock), 0, H->s, m64, n3,
+                           density, cold, cold32 ? H->L32[0].phi : nullptr, M32::kVar,
+                           -shift32 * M32::kVar, H->partial);
+        LAUNCH_CHECK(H->err, "k_cold_start_sumsq");
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
+        LAUNCH_CHECK(H->err, "k_reduce");
+        HIP_TRY(H->err,
+                hipMemcpyAsync(H->host, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->s));
+        HIP_TRY(H->err, hipStreamSynchronize(H->s));
+    }
+    // A cold-start residual at the rounding level of its Laplacian means the
+    // cold start is an exact root (uniform density): absolute tolerance.
+    const double cold_rms = std::sqrt(H->host[0] / (double)n3);
     double r_ref;
     if ((r = fine_rms<double, M64>(H, m64, cold, density, nullptr, &r_ref))) return r;
     if (!std::isfinite(r_ref)) {
@@ -622,10 +641,6 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                         "values in eta)");
         return ISIS_ERR_INVALID_ARG;
     }
-    // A cold-start residual at the rounding level of its Laplacian means the
-    // cold start is an exact root (uniform density): absolute tolerance.
-    double cold_rms;
-    if ((r = field_rms<double>(H, cold, n3, &cold_rms))) return r;
     const double h0 = H->L64[0].h;
     const double cold_scale = 1e-14 * 6.0 / (h0 * h0) * cold_rms;
     if (singular && (r = sub_mean<double>(H, field, n3))) return r;
@@ -656,16 +671,20 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     // Mixed precision, phase 1: FP32 V-cycles on the FP32 copy of the
     // problem, monitored by the FP64 defect of the FP32 iterate.
     if (mixed && status == ISIS_ERR_NOT_CONVERGED) {
-        for (int l = 0; l < H->nlev; ++l) {
+        {  // the coarsest density (the finer ones came with the restrictions)
+            const int l = H->nlev - 1;
             long c3 = (long)H->L32[l].n * H->L32[l].n * H->L32[l].n;
             hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(c3)), dim3(kBlock), 0,
                                H->s, c3, H->L64[l].eta, H->L32[l].eta, 1.0, 0.0);
             LAUNCH_CHECK(H->err, "k_convert");
         }
-        // the FP32 models may carry a scaled variable (f(R): u / ln 2)
-        hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                           n3, field, H->L32[0].phi, M32::kVar, -shift32 * M32::kVar);
-        LAUNCH_CHECK(H->err, "k_convert");
+        // the FP32 models may carry a scaled variable (f(R): u / ln 2); from
+        // the cold start the copy was written by k_cold_start_sumsq
+        if (!cold32) {
+            hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(n3)), dim3(kBlock), 0,
+                               H->s, n3, field, H->L32[0].phi, M32::kVar, -shift32 * M32::kVar);
+            LAUNCH_CHECK(H->err, "k_convert");
+        }
         H->L32[0].sigma = nullptr;
         // The last cycle runs in FP64, so the answer carries FP64-cycle error
         // (an FP32-only solve meeting the same tol is ~10% less accurate in phi

@@ -248,7 +248,8 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean(long total, T* __restrict__
 // coarse = mean of 8 children.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_restrict(int nf, const T* __restrict__ fine,
-                                                     T* __restrict__ coarse)
+                                                     T* __restrict__ coarse,
+                                                     float* __restrict__ fine32)
 {
     const int nc = nf >> 1;
     const long total = (long)nc * nc * nc;
@@ -264,8 +265,12 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nf, const T* __restrict
 #pragma unroll
             for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
-                for (int dk = 0; dk < 2; ++dk)
-                    s += fine[cell(nf, 2 * I + di, 2 * J + dj, 2 * K + dk)];
+                for (int dk = 0; dk < 2; ++dk) {
+                    const long c = cell(nf, 2 * I + di, 2 * J + dj, 2 * K + dk);
+                    const T v = fine[c];
+                    s += v;
+                    if (fine32) fine32[c] = (float)v;  // the fine level's FP32 copy, same pass
+                }
         coarse[q] = s / T(8);
     }
 }
@@ -401,6 +406,28 @@ __global__ __launch_bounds__(64) void k_coarse_solve(M m, T ih2, T* __restrict__
         }
     }
     phi[t] = f[t];
+}
+
+// The cold start written into phi64, its FP32 copy (cold - shift) * kVar into
+// phi32 (if not NULL) and per-block partial sums of cold^2, in one pass.
+template <class M>
+__global__ __launch_bounds__(kBlock) void k_cold_start_sumsq(M m, long total,
+                                                             const double* __restrict__ eta,
+                                                             double* __restrict__ phi64,
+                                                             float* __restrict__ phi32,
+                                                             double scale32, double offset32,
+                                                             double* __restrict__ partial)
+{
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < total;
+         c += (long)gridDim.x * blockDim.x) {
+        const double v = (double)m.cold(eta[c]);
+        phi64[c] = v;
+        if (phi32) phi32[c] = (float)(v * scale32 + offset32);
+        acc += v * v;
+    }
+    double s = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 template <class T, class M>
