@@ -90,7 +90,7 @@ def measured_traffic(model: str, prec: str, n: int, tb: int):
     return None
 
 
-def roofline(kern: dict, n: int, tb: int):
+def roofline(kern: dict, n: int):
     """Roofline of the finest-level sweep kernels: achieved = compulsory bytes
     per launch / mean event-timed launch duration.  The dominant kernel (most
     time in the step) is the headline."""
@@ -100,6 +100,7 @@ def roofline(kern: dict, n: int, tb: int):
         avg_ms = v["ms"] / v["launches"]
         bpl = v["bytes"] / v["launches"]
         ach = bpl / (avg_ms * 1e-3) / 1e9
+        tb = v["tb"]
         kernels.append(dict(
             kernel=f"k_sweep_fused<{t}, {mt}<{t}>, {tb}, ...> ({n}^3, no FAS source)",
             model=model, precision=prec, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
@@ -141,7 +142,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="grid size (512 = the reported workload)")
     ap.add_argument("--temporal-block", type=int, default=-1,
-                    help="sweep fusion of the production path (-1: best available)")
+                    help="sweeps per HBM pass (-1: chosen per model by the library)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--fp32-floor", type=float, default=0.0,
                     help="mixed mode: relative residual where FP32 cycles hand over to FP64 "
@@ -175,7 +176,7 @@ def main() -> int:
 
     n = args.n
     box = 256.0
-    tb = args.temporal_block if args.temporal_block >= 0 else 1
+    tb = args.temporal_block  # -1: the library chooses per model (reported per model)
     log(f"generating density {n}^3 (lognormal sigma_delta=2 seed 20 + 400 NFW seed 22)")
     t0 = time.time()
     eta_np = synth.lognormal_nfw(n, box, 2.0, 20, 400, 22, omega_m=0.27,
@@ -223,7 +224,7 @@ def main() -> int:
                 continue
             kern[(name, prec)] = dict(
                 ms=ms, launches=nl, updates=sum(st.fine_sweep_updates[k] for st in sts),
-                bytes=sum(st.fine_sweep_bytes[k] for st in sts))
+                bytes=sum(st.fine_sweep_bytes[k] for st in sts), tb=sts[-1].temporal_block)
     sweep_ms = sum(v["ms"] for v in kern.values())
     sweep_upd = sum(v["updates"] for v in kern.values())
     per_model = {}
@@ -232,8 +233,9 @@ def main() -> int:
         per_model[name] = dict(
             seconds=float(np.mean([s.ms_total for s in sts]) / 1000.0),
             cycles=st.cycles, cycles_fp32=st.cycles_fp32, rel_res=st.rel_res,
+            temporal_block=st.temporal_block,
             rho=[st.rel_hist[i + 1] / st.rel_hist[i] for i in range(st.cycles)])
-    roof, kernels = roofline(kern, n, tb)
+    roof, kernels = roofline(kern, n)
 
     fp64 = {}
     if not args.no_fp64_compare:
@@ -409,7 +411,9 @@ def main() -> int:
                          "a_ssb=0.5, a=1) and Hu-Sawicki f(R) (n=1, |fR0|=1e-5, Om=0.27, a=1), "
                          "each solved to relative residual 1e-8"),
             "grid": n, "box": box, "tol": TOL, "precision": args.precision,
-            "temporal_block": tb, "fp32_floor": args.fp32_floor or None,
+            "temporal_block": ({k: v["temporal_block"] for k, v in per_model.items()}
+                               if tb < 0 else tb),
+            "fp32_floor": args.fp32_floor or None,
             "parallelism": "single GPU", "eta_sha256": eta_sha,
         },
         "cell_updates_per_s": {

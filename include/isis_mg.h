@@ -110,7 +110,11 @@ typedef struct {
                           expected to reach tol; else in [1e-12, 1]             */
     int temporal_block;/* 0: one HBM pass per red or black half-sweep;
                           1: one pass per full red-black sweep (fused);
-                          2: two full sweeps per pass (temporal blocking)           */
+                          2: two full sweeps per pass (temporal blocking);
+                          -1: chosen per model at each solve: 2 for the canonical
+                          models (symmetron, linear), whose sweeps are bound by
+                          HBM; 1 for the non-canonical ones (f(R), chameleon),
+                          whose sweeps are bound by arithmetic and latency      */
     void* stream;      /* hipStream_t                                              */
     void* workspace;   /* device scratch, >= isis_mg_workspace_size bytes          */
     size_t workspace_bytes;
@@ -140,6 +144,7 @@ typedef struct {
                                      per cell in FP64, 4+4+4 in FP32); a pass is
                                      one sweep, or temporal_block sweeps when
                                      blocked                                      */
+    int temporal_block;           /* the temporal block the solve used (0..2)     */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;

@@ -40,7 +40,8 @@ class StatsC(C.Structure):
                 ("rel_hist", C.c_double * MAX_HIST), ("ms_total", C.c_double),
                 ("cell_updates", C.c_double), ("used_guess", C.c_int),
                 ("fine_sweep_ms", C.c_double * 2), ("fine_sweep_launches", C.c_int * 2),
-                ("fine_sweep_updates", C.c_double * 2), ("fine_sweep_bytes", C.c_double * 2)]
+                ("fine_sweep_updates", C.c_double * 2), ("fine_sweep_bytes", C.c_double * 2),
+                ("temporal_block", C.c_int)]
 
 
 _lib = None

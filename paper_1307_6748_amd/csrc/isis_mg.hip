@@ -380,6 +380,7 @@ struct isis_mg {
     char err[512];
     // finest-level sweep timing
     static constexpr int kMaxTimed = 2 * ISIS_MG_MAX_HIST + 8;
+    int tb;  // temporal block of the current solve (desc.temporal_block resolved)
     int profile;
     int ntimed;
     hipEvent_t ev0[kMaxTimed], ev1[kMaxTimed];
@@ -466,8 +467,8 @@ bool valid_desc(const isis_mg_desc* d, char* err)
         fmt_err(err, "unknown precision %d", d->precision);
         return false;
     }
-    if (d->temporal_block < 0 || d->temporal_block > 2) {
-        fmt_err(err, "temporal_block must be 0, 1 or 2");
+    if (d->temporal_block < -1 || d->temporal_block > 2) {
+        fmt_err(err, "temporal_block must be -1 (per model), 0, 1 or 2");
         return false;
     }
     if (!(d->fp32_floor == 0.0 || (d->fp32_floor >= 1e-12 && d->fp32_floor <= 1.0))) {
@@ -539,7 +540,7 @@ int sub_mean(isis_mg* H, T* f, long n3)
 template <class T, class M>
 int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
 {
-    const int tb = H->d.temporal_block;
+    const int tb = H->tb;
     const bool timed = H->profile && l == 0 && count > 0 && H->ntimed < isis_mg::kMaxTimed;
     const int q = H->ntimed;
     if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
@@ -573,7 +574,7 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
         return launch_coarse<T, M>(m, f.h, f.phi, f.eta, f.sigma, d.nu_coarse, H->s, H->err);
     }
     LevP<T>& c = L[l + 1];
-    const int tb = d.temporal_block;
+    const int tb = H->tb;
     if ((r = timed_sweeps<T, M>(H, m, f, l, d.nu_pre))) return r;
     *updates += d.nu_pre * n3;
     if ((r = launch_descend<T, M>(m, f.n, f.h, f.phi, f.eta, f.sigma, c.eta, c.phi, c.phihat,
@@ -909,6 +910,13 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
     }
     if (hipSetDevice(H->device) != hipSuccess) return hip_fail(H->err, hipGetLastError(), "hipSetDevice");
     if (stats) memset(stats, 0, sizeof(*stats));
+    // Per-model temporal block (desc.temporal_block = -1): two sweeps per HBM
+    // pass for the canonical models, whose fused sweeps are HBM-bound; one for
+    // f(R) and the chameleon, whose two-sweep kernels are arithmetic- and
+    // register-bound (measured at 512^3: symmetron -8 %, f(R) +32 %).
+    H->tb = H->d.temporal_block >= 0 ? H->d.temporal_block
+            : (params->model == ISIS_FR_HS || params->model == ISIS_CHAMELEON) ? 1 : 2;
+    if (stats) stats->temporal_block = H->tb;
     int r;
     switch (params->model) {
     case ISIS_SYMMETRON:

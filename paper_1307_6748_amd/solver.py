@@ -109,13 +109,14 @@ class Stats:
     fine_sweep_launches: list = field(default_factory=lambda: [0, 0])
     fine_sweep_updates: list = field(default_factory=lambda: [0.0, 0.0])
     fine_sweep_bytes: list = field(default_factory=lambda: [0.0, 0.0])
+    temporal_block: int = 0  # the temporal block the solve used
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
         return Stats(status, s.cycles, s.cycles_fp32, s.r_ref, s.r0, s.rel_res,
                      list(s.rel_hist[: s.cycles + 1]), s.ms_total, s.cell_updates,
                      bool(s.used_guess), list(s.fine_sweep_ms), list(s.fine_sweep_launches),
-                     list(s.fine_sweep_updates), list(s.fine_sweep_bytes))
+                     list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block)
 
 
 def _ptr(t: torch.Tensor | None):

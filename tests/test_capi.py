@@ -51,7 +51,7 @@ def test_workspace_size_validation():
                                                     fp32_floor=1e-7))) > ok
     for bad in (dict(N=12), dict(N=4), dict(box=0.0), dict(box=float("nan")),
                 dict(nu_coarse=0), dict(max_cycles=0), dict(max_cycles=A.MAX_HIST),
-                dict(precision=7), dict(temporal_block=3), dict(nu_pre=0, nu_post=0),
+                dict(precision=7), dict(temporal_block=3), dict(temporal_block=-2), dict(nu_pre=0, nu_post=0),
                 dict(fp32_floor=-1e-6), dict(fp32_floor=2.0), dict(fp32_floor=1e-13),
                 dict(fp32_floor=float("nan"))):
         assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad

@@ -128,10 +128,11 @@ def test_fofr_256_fp64_and_mixed(orc, fr256):
     assert errm <= 1e-6
 
 
-@pytest.mark.parametrize("tb", [1, 2])
+@pytest.mark.parametrize("tb", [-1, 1, 2])
 def test_512_bench_configuration(orc, tb):
-    """The 512^3 benchmark configuration (mixed precision; one sweep per pass
-    as bench.py runs it, and two), checked by the oracle: the oracle's own
+    """The 512^3 benchmark configuration (mixed precision; the per-model
+    choice bench.py runs (-1: two sweeps per pass for the symmetron, one for
+    f(R)), and one and two for both), checked by the oracle: the oracle's own
     residual of the GPU solution is within the tolerance, and equals the
     residual the GPU reports."""
     S = _S()
@@ -146,8 +147,9 @@ def test_512_bench_configuration(orc, tb):
         (S.fofr(1.0, 1e-5, 0.27, 0.73),
          orc.Model(model=orc.FR_HS, a=1.0, n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73)),
     ]
-    for sp, om in cases:
+    for (sp, om), tb_auto in zip(cases, (2, 1)):
         phi, st = s.solve(ge, sp, 1.0, 1e-8)
+        assert st.temporal_block == (tb_auto if tb < 0 else tb)
         got = cubic(phi, n)
         r = orc.rms(orc.defect(om, h, got, eta))
         r_ref = orc.rms(orc.defect(om, h, orc.cold_start(om, eta), eta))
