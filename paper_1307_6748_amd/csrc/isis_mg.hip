@@ -507,21 +507,6 @@ int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* r
     return ISIS_OK;
 }
 
-// sqrt(mean(f^2)) of a field.
-template <class T>
-int field_rms(isis_mg* H, const T* f, long n3, double* out)
-{
-    int g = std::min(kReduceBlocks, grid_for(n3));
-    hipLaunchKernelGGL((k_sumsq<T>), dim3(g), dim3(kBlock), 0, H->s, n3, f, H->partial);
-    LAUNCH_CHECK(H->err, "k_sumsq");
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
-    LAUNCH_CHECK(H->err, "k_reduce");
-    HIP_TRY(H->err, hipMemcpyAsync(H->host, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->s));
-    HIP_TRY(H->err, hipStreamSynchronize(H->s));
-    *out = std::sqrt(H->host[0] / (double)n3);
-    return ISIS_OK;
-}
-
 template <class T>
 int sub_mean(isis_mg* H, T* f, long n3)
 {

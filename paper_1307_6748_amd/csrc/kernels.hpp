@@ -202,19 +202,6 @@ __global__ __launch_bounds__(kBlock) void k_sum(long total, const T* __restrict_
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Sum of squares of a field.
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_sumsq(long total, const T* __restrict__ f,
-                                                  double* __restrict__ partial)
-{
-    double acc = 0.0;
-    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < total;
-         c += (long)gridDim.x * blockDim.x)
-        acc += (double)f[c] * (double)f[c];
-    double s = block_sum(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
 // out[0] = sum of partial[0..count) in a fixed order (one block).
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partial, int count,
                                                    double* __restrict__ out)
