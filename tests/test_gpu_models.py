@@ -121,3 +121,17 @@ def test_chameleon_force_is_unsupported():
     x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
     with pytest.raises(S.IsisError):
         S.force(S.chameleon(), 1.0, 8.0, field=x, potential=None)
+
+
+def test_automatic_temporal_block_per_model():
+    """temporal_block = -1: two sweeps per HBM pass for the canonical models
+    (symmetron, linear), one for the non-canonical ones (f(R), chameleon);
+    the stats report the choice, and each solve still converges."""
+    from paper_1307_6748_amd import solver as S
+    n, box = 64, 128.0
+    eta = dev(_eta(n, box, 34))
+    s = _solver(n, box, temporal_block=-1, max_cycles=60)
+    for p, a, tb in ((S.symmetron(1.0, 0.5), 1.0, 2), (S.linear(1.3, 0.4), 1.0, 2),
+                     (S.fofr(1.0, 1e-5, 0.27, 0.73), 1.0, 1), (S.chameleon(2.0, 3.0, 1.0), 1.0, 1)):
+        _, st = s.solve(eta, p, a, 1e-8)
+        assert st.status == 0 and st.temporal_block == tb
