@@ -141,11 +141,13 @@ class Solver:
     """FAS multigrid solver for one grid size (one C-ABI handle).
 
     The workspace is a torch uint8 tensor on the current device; kernels run
-    on the torch stream current at construction."""
+    on the torch stream current at construction.  temporal_block = -1 (the
+    default) lets the library pick the sweeps per HBM pass for each model;
+    0, 1, 2 force one choice (see isis_mg_desc)."""
 
     def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = 2,
                  nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
-                 temporal_block: int = 0, fp32_floor: float = 0.0):
+                 temporal_block: int = -1, fp32_floor: float = 0.0):
         self.N, self.box = int(N), float(box)
         self._h = None
         lib = A.lib()
