@@ -237,22 +237,27 @@ def main() -> int:
             rho=[st.rel_hist[i + 1] / st.rel_hist[i] for i in range(st.cycles)])
     roof, kernels = roofline(kern, n)
 
-    fp64 = {}
+    # FP64-only solves of the same problems: "plain" with one launch per colour
+    # (no sweep fusion), and "fused" with the same fused sweeps and per-model
+    # sweeps per pass as the mixed solve, so that the second ratio isolates
+    # what the FP32 cycles gain.
+    fp64, fp64_fused = {}, {}
     if not args.no_fp64_compare:
-        plain = S.Solver(n, box, precision="fp64", temporal_block=0, max_cycles=100)
-        for name, (p, a) in mods.items():
-            ph = torch.empty_like(eta)
-            plain.solve(eta, p, a, TOL, phi=ph)  # warm
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, st = plain.solve(eta, p, a, TOL, phi=ph)
-            torch.cuda.synchronize()
-            fp64[name] = dict(seconds=time.perf_counter() - t1, cycles=st.cycles,
-                              rel_res=st.rel_res)
-            log(f"plain fp64 {name}: {fp64[name]['seconds']:.4f}s, {st.cycles} cycles")
-            del ph
-        plain.close()
-        del plain
+        for label, tbc, dst in (("plain", 0, fp64), ("fused", -1, fp64_fused)):
+            solver64 = S.Solver(n, box, precision="fp64", temporal_block=tbc, max_cycles=100)
+            for name, (p, a) in mods.items():
+                ph = torch.empty_like(eta)
+                solver64.solve(eta, p, a, TOL, phi=ph)  # warm
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, st = solver64.solve(eta, p, a, TOL, phi=ph)
+                torch.cuda.synchronize()
+                dst[name] = dict(seconds=time.perf_counter() - t1, cycles=st.cycles,
+                                 rel_res=st.rel_res, temporal_block=st.temporal_block)
+                log(f"{label} fp64 {name}: {dst[name]['seconds']:.4f}s, {st.cycles} cycles")
+                del ph
+            solver64.close()
+            del solver64
 
     # The step after the solve: the Newtonian potential on the same grid (the
     # Poisson equation of Sec. 3.1 as the linear model) and the total force
@@ -424,6 +429,10 @@ def main() -> int:
         "fp64_plain": fp64 or None,
         "speedup_vs_fp64_plain": (float(np.mean([fp64[k]["seconds"] for k in fp64])) / value
                                   if fp64 else None),
+        "fp64_fused": fp64_fused or None,
+        "speedup_vs_fp64_fused": (float(np.mean([fp64_fused[k]["seconds"]
+                                                 for k in fp64_fused])) / value
+                                  if fp64_fused else None),
         "roofline": roof,
         "sweep_kernels": kernels,
         "cpu_baseline": cpu,

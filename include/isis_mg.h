@@ -171,9 +171,10 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
  * ISIS_MIXED: FP32 V-cycles (FP32 fields, FP32 smoothing and coarse-grid
  * work; the f(R) source in FP64), each followed by the FP64 defect of the
  * FP32 iterate on the finest level, while that residual falls by at least
- * 0.6x per cycle, no cycle's factor exceeds both 0.2 and 3x the previous
- * one's (the FP32 round-off floor coming into view: ~2e-7 relative for the
- * symmetron, below 1e-8 for f(R) on the 512^3 halo workload) and, by
+ * 0.6x per cycle, no cycle at a relative residual <= 1e-6 has a factor
+ * above both 0.2 and 3x the previous one's (the FP32 round-off floor coming
+ * into view: ~2e-7 relative for the symmetron, below 1e-8 for f(R) on the
+ * 512^3 halo workload) and, by
  * default, one more cycle at the last factor rho is not expected to reach tol
  * (residual * rho > 0.7 tol; with desc.fp32_floor set: the residual is above
  * that level); then FP64 V-cycles from the promoted iterate to tol, by default

@@ -572,6 +572,11 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
     return ISIS_OK;
 }
 
+// Relative residual above which a jump of the FP32 cycles' factor is not taken
+// for their round-off floor: FP32 floors sit within ~20 eps_32 of the scale
+// of the equation's terms (symmetron ~2e-7 relative, f(R) below 1e-8).
+constexpr double kFloorJumpMax = 1e-6;
+
 // The solve for one model; M64/M32 are its double and float device models.
 // In mixed precision the FP32 field is (field - shift32) * M32::kVar: f(R) in
 // the paper's variable runs its FP32 cycles in ln(f_R/f_R0) (shift32 =
@@ -702,12 +707,16 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                 break;
             }
             // Refine in FP64 once the FP32 cycles reach their round-off floor:
-            // a cycle reduces the residual by less than 0.6x, or its factor
-            // jumps to more than 3x the previous cycle's (and above 0.2) as
-            // the floor comes into view; or once one more cycle is expected
-            // to finish (default), or at the caller's hand-over level.
+            // a cycle reduces the residual by less than 0.6x, or, near FP32
+            // round-off (kFloorJumpMax), its factor jumps to more than 3x the
+            // previous cycle's (and above 0.2) as the floor comes into view;
+            // or once one more cycle is expected to finish (default), or at
+            // the caller's hand-over level.  Far above round-off a rising
+            // factor is the cycle's own asymptotic rate settling in (f(R)
+            // with three sweeps per side: 0.06 then 0.23 at 3e-5).
             const double rho = rc / rprev;
-            if (rc > 0.6 * rprev || (rho > 0.2 && rho > 3.0 * rho_prev) ||
+            const bool jump = rho > 0.2 && rho > 3.0 * rho_prev && rc <= kFloorJumpMax * rnorm;
+            if (rc > 0.6 * rprev || jump ||
                 (predict ? rc * rho <= 0.7 * tol * rnorm : rc <= fp32_floor * rnorm))
                 break;
             rho_prev = rho;

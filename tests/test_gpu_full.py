@@ -34,6 +34,27 @@ def fr256():
     return synth.workload("fr_256")
 
 
+@pytest.fixture(scope="module")
+def bench512():
+    """The 512^3 benchmark density: lognormal sigma_delta = 2 (seed 20) + 400
+    NFW haloes (seed 22), box 256 Mpc/h."""
+    from paper_1307_6748_amd import synth
+    return synth.lognormal_nfw(512, 256.0, 2.0, 20, 400, 22, omega_m=0.27)
+
+
+def _check_512(orc, om, phi, st, eta, box=256.0):
+    """The oracle's own residual of the GPU solution meets the tolerance 1e-8
+    and equals the residual the GPU reports."""
+    n = 512
+    h = box / n
+    got = cubic(phi, n)
+    r = orc.rms(orc.defect(om, h, got, eta))
+    r_ref = orc.rms(orc.defect(om, h, orc.cold_start(om, eta), eta))
+    assert abs(r_ref - st.r_ref) <= 1e-9 * r_ref
+    assert r / r_ref <= 1e-8 * 1.001
+    assert abs(r / r_ref - st.rel_res) <= 1e-6 * st.rel_res
+
+
 def _hist_close(g, o, rtol):
     g, o = np.asarray(g), np.asarray(o)
     assert len(g) == len(o), (g, o)
@@ -129,19 +150,16 @@ def test_fofr_256_fp64_and_mixed(orc, fr256):
 
 
 @pytest.mark.parametrize("tb", [-1, 1, 2])
-def test_512_bench_configuration(orc, tb):
+def test_512_bench_configuration(orc, bench512, tb):
     """The 512^3 benchmark configuration (mixed precision; the per-model
     choice bench.py runs (-1: two sweeps per pass for the symmetron, one for
     f(R)), and one and two for both), checked by the oracle: the oracle's own
     residual of the GPU solution is within the tolerance, and equals the
     residual the GPU reports."""
     S = _S()
-    from paper_1307_6748_amd import synth
-    n, box = 512, 256.0
-    eta = synth.lognormal_nfw(n, box, 2.0, 20, 400, 22, omega_m=0.27)
-    s = S.Solver(n, box, precision="mixed", temporal_block=tb, max_cycles=100)
+    eta = bench512
+    s = S.Solver(512, 256.0, precision="mixed", temporal_block=tb, max_cycles=100)
     ge = dev(eta)
-    h = box / n
     cases = [
         (S.symmetron(1.0, 0.5), orc.Model(model=orc.SYMMETRON, a=1.0, lambda0=1.0, a_ssb=0.5)),
         (S.fofr(1.0, 1e-5, 0.27, 0.73),
@@ -150,13 +168,23 @@ def test_512_bench_configuration(orc, tb):
     for (sp, om), tb_auto in zip(cases, (2, 1)):
         phi, st = s.solve(ge, sp, 1.0, 1e-8)
         assert st.temporal_block == (tb_auto if tb < 0 else tb)
-        got = cubic(phi, n)
-        r = orc.rms(orc.defect(om, h, got, eta))
-        r_ref = orc.rms(orc.defect(om, h, orc.cold_start(om, eta), eta))
-        assert abs(r_ref - st.r_ref) <= 1e-9 * r_ref
-        assert r / r_ref <= 1e-8 * 1.001
-        assert abs(r / r_ref - st.rel_res) <= 1e-6 * st.rel_res
-        del got, phi
+        _check_512(orc, om, phi, st, eta)
+        del phi
+
+
+def test_512_fofr_v33_keeps_fp32_cycles(orc, bench512):
+    """f(R) on the 512^3 benchmark density with three sweeps per side, mixed
+    precision: the FP32 factor rises by itself from ~0.06 to ~0.23 at a
+    relative residual of ~3e-5, far above FP32 round-off, which is not taken
+    for the round-off floor: the FP32 phase runs until at most two cycles
+    before the end, and the result passes the oracle's residual check."""
+    S = _S()
+    s = S.Solver(512, 256.0, nu_pre=3, nu_post=3, precision="mixed", max_cycles=100)
+    phi, st = s.solve(dev(bench512), S.fofr(1.0, 1e-5, 0.27, 0.73), 1.0, 1e-8)
+    assert st.status == 0
+    assert st.cycles - st.cycles_fp32 <= 2, (st.cycles, st.cycles_fp32, st.rel_hist)
+    om = orc.Model(model=orc.FR_HS, a=1.0, n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73)
+    _check_512(orc, om, phi, st, bench512)
 
 
 def test_1024_largest_grid(orc):
