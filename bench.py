@@ -11,7 +11,8 @@ production configuration (mixed precision, fused/temporally blocked sweeps).
 Printed: one JSON line.  `value` is seconds per 512^3 solve (mean over the two
 models of the timed steps).  Also reported: Newton-GS cell updates/s, the
 finest-level smoother's achieved HBM bandwidth measured with HIP events on the
-solver stream (roofline), the plain FP64 GPU solve for comparison, a full-size
+solver stream (roofline), two FP64 GPU solves for comparison (one launch per
+colour; the same fused sweeps as the mixed solve), a full-size
 residual check of the GPU solutions by the CPU oracle, and the CPU oracle timed
 solving the same two problems (cpu_baseline), the learned warm start
 (U-Net prediction + solve, symmetron) as a separate leg, and the step after the

@@ -1,0 +1,89 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the lookup of
+counted HBM traffic by kernel and source hash, and the roofline arithmetic."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}),
+                                      ([], {"WORLD_SIZE": "2"})])
+def test_more_than_one_gpu_is_refused(argv, env):
+    e = dict(os.environ)
+    e.update(env)
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv],
+                       capture_output=True, text=True, env=e, timeout=120)
+    assert p.returncode == 2
+    assert p.stdout == ""
+    assert "one GPU" in p.stderr
+
+
+def test_traffic_lookup_by_kernel_and_source_hash(tmp_path, monkeypatch):
+    src = bench.sweep_source_hash()
+    f = tmp_path / "pmc.txt"
+    f.write_text("# counters\n"
+                 f"traffic fofr fp32 512 1 {src} 1.5e9 5.0e8\n"
+                 f"traffic symmetron fp32 512 2 {src} 2.5e9 5.0e8\n"
+                 "traffic fofr fp64 512 1 0000000000000000 9e9 9e9\n"
+                 "traffic fofr fp32 512 1 junk\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("fofr", "fp32", 512, 1) == pytest.approx(2.0e9)
+    assert bench.measured_traffic("symmetron", "fp32", 512, 2) == pytest.approx(3.0e9)
+    # recorded for other sources (the kernel changed since): not reported
+    assert bench.measured_traffic("fofr", "fp64", 512, 1) is None
+    # another temporal block or grid is another kernel
+    assert bench.measured_traffic("symmetron", "fp32", 512, 1) is None
+    assert bench.measured_traffic("fofr", "fp32", 256, 1) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic("fofr", "fp32", 512, 1) is None
+
+
+def test_source_hash_tracks_the_sweep_sources(tmp_path, monkeypatch):
+    h0 = bench.sweep_source_hash()
+    assert len(h0) == 16 and int(h0, 16) >= 0
+    for rel in bench.SWEEP_SOURCES:
+        d = tmp_path / os.path.dirname(rel)
+        d.mkdir(parents=True, exist_ok=True)
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            (tmp_path / rel).write_bytes(fh.read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.sweep_source_hash() == h0
+    p = tmp_path / bench.SWEEP_SOURCES[1]
+    p.write_bytes(p.read_bytes() + b"\n")
+    assert bench.sweep_source_hash() != h0
+
+
+def test_committed_traffic_lines_are_well_formed():
+    lines = [ln.split() for ln in open(bench.TRAFFIC_FILE) if ln.startswith("traffic ")]
+    assert lines
+    for f in lines:
+        assert len(f) == 8
+        assert f[1] in bench.MODEL_TYPES and f[2] in bench.TYPES
+        assert int(f[3]) > 0 and int(f[4]) in (1, 2) and len(f[5]) == 16
+        assert float(f[6]) > 0 and float(f[7]) > 0
+    # the dominant kernel of the benchmark (FP32 f(R), one sweep per pass)
+    assert any(f[1:5] == ["fofr", "fp32", "512", "1"] for f in lines)
+
+
+def test_roofline_head_is_the_kernel_with_most_time(monkeypatch):
+    monkeypatch.setattr(bench, "measured_traffic", lambda *a: None)
+    n = 512
+    b32 = 3 * 4 * n ** 3
+    kern = {
+        ("symmetron", "fp32"): dict(ms=10 * 0.6, launches=10, bytes=10 * b32, tb=2),
+        ("fofr", "fp32"): dict(ms=52 * 0.4, launches=52, bytes=52 * b32, tb=1),
+    }
+    head, ks = bench.roofline(kern, n)
+    assert [k["model"] for k in ks] == ["fofr", "symmetron"]
+    assert head["model"] == "fofr" and head["bound"] == "hbm" and head["unit"] == "GB/s"
+    assert head["avg_launch_ms"] == pytest.approx(0.4)
+    assert head["achieved"] == pytest.approx(b32 / 0.4e-3 / 1e9)
+    assert head["frac"] == pytest.approx(head["achieved"] / 8000.0)
+    assert head["peak"] == 8000.0 and head["traffic"] is None
+    assert ", 1, " in head["kernel"] and ", 2, " in ks[1]["kernel"]
