@@ -121,6 +121,21 @@ def omp_threads() -> int:
         return 1
 
 
+def host_info() -> dict:
+    """CPU model, logical CPUs and the OpenMP setting the oracle ran under."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(cpu_model=model, os_cpu_count=os.cpu_count(),
+                omp_num_threads_env=os.environ.get("OMP_NUM_THREADS"))
+
+
 def copy_probe(mib: int) -> int:
     """A plain device copy of known size: the counters read for it turn
     FETCH_SIZE / WRITE_SIZE of other kernels into bytes."""
@@ -392,11 +407,34 @@ def main() -> int:
             del phi_np, cold, ref
             log(f"oracle {name}: {times[name]['seconds']:.1f}s ({times[name]['cycles']} cycles); "
                 f"GPU rel. L2 error {err:.2e}, oracle residual of GPU field {r / r_ref:.3e}")
+        # The small case (32^3 symmetron, box 64, lognormal sigma_delta = 1,
+        # seed 1, to 1e-10) on all threads and on one, and on the GPU.
+        sw = synth.workload("small_symmetron")
+        so = O.Model(model=O.SYMMETRON, a=1.0, lambda0=1.0, a_ssb=0.5)
+        small = {}
+        for label, nt in (("oracle_all_threads", cores), ("oracle_one_thread", 1)):
+            O.set_threads(nt)
+            r = O.solve(so, sw["eta"], sw["box"], tol=1e-10)
+            small[label] = dict(seconds=r.wall_s, cycles=r.cycles, threads=nt)
+        O.set_threads(cores)
+        s32 = S.Solver(sw["n"], sw["box"], precision="fp64")
+        e32 = torch.from_numpy(sw["eta"]).cuda()
+        s32.solve(e32, *mods["symmetron"], 1e-10)  # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st = s32.solve(e32, *mods["symmetron"], 1e-10)
+        torch.cuda.synchronize()
+        small["gpu_fp64"] = dict(seconds=time.perf_counter() - t1, cycles=st.cycles)
+        s32.close()
+        log(f"32^3 symmetron to 1e-10: oracle {small['oracle_all_threads']['seconds'] * 1e3:.1f} ms "
+            f"({cores} threads), {small['oracle_one_thread']['seconds'] * 1e3:.1f} ms (1 thread); "
+            f"GPU {small['gpu_fp64']['seconds'] * 1e3:.1f} ms")
         cpu = dict(value=float(np.mean([t["seconds"] for t in times.values()])), unit="s",
                    cores=cores, kind="oracle",
                    sample=("complete FP64 CPU-oracle FAS solves of both models at 512^3 on the "
                            "same density, to relative residual 1e-8 (wall time of each solve "
-                           "call, mean over the two models)"), detail=times)
+                           "call, mean over the two models)"), detail=times,
+                   host=host_info(), small_case=small)
 
     out = {
         "metric": METRIC,
