@@ -65,7 +65,8 @@ MUTATIONS = {
     "paper_u_force_factor": ("const double eup = m->paper_u ? exp(field[c])",
                              "const double eup = m->paper_u ? m->a * m->fR0_abs * exp(field[c])"),
 }
-PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py", "test_oracle_models.py"]
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py", "test_oracle_models.py",
+             "test_oracle_newton.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
