@@ -172,6 +172,35 @@ def test_512_bench_configuration(orc, bench512, tb):
         del phi
 
 
+def test_512_fp32_cycles_match_oracle_cycles(orc, bench512):
+    """The benchmark's launch configuration at 512^3 (mixed precision, the
+    per-model sweeps per pass: two for the symmetron, one for f(R)), stopped
+    after two FP32 V-cycles: the promoted iterate equals two FP64 V-cycles of
+    the oracle element by element to FP32 rounding, and the judge's residual
+    equals the oracle's residual of that field."""
+    S = _S()
+    n, box = 512, 256.0
+    h = box / n
+    ge = dev(bench512)
+    s = S.Solver(n, box, precision="mixed", max_cycles=2)
+    cases = [
+        (S.symmetron(1.0, 0.5), orc.Model(model=orc.SYMMETRON, a=1.0, lambda0=1.0, a_ssb=0.5), 2),
+        (S.fofr(1.0, 1e-5, 0.27, 0.73),
+         orc.Model(model=orc.FR_HS, a=1.0, n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73), 1),
+    ]
+    for sp, om, tb in cases:
+        phi, st = s.solve(ge, sp, 1.0, 1e-300, check=False)
+        assert st.status == -2 and st.cycles_fp32 == 2 and st.temporal_block == tb
+        got = cubic(phi, n)
+        del phi
+        ro = orc.vcycles(om, bench512, box, orc.cold_start(om, bench512), 2)
+        err = np.max(np.abs(got - ro.phi)) / (np.abs(ro.phi).max() + 1.0)
+        assert err <= 1e-6, err
+        r = orc.rms(orc.defect(om, h, got, bench512)) / ro.r_ref
+        assert abs(st.rel_res - r) <= 1e-9 * r, (st.rel_res, r)
+        del got, ro
+
+
 def test_512_fofr_v33_keeps_fp32_cycles(orc, bench512):
     """f(R) on the 512^3 benchmark density with three sweeps per side, mixed
     precision: the FP32 factor rises by itself from ~0.06 to ~0.23 at a
