@@ -292,24 +292,32 @@ __global__ void k_pool2(const bf16_t* __restrict__ x, int nf, int cs, int c0, in
 }
 
 // Nearest upsampling of a [nc^3][C] tensor into channels [0, C) of a
-// [(2nc)^3][cs] tensor, and copy of skip [(2nc)^3][S] into channels [C, C+S).
-__global__ void k_up2_cat(const bf16_t* __restrict__ lo, int nc, int C,
-                          const bf16_t* __restrict__ skip, int S, bf16_t* __restrict__ out)
+// [(2nc)^3][C+S] tensor, and copy of skip [(2nc)^3][S] into channels
+// [C, C+S).  One 16-byte vector of 8 output channels per thread, so a wave
+// writes 1 KiB of contiguous output (C and S are multiples of 8, the tensors
+// 256-byte aligned); coordinates by shifts (the side is a power of two).
+template <int C, int S>
+__global__ void k_up2_cat(const bf16_t* __restrict__ lo, int nc, const bf16_t* __restrict__ skip,
+                          bf16_t* __restrict__ out)
 {
-    const int nf = 2 * nc, cs = C + S;
-    const long total = (long)nf * nf * nf * cs;
+    static_assert(C % 8 == 0 && S % 8 == 0, "channels in whole 16-byte vectors");
+    constexpr int VC = C / 8, VS = S / 8, VT = VC + VS;
+    const int nf = 2 * nc, lf = __builtin_ctz(nf);
+    const long total = (long)nf * nf * nf * VT;
+    const uint4* lov = reinterpret_cast<const uint4*>(lo);
+    const uint4* skv = reinterpret_cast<const uint4*>(skip);
+    uint4* outv = reinterpret_cast<uint4*>(out);
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(e % cs);
-        const long v = e / cs;
-        if (c < C) {
-            const int k = (int)(v % nf);
-            const long r = v / nf;
-            const int j = (int)(r % nf), i = (int)(r / nf);
-            const long V = ((long)(i / 2) * nc + j / 2) * nc + k / 2;
-            out[e] = lo[V * C + c];
+        const long v = e / VT;
+        const int q = (int)(e - v * VT);
+        if (q < VC) {
+            const int k = (int)(v & (nf - 1)), j = (int)((v >> lf) & (nf - 1));
+            const int i = (int)(v >> (2 * lf));
+            const long V = ((long)(i >> 1) * nc + (j >> 1)) * nc + (k >> 1);
+            outv[e] = lov[V * VC + q];
         } else {
-            out[e] = skip[v * S + (c - C)];
+            outv[e] = skv[v * VS + (q - VC)];
         }
     }
 }
@@ -649,8 +657,17 @@ int run_forward(const Plan& P, const float* params, hipStream_t s)
         return (int)ISIS_OK;
     };
     auto upcat = [&](const bf16_t* lo, int lvc, int C, const bf16_t* skip, int S, bf16_t* out) -> int {
-        hipLaunchKernelGGL(k_up2_cat, dim3(grid_of(P.nv[lvc - 1] * (C + S))), dim3(kThreads), 0, s,
-                           lo, P.n[lvc], C, skip, S, out);
+        const dim3 g(grid_of(P.nv[lvc - 1] * (C + S) / 8));
+        if (C == 64 && S == 64)
+            hipLaunchKernelGGL((k_up2_cat<64, 64>), g, dim3(kThreads), 0, s, lo, P.n[lvc], skip, out);
+        else if (C == 64 && S == 32)
+            hipLaunchKernelGGL((k_up2_cat<64, 32>), g, dim3(kThreads), 0, s, lo, P.n[lvc], skip, out);
+        else if (C == 32 && S == 16)
+            hipLaunchKernelGGL((k_up2_cat<32, 16>), g, dim3(kThreads), 0, s, lo, P.n[lvc], skip, out);
+        else {
+            uerr("k_up2_cat: no instance for %d + %d channels", C, S);
+            return (int)ISIS_ERR_INVALID_ARG;
+        }
         ULAUNCH("k_up2_cat");
         return (int)ISIS_OK;
     };
