@@ -147,6 +147,92 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const bf16_t* __restrict__ x
         }
 }
 
+// The same convolution with its input staged in LDS (sides n >= 64).  A
+// workgroup computes a 4 (y) x 64 (z) tile of one x-plane, one z-row of 64
+// voxels per wave (four M tiles of 16).  For each 16-channel slice of the
+// input it stages the 3 x 6 x 66 voxels its 27 taps read (38 KB), so every
+// input value comes from L2 about 4.6 times per convolution instead of once
+// per tap; A operands are then read from LDS (16 consecutive voxels x 32 B
+// per MFMA: no bank conflicts).  Tiles are dealt to the 8 XCDs in
+// contiguous ranges with x fastest, so neighbouring planes share an L2.
+constexpr int kLY = 4, kLZ = 64;                   // output tile (y, z)
+constexpr int kLPY = kLY + 2, kLPZ = kLZ + 2;      // with the halo
+constexpr int kLVox = 3 * kLPY * kLPZ;             // staged voxels per slice
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict__ x, int n,
+                                                        const bf16_t* __restrict__ w,
+                                                        const float* __restrict__ bias, int relu,
+                                                        bf16_t* __restrict__ y,
+                                                        float* __restrict__ yf)
+{
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "whole 16-channel slices");
+    constexpr int NT = COUT / 16;
+    __shared__ uint4 tile[kLVox * 2];  // [plane][row][z][16 channels] as two 16-byte halves
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int msk = n - 1, nyt = n / kLY;
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int x0 = b % n, yt = (b / n) % nyt, zt = b / (n * nyt);
+    const int y0 = yt * kLY, z0 = zt * kLZ;
+
+    f4 acc[4][NT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) acc[t][u] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const bf16_t* tb = reinterpret_cast<const bf16_t*>(tile);
+    for (int c0 = 0; c0 < CIN; c0 += 16) {
+        if (c0) __syncthreads();  // the previous slice has been consumed
+        for (int e = tid; e < kLVox * 2; e += kThreads) {
+            const int vox = e >> 1, h = e & 1;
+            const int zz = vox % kLPZ, rr = (vox / kLPZ) % kLPY, pp = vox / (kLPZ * kLPY);
+            const long gv = ((long)((x0 - 1 + pp) & msk) * n + ((y0 - 1 + rr) & msk)) * n +
+                            ((z0 - 1 + zz) & msk);
+            tile[e] = *reinterpret_cast<const uint4*>(x + gv * CIN + c0 + 8 * h);
+        }
+        __syncthreads();
+        for (int tap = 0; tap < 27; ++tap) {
+            // staged plane, row and column offsets of this tap (halo included)
+            const int pi = tap / 9, rj = (tap / 3) % 3, zk = tap % 3;
+            const bf16_t* wt = w + (long)tap * COUT * CIN;
+            s4 bw[NT];
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+                bw[u] = *reinterpret_cast<const s4*>(wt + (long)(16 * u + m) * CIN + c0 + 4 * g);
+            const int base = (pi * kLPY + wv + rj) * kLPZ + m + zk;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const s4 a = *reinterpret_cast<const s4*>(tb + (base + 16 * t) * 16 + 4 * g);
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[u], acc[t][u], 0,
+                                                                          0, 0);
+            }
+        }
+    }
+    // D[row = 4g + r][col = m]: voxel z0 + 16t + 4g + r of row y0 + wv, channel 16u + m
+    const long v0 = ((long)x0 * n + (y0 + wv)) * n + z0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int co = 16 * u + m;
+            const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long v = v0 + 16 * t + 4 * g + r;
+                float val = acc[t][u][r] + bb;
+                if (relu) val = fmaxf(val, 0.f);
+                if (y) y[v * COUT + co] = f2bf(val);
+                if (yf) yf[v * COUT + co] = val;
+            }
+        }
+}
+
 // dW partials: part[chunk][t][co][ci] = sum over the chunk's voxels v of
 // dy[v][co] * x[v + d_t][ci].  One workgroup per (tap, chunk); its waves
 // split the 16x16 output tiles.  K (voxels) advances 16 at a time.
@@ -496,10 +582,18 @@ int launch_conv(const bf16_t* x, int n, int cin, const bf16_t* w, const float* b
 {
     const long nvox = (long)n * n * n;
     const int blocks = (int)((nvox + 255) / 256);
+    // sides >= 64 (powers of two): the LDS-staged kernel, one workgroup per
+    // 4 x 64 tile of an x-plane
+    const bool lds = n >= kLZ;
+    const long lblocks = (long)n * (n / kLY) * (n / kLZ);
 #define CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                          \
-        hipLaunchKernelGGL((k_conv3<CI, CO>), dim3(blocks), dim3(kThreads), 0, s, x, n, w,  \
-                           bias, relu, y, yf);                                              \
+        if (lds)                                                                            \
+            hipLaunchKernelGGL((k_conv3_lds<CI, CO>), dim3((unsigned)lblocks), dim3(kThreads), \
+                               0, s, x, n, w, bias, relu, y, yf);                           \
+        else                                                                                \
+            hipLaunchKernelGGL((k_conv3<CI, CO>), dim3(blocks), dim3(kThreads), 0, s, x, n, \
+                               w, bias, relu, y, yf);                                       \
         ULAUNCH("k_conv3");                                                                 \
         return ISIS_OK;                                                                     \
     }

@@ -59,6 +59,35 @@ def test_conv_forward(cin, cout, n):
         1e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("cin,cout,n", [(c, o, 64) for c, o in SHAPES] +
+                         [(16, 48, 64), (16, 16, 128), (48, 16, 128)])
+def test_conv_forward_staged(cin, cout, n):
+    """Sides >= 64 take the LDS-staged kernel (4 x 64 tiles of an x-plane,
+    16-channel slices).  Checked on eight 8^3 output blocks (corners and the
+    periodic wrap included): the oracle convolves each block with its
+    one-voxel periodic halo, whose interior is then exact."""
+    rng = np.random.default_rng(cin * 7 + cout + n)
+    x = U.bf16(rng.standard_normal((n, n, n, cin)))
+    W = U.bf16(rng.standard_normal((27, cout, cin)) * 0.1)
+    b = rng.standard_normal(cout).astype(np.float32).astype(np.float64)
+    yf = torch.empty(n ** 3 * cout, dtype=torch.float32, device="cuda")
+    yb = torch.empty(n ** 3 * cout, dtype=torch.int16, device="cuda")
+    bt = torch.from_numpy(b.astype(np.float32)).cuda()
+    xt, wt = raw(x), raw(W)
+    rc = lib().isis_conv3_fwd(P(xt), n, cin, P(wt), P(bt), cout, 1, P(yb), P(yf), None)
+    assert rc == 0
+    got = yf.cpu().numpy().reshape(n, n, n, cout)
+    gb = (yb.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    corners = [(0, 0, 0), (n - 4, n - 4, n - 4), (n // 2 - 3, 5, n - 60), (7, n - 8, 28)]
+    corners += [tuple(int(c) for c in rng.integers(0, n, 3)) for _ in range(4)]
+    for c in corners:
+        idx = [(c[d] - 1 + np.arange(10)) % n for d in range(3)]
+        ref = np.maximum(U.conv3(x[np.ix_(*idx)], W, b)[1:9, 1:9, 1:9], 0.0)
+        sel = np.ix_(idx[0][1:9], idx[1][1:9], idx[2][1:9])
+        assert np.max(np.abs(got[sel] - ref)) <= 1e-5 * max(np.abs(ref).max(), 1e-30), c
+        assert np.array_equal(gb.reshape(got.shape)[sel], U.bf16(got[sel]).astype(np.float32))
+
+
 @pytest.mark.parametrize("cin,cout", SHAPES)
 def test_conv_data_gradient(cin, cout):
     """Flipped, transposed weights turn the forward kernel into the adjoint."""
