@@ -152,9 +152,11 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const bf16_t* __restrict__ x
 // voxels per wave (four M tiles of 16).  For each 16-channel slice of the
 // input it stages the 3 x 6 x 66 voxels its 27 taps read (38 KB), so every
 // input value comes from L2 about 4.6 times per convolution instead of once
-// per tap; A operands are then read from LDS (16 consecutive voxels x 32 B
-// per MFMA: no bank conflicts).  Tiles are dealt to the 8 XCDs in
-// contiguous ranges with x fastest, so neighbouring planes share an L2.
+// per tap.  LDS holds a slice as four arrays of 8-byte units, one per group
+// of 4 channels (the MFMA's k-groups), so the 16 lanes of a k-group read 128
+// contiguous bytes (voxel-major 32-byte rows put lanes m, m+4, m+8, m+12 on
+// one bank).  Tiles are dealt to the 8 XCDs in contiguous ranges with x
+// fastest, so neighbouring planes share an L2.
 constexpr int kLY = 4, kLZ = 64;                   // output tile (y, z)
 constexpr int kLPY = kLY + 2, kLPZ = kLZ + 2;      // with the halo
 constexpr int kLVox = 3 * kLPY * kLPZ;             // staged voxels per slice
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
 {
     static_assert(CIN % 16 == 0 && COUT % 16 == 0, "whole 16-channel slices");
     constexpr int NT = COUT / 16;
-    __shared__ uint4 tile[kLVox * 2];  // [plane][row][z][16 channels] as two 16-byte halves
+    __shared__ uint2 tile[4 * kLVox];  // [4-channel group][plane][row][z]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, g = lane >> 4;
     const int msk = n - 1, nyt = n / kLY;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
 #pragma unroll
         for (int u = 0; u < NT; ++u) acc[t][u] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const bf16_t* tb = reinterpret_cast<const bf16_t*>(tile);
+    const uint2* tg = tile + g * kLVox;  // this lane's k-group
     for (int c0 = 0; c0 < CIN; c0 += 16) {
         if (c0) __syncthreads();  // the previous slice has been consumed
         for (int e = tid; e < kLVox * 2; e += kThreads) {
@@ -192,9 +194,12 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
             const int zz = vox % kLPZ, rr = (vox / kLPZ) % kLPY, pp = vox / (kLPZ * kLPY);
             const long gv = ((long)((x0 - 1 + pp) & msk) * n + ((y0 - 1 + rr) & msk)) * n +
                             ((z0 - 1 + zz) & msk);
-            tile[e] = *reinterpret_cast<const uint4*>(x + gv * CIN + c0 + 8 * h);
+            const uint4 v = *reinterpret_cast<const uint4*>(x + gv * CIN + c0 + 8 * h);
+            tile[(2 * h) * kLVox + vox] = uint2{v.x, v.y};
+            tile[(2 * h + 1) * kLVox + vox] = uint2{v.z, v.w};
         }
         __syncthreads();
+#pragma unroll
         for (int tap = 0; tap < 27; ++tap) {
             // staged plane, row and column offsets of this tap (halo included)
             const int pi = tap / 9, rj = (tap / 3) % 3, zk = tap % 3;
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
             const int base = (pi * kLPY + wv + rj) * kLPZ + m + zk;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const s4 a = *reinterpret_cast<const s4*>(tb + (base + 16 * t) * 16 + 4 * g);
+                const s4 a = *reinterpret_cast<const s4*>(tg + base + 16 * t);
 #pragma unroll
                 for (int u = 0; u < NT; ++u)
                     acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[u], acc[t][u], 0,
@@ -231,6 +236,113 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
                 if (yf) yf[v * COUT + co] = val;
             }
         }
+}
+
+// 16 input channels (sides n >= 64): the 4 x 64 tile streams along x over
+// xc planes through a ring of three staged planes (6 x 66 voxels, 32 B
+// each), so each output plane stages one new input plane instead of three;
+// the next plane is loaded into registers while the current one is computed.
+template <int COUT>
+__global__ __launch_bounds__(kThreads) void k_conv3_ring(const bf16_t* __restrict__ x, int n,
+                                                         int xc, const bf16_t* __restrict__ w,
+                                                         const float* __restrict__ bias, int relu,
+                                                         bf16_t* __restrict__ y,
+                                                         float* __restrict__ yf)
+{
+    constexpr int CIN = 16, NT = COUT / 16;
+    constexpr int PVOX = kLPY * kLPZ;                   // voxels per staged plane
+    constexpr int PV = PVOX * 2;                        // 16-byte input vectors per plane
+    constexpr int PER = (PV + kThreads - 1) / kThreads;  // of them per thread
+    __shared__ uint2 ring[3 * 4 * PVOX];  // [slot][4-channel group][row][z] (see k_conv3_lds)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int msk = n - 1, nyt = n / kLY, nzt = n / kLZ;
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int yt = b % nyt, zt = (b / nyt) % nzt, xq = b / (nyt * nzt);
+    const int y0 = yt * kLY, z0 = zt * kLZ, x0 = xq * xc;
+    const size_t plane = (size_t)n * n * CIN;
+    // in-plane element offsets of this thread's vectors (tail clamped; its
+    // stores are skipped)
+    unsigned poff[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = min(tid + q * kThreads, PV - 1);
+        const int vox = e >> 1, h = e & 1;
+        const int zz = vox % kLPZ, rr = vox / kLPZ;
+        poff[q] = (unsigned)((((y0 - 1 + rr) & msk) * n + ((z0 - 1 + zz) & msk)) * CIN + 8 * h);
+    }
+    uint4 pre[PER];
+    auto load = [&](int xp) __attribute__((always_inline)) {
+        const bf16_t* pl = x + (size_t)(xp & msk) * plane;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = *reinterpret_cast<const uint4*>(pl + poff[q]);
+    };
+    auto put = [&](int xp) __attribute__((always_inline)) {
+        uint2* dst = ring + ((xp - x0 + 1) % 3) * 4 * PVOX;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * kThreads;
+            if ((q + 1) * kThreads <= PV || e < PV) {
+                const int vox = e >> 1, h = e & 1;
+                dst[(2 * h) * PVOX + vox] = uint2{pre[q].x, pre[q].y};
+                dst[(2 * h + 1) * PVOX + vox] = uint2{pre[q].z, pre[q].w};
+            }
+        }
+    };
+    load(x0 - 1);
+    put(x0 - 1);
+    load(x0);
+    put(x0);
+    load(x0 + 1);
+    for (int xi = x0; xi < x0 + xc; ++xi) {
+        put(xi + 1);  // into the slot of plane xi - 2, free since the last barrier
+        __syncthreads();
+        if (xi + 2 <= x0 + xc) load(xi + 2);  // in flight during this plane's taps
+        f4 acc[4][NT];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[t][u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) {
+            const int pi = tap / 9, rj = (tap / 3) % 3, zk = tap % 3;
+            const bf16_t* wt = w + (long)tap * COUT * CIN;
+            s4 bw[NT];
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+                bw[u] = *reinterpret_cast<const s4*>(wt + (16 * u + m) * CIN + 4 * g);
+            const int slot = (xi - 1 + pi - x0 + 1) % 3;
+            const uint2* tg = ring + (slot * 4 + g) * PVOX;  // this lane's k-group
+            const int base = (wv + rj) * kLPZ + m + zk;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const s4 a = *reinterpret_cast<const s4*>(tg + base + 16 * t);
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[u], acc[t][u], 0,
+                                                                          0, 0);
+            }
+        }
+        const long v0 = ((long)xi * n + (y0 + wv)) * n + z0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const int co = 16 * u + m;
+                const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const long v = v0 + 16 * t + 4 * g + r;
+                    float val = acc[t][u][r] + bb;
+                    if (relu) val = fmaxf(val, 0.f);
+                    if (y) y[v * COUT + co] = f2bf(val);
+                    if (yf) yf[v * COUT + co] = val;
+                }
+            }
+        __syncthreads();  // the slot of plane xi - 1 is free for the next put
+    }
 }
 
 // dW partials: part[chunk][t][co][ci] = sum over the chunk's voxels v of
@@ -586,9 +698,17 @@ int launch_conv(const bf16_t* x, int n, int cin, const bf16_t* w, const float* b
     // 4 x 64 tile of an x-plane
     const bool lds = n >= kLZ;
     const long lblocks = (long)n * (n / kLY) * (n / kLZ);
+    // 16 input channels: planes per workgroup for the ring kernel, a power of
+    // two up to 16 that leaves >= 2048 workgroups
+    const long tiles2d = (long)(n / kLY) * (n / kLZ);
+    int xc = 1;
+    while (xc < 16 && tiles2d * (n / (2 * xc)) >= 2048) xc *= 2;
 #define CONV_CASE(CI, CO)                                                                   \
     if (cin == CI && cout == CO) {                                                          \
-        if (lds)                                                                            \
+        if (lds && CI == 16)                                                                \
+            hipLaunchKernelGGL((k_conv3_ring<CO>), dim3((unsigned)(tiles2d * (n / xc))),     \
+                               dim3(kThreads), 0, s, x, n, xc, w, bias, relu, y, yf);       \
+        else if (lds)                                                                       \
             hipLaunchKernelGGL((k_conv3_lds<CI, CO>), dim3((unsigned)lblocks), dim3(kThreads), \
                                0, s, x, n, w, bias, relu, y, yf);                           \
         else                                                                                \
