@@ -465,27 +465,37 @@ __global__ void k_to_bf16(const float* __restrict__ src, long total, bf16_t* __r
 // ---------------------------------------------------------------------------
 
 // y[V][c] = mean of the 8 children (reading channels [c0, c0+C) of a tensor
-// with channel stride cs); nf = fine side.
+// with channel stride cs); nf = fine side (a power of two).  One 16-byte
+// vector of 8 channels per thread (C, cs, c0 multiples of 8, C / 8 a power
+// of two).
 __global__ void k_pool2(const bf16_t* __restrict__ x, int nf, int cs, int c0, int C,
                         bf16_t* __restrict__ y)
 {
-    const int nc = nf / 2;
-    const long total = (long)nc * nc * nc * C;
+    const int nc = nf / 2, lc = __builtin_ctz(nc), lq = __builtin_ctz(C / 8);
+    const long total = ((long)nc * nc * nc) << lq;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(e % C);
-        const long V = e / C;
-        const int K = (int)(V % nc);
-        const long r = V / nc;
-        const int J = (int)(r % nc), I = (int)(r / nc);
-        float s = 0.f;
+        const int q = (int)(e & ((C / 8) - 1));
+        const long V = e >> lq;
+        const int K = (int)(V & (nc - 1)), J = (int)((V >> lc) & (nc - 1)), I = (int)(V >> (2 * lc));
+        float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
                 for (int d = 0; d < 2; ++d) {
                     const long vf = ((long)(2 * I + a) * nf + (2 * J + b)) * nf + (2 * K + d);
-                    s += bf2f(x[vf * cs + c0 + c]);
+                    const uint4 u = *reinterpret_cast<const uint4*>(x + vf * cs + c0 + 8 * q);
+                    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        sum[2 * i] += bf2f((bf16_t)(w[i] & 0xffffu));
+                        sum[2 * i + 1] += bf2f((bf16_t)(w[i] >> 16));
+                    }
                 }
-        y[e] = f2bf(s * 0.125f);
+        uint32_t o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            o[i] = (uint32_t)f2bf(sum[2 * i] * 0.125f) | ((uint32_t)f2bf(sum[2 * i + 1] * 0.125f) << 16);
+        reinterpret_cast<uint4*>(y)[e] = uint4{o[0], o[1], o[2], o[3]};
     }
 }
 
@@ -579,11 +589,12 @@ __global__ void k_make_input(const double* __restrict__ eta, const double* __res
 {
     for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox;
          v += (long)gridDim.x * blockDim.x) {
-        bf16_t* o = x + v * 16;
-        o[0] = f2bf((float)(log(eta[v]) * 0.5));
-        o[1] = f2bf((float)a);
-        o[2] = f2bf((float)cold[v]);
-        for (int c = 3; c < 16; ++c) o[c] = 0;
+        // channels 0, 1, 2 = log(eta)/2, a, cold; 3..15 zero (two 16-byte stores)
+        uint4* o = reinterpret_cast<uint4*>(x + v * 16);
+        const uint32_t c01 = (uint32_t)f2bf((float)(log(eta[v]) * 0.5)) |
+                             ((uint32_t)f2bf((float)a) << 16);
+        o[0] = uint4{c01, (uint32_t)f2bf((float)cold[v]), 0u, 0u};
+        o[1] = uint4{0u, 0u, 0u, 0u};
     }
 }
 
@@ -595,8 +606,15 @@ __global__ void k_head(const bf16_t* __restrict__ d, const float* __restrict__ w
 {
     for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox;
          v += (long)gridDim.x * blockDim.x) {
+        const uint4* dv = reinterpret_cast<const uint4*>(d + v * 16);
+        const uint4 u0 = dv[0], u1 = dv[1];
+        const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
         float s = wh[16];
-        for (int c = 0; c < 16; ++c) s += bf2f(d[v * 16 + c]) * wh[c];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            s += bf2f((bf16_t)(w[i] & 0xffffu)) * wh[2 * i];
+            s += bf2f((bf16_t)(w[i] >> 16)) * wh[2 * i + 1];
+        }
         if (out) out[v] = s;
         if (guess) guess[v] = cold[v] + (double)s;
     }
@@ -865,7 +883,7 @@ int run_forward(const Plan& P, const float* params, hipStream_t s)
                            kConvs[c].cout, 1, P.o[c], nullptr, s);
     };
     auto pool = [&](const bf16_t* x, int lvf, int C, bf16_t* y) -> int {
-        hipLaunchKernelGGL(k_pool2, dim3(grid_of(P.nv[lvf + 1] * C)), dim3(kThreads), 0, s, x,
+        hipLaunchKernelGGL(k_pool2, dim3(grid_of(P.nv[lvf + 1] * C / 8)), dim3(kThreads), 0, s, x,
                            P.n[lvf], C, 0, C, y);
         ULAUNCH("k_pool2");
         return (int)ISIS_OK;
