@@ -161,14 +161,20 @@ constexpr int kLY = 4, kLZ = 64;                   // output tile (y, z)
 constexpr int kLPY = kLY + 2, kLPZ = kLZ + 2;      // with the halo
 constexpr int kLVox = 3 * kLPY * kLPZ;             // staged voxels per slice
 
-template <int CIN, int COUT>
+//
+// CLO > 0: the input is the concatenation [nearest upsampling of lo, x] of a
+// coarse [(n/2)^3][CLO] tensor and a fine [n^3][CIN - CLO] tensor (the
+// decoder's skip), read directly instead of materialised.
+template <int CIN, int COUT, int CLO = 0>
 __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict__ x, int n,
                                                         const bf16_t* __restrict__ w,
                                                         const float* __restrict__ bias, int relu,
                                                         bf16_t* __restrict__ y,
-                                                        float* __restrict__ yf)
+                                                        float* __restrict__ yf,
+                                                        const bf16_t* __restrict__ lo = nullptr)
 {
-    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "whole 16-channel slices");
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0 && CLO % 16 == 0 && CLO < CIN,
+                  "whole 16-channel slices");
     constexpr int NT = COUT / 16;
     __shared__ uint2 tile[4 * kLVox];  // [4-channel group][plane][row][z]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -192,9 +198,20 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
         for (int e = tid; e < kLVox * 2; e += kThreads) {
             const int vox = e >> 1, h = e & 1;
             const int zz = vox % kLPZ, rr = (vox / kLPZ) % kLPY, pp = vox / (kLPZ * kLPY);
-            const long gv = ((long)((x0 - 1 + pp) & msk) * n + ((y0 - 1 + rr) & msk)) * n +
-                            ((z0 - 1 + zz) & msk);
-            const uint4 v = *reinterpret_cast<const uint4*>(x + gv * CIN + c0 + 8 * h);
+            const int xf = (x0 - 1 + pp) & msk, yf_ = (y0 - 1 + rr) & msk, zf = (z0 - 1 + zz) & msk;
+            const bf16_t* src;
+            if constexpr (CLO > 0) {
+                if (c0 < CLO) {
+                    const int nc = n >> 1;
+                    const long V = ((long)(xf >> 1) * nc + (yf_ >> 1)) * nc + (zf >> 1);
+                    src = lo + V * CLO + c0 + 8 * h;
+                } else {
+                    src = x + (((long)xf * n + yf_) * n + zf) * (CIN - CLO) + (c0 - CLO) + 8 * h;
+                }
+            } else {
+                src = x + (((long)xf * n + yf_) * n + zf) * CIN + c0 + 8 * h;
+            }
+            const uint4 v = *reinterpret_cast<const uint4*>(src);
             tile[(2 * h) * kLVox + vox] = uint2{v.x, v.y};
             tile[(2 * h + 1) * kLVox + vox] = uint2{v.z, v.w};
         }
@@ -744,6 +761,24 @@ int launch_conv(const bf16_t* x, int n, int cin, const bf16_t* w, const float* b
     return ISIS_ERR_UNSUPPORTED;
 }
 
+// Convolution of [nearest upsampling of lo (n/2)^3 x clo, skip n^3 x (cin -
+// clo)] without materialising the concatenation (sides n >= 64).
+int launch_conv_cat(const bf16_t* lo, const bf16_t* skip, int n, int cin, int clo,
+                    const bf16_t* w, const float* bias, int cout, int relu, bf16_t* y,
+                    hipStream_t s)
+{
+    if (n < kLZ || !(cin == 48 && clo == 32 && cout == 16)) {
+        uerr("no fused decoder convolution for %d (%d upsampled) -> %d channels at side %d", cin,
+             clo, cout, n);
+        return ISIS_ERR_UNSUPPORTED;
+    }
+    const long lblocks = (long)n * (n / kLY) * (n / kLZ);
+    hipLaunchKernelGGL((k_conv3_lds<48, 16, 32>), dim3((unsigned)lblocks), dim3(kThreads), 0, s,
+                       skip, n, w, bias, relu, y, nullptr, lo);
+    ULAUNCH("k_conv3_lds (concatenated input)");
+    return ISIS_OK;
+}
+
 int dw_chunk(long nvox) { return (int)std::min<long>(nvox, 4096); }
 
 size_t dw_part_floats(long nvox, int cin, int cout)
@@ -868,7 +903,10 @@ Plan make_plan(int n, int training, char* base)
         if (r_ != ISIS_OK) return r_; \
     } while (0)
 
-int run_forward(const Plan& P, const float* params, hipStream_t s)
+// fuse_cat: the last decoder stage reads its upsampled and skip inputs
+// directly (prediction; training keeps the concatenation for the weight
+// gradient).
+int run_forward(const Plan& P, const float* params, hipStream_t s, bool fuse_cat = false)
 {
     for (int c = 0; c < 14; ++c) {
         const long e = 27L * kConvs[c].cin * kConvs[c].cout;
@@ -920,8 +958,13 @@ int run_forward(const Plan& P, const float* params, hipStream_t s)
     TRY(upcat(P.o[9], 2, 64, P.o[3], 32, P.c10));
     TRY(conv(10, P.c10));
     TRY(conv(11, P.o[10]));
-    TRY(upcat(P.o[11], 1, 32, P.o[1], 16, P.c12));
-    TRY(conv(12, P.c12));
+    if (fuse_cat && P.n[0] >= kLZ) {
+        TRY(launch_conv_cat(P.o[11], P.o[1], P.n[0], 48, 32, P.wf[12],
+                            params + param_offset(12) + 27L * 48 * 16, 16, 1, P.o[12], s));
+    } else {
+        TRY(upcat(P.o[11], 1, 32, P.o[1], 16, P.c12));
+        TRY(conv(12, P.c12));
+    }
     TRY(conv(13, P.o[12]));
     return ISIS_OK;
 }
@@ -1029,7 +1072,7 @@ int isis_unet_predict(const float* params, const double* eta, const double* phi_
     hipLaunchKernelGGL(k_make_input, dim3(grid_of(P.nv[0])), dim3(kThreads), 0, s, eta, phi_cold,
                        a, P.nv[0], P.in);
     ULAUNCH("k_make_input");
-    TRY(run_forward(P, params, s));
+    TRY(run_forward(P, params, s, true));
     hipLaunchKernelGGL(k_head, dim3(grid_of(P.nv[0])), dim3(kThreads), 0, s, P.o[13],
                        params + param_offset(14), P.nv[0], out, phi_cold, guess);
     ULAUNCH("k_head");
