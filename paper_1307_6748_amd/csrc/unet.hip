@@ -21,7 +21,10 @@
 // consecutive voxels along z (four 16-voxel M tiles) and all output channels.
 // The data gradient is the same kernel on flipped, transposed weights; the
 // weight gradient is a split-K GEMM over voxel chunks with a fixed-order
-// reduction of the partial sums (deterministic).
+// reduction of the partial sums (deterministic).  On sides >= 64 the input is
+// staged in LDS (k_conv3_lds; k_conv3_ring streams along x for 16 input
+// channels), and the prediction's last decoder convolution reads its
+// upsampled and skip inputs directly instead of a materialised concatenation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
