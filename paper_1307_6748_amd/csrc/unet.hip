@@ -49,6 +49,7 @@ void uerr(const char* fmt, ...)
 
 using bf16_t = uint16_t;
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
     static_assert(CIN % 16 == 0 && COUT % 16 == 0 && CLO % 16 == 0 && CLO < CIN,
                   "whole 16-channel slices");
     constexpr int NT = COUT / 16;
-    __shared__ uint2 tile[4 * kLVox];  // [4-channel group][plane][row][z]
+    __shared__ uint4 tile[2 * kLVox];  // [8-channel half][plane][row][z]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, g = lane >> 4;
     const int msk = n - 1, nyt = n / kLY;
@@ -195,7 +196,11 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
 #pragma unroll
         for (int u = 0; u < NT; ++u) acc[t][u] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const uint2* tg = tile + g * kLVox;  // this lane's k-group
+    // k of the 16x16x32 MFMA = two taps of one slice: lanes g = 0, 1 carry
+    // channels 8g..8g+7 of tap 2p, lanes g = 2, 3 those of tap 2p + 1; the
+    // 27th tap uses the 16x16x16 MFMA (channels 4g..4g+3).
+    const int hh = g & 1, side = g >> 1;
+    const uint4* th = tile + hh * kLVox;  // this lane's 8-channel half
     for (int c0 = 0; c0 < CIN; c0 += 16) {
         if (c0) __syncthreads();  // the previous slice has been consumed
         for (int e = tid; e < kLVox * 2; e += kThreads) {
@@ -214,24 +219,38 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
             } else {
                 src = x + (((long)xf * n + yf_) * n + zf) * CIN + c0 + 8 * h;
             }
-            const uint4 v = *reinterpret_cast<const uint4*>(src);
-            tile[(2 * h) * kLVox + vox] = uint2{v.x, v.y};
-            tile[(2 * h + 1) * kLVox + vox] = uint2{v.z, v.w};
+            tile[h * kLVox + vox] = *reinterpret_cast<const uint4*>(src);
         }
         __syncthreads();
 #pragma unroll
-        for (int tap = 0; tap < 27; ++tap) {
-            // staged plane, row and column offsets of this tap (halo included)
-            const int pi = tap / 9, rj = (tap / 3) % 3, zk = tap % 3;
+        for (int pr = 0; pr < 13; ++pr) {
+            const int tap = 2 * pr + side;
+            const int off = ((tap / 9) * kLPY + wv + (tap / 3) % 3) * kLPZ + m + tap % 3;
+            const bf16_t* wt = w + (long)tap * COUT * CIN;
+            bf8v bw[NT];
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+                bw[u] = *reinterpret_cast<const bf8v*>(wt + (long)(16 * u + m) * CIN + c0 + 8 * hh);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bf8v a = *reinterpret_cast<const bf8v*>(th + off + 16 * t);
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[u], acc[t][u], 0, 0, 0);
+            }
+        }
+        {
+            constexpr int tap = 26;
+            const int off = ((tap / 9) * kLPY + wv + (tap / 3) % 3) * kLPZ + m + tap % 3;
             const bf16_t* wt = w + (long)tap * COUT * CIN;
             s4 bw[NT];
 #pragma unroll
             for (int u = 0; u < NT; ++u)
                 bw[u] = *reinterpret_cast<const s4*>(wt + (long)(16 * u + m) * CIN + c0 + 4 * g);
-            const int base = (pi * kLPY + wv + rj) * kLPZ + m + zk;
+            const uint2* tq = reinterpret_cast<const uint2*>(tile + side * kLVox);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const s4 a = *reinterpret_cast<const s4*>(tg + base + 16 * t);
+                const s4 a = *reinterpret_cast<const s4*>(tq + 2 * (off + 16 * t) + hh);
 #pragma unroll
                 for (int u = 0; u < NT; ++u)
                     acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[u], acc[t][u], 0,
