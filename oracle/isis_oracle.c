@@ -115,7 +115,21 @@ typedef struct {
     double r0;                     /* RMS of L_0 at the initial field       */
     double rel_hist[ORC_MAX_HIST]; /* rel. residual before cycle 1, after each cycle */
     double wall_s;
+    long long guard_hits;          /* symmetron updates with the safeguarded
+                                      denominator (reading R10), all levels      */
 } orc_stats;
+
+/* Running count of symmetron Gauss-Seidel updates at which dS/dchi < 0, i.e.
+ * where the safeguarded denominator of reading R10 differs from the Jacobian.
+ * Reset and reported by orc_solve; readable with orc_guard_hits(). */
+static long long g_guard_hits = 0;
+
+long long orc_guard_hits(int reset)
+{
+    long long v = g_guard_hits;
+    if (reset) g_guard_hits = 0;
+    return v;
+}
 
 /* ------------------------------------------------------------------ */
 /* Pointwise source S(phi, eta) and its derivative dS/dphi.            */
@@ -288,19 +302,26 @@ void orc_halfsweep(const orc_model* m, int n, double h, double* phi, const doubl
                    const double* sigma, int colour)
 {
     long nn = n;
-#pragma omp parallel for schedule(static)
+    long long hits = 0;
+#pragma omp parallel for schedule(static) reduction(+ : hits)
     for (long i = 0; i < nn; ++i)
         for (long j = 0; j < nn; ++j)
             for (long k = (i + j + colour) & 1; k < nn; k += 2) {
                 long c = cidx(nn, i, j, k);
                 double D;
                 double L = op_cell(m, nn, h, phi, eta, i, j, k, &D);
+                if (m->model == ORC_SYMMETRON) {
+                    double S, dS;
+                    orc_source(m, phi[c], eta[c], &S, &dS);
+                    if (dS < 0.0) ++hits;
+                }
                 double eps = L - (sigma ? sigma[c] : 0.0);
                 double step = eps / D;
                 if (m->model == ORC_CHAMELEON) /* reading R15 */
                     step = fmax(-ORC_CHAM_MAX_STEP, fmin(ORC_CHAM_MAX_STEP, step));
                 phi[c] = phi[c] - step;
             }
+    g_guard_hits += hits;
 }
 
 void orc_sweep(const orc_model* m, int n, double h, double* phi, const double* eta,
@@ -541,6 +562,7 @@ int orc_solve(const orc_model* m, const orc_cfg* cfg, int n, double box, const d
     double cold_scale = 1e-14 * 6.0 / (lv[0].h * lv[0].h) * orc_rms(n, cold);
     if (!use_guess) memcpy(phi, cold, sizeof(double) * (size_t)n3);
     free(cold);
+    g_guard_hits = 0;
     double r_norm = r_ref > cold_scale ? r_ref : 1.0;
     int singular = (m->model == ORC_LINEAR && m->m2 == 0.0);
     if (singular) {
@@ -575,6 +597,7 @@ int orc_solve(const orc_model* m, const orc_cfg* cfg, int n, double box, const d
     clock_gettime(CLOCK_MONOTONIC, &t1);
     if (st) {
         st->cycles = cyc;
+        st->guard_hits = g_guard_hits;
         st->wall_s = (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
     }
 

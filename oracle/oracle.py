@@ -59,7 +59,8 @@ class _Cfg(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("r_ref", C.c_double), ("r0", C.c_double),
-                ("rel_hist", C.c_double * MAX_HIST), ("wall_s", C.c_double)]
+                ("rel_hist", C.c_double * MAX_HIST), ("wall_s", C.c_double),
+                ("guard_hits", C.c_longlong)]
 
 
 @dataclass
@@ -107,6 +108,7 @@ class Result:
     r0: float
     rel_hist: np.ndarray = field(default_factory=lambda: np.zeros(0))
     wall_s: float = 0.0
+    guard_hits: int = 0  # symmetron updates with the safeguarded denominator
 
 
 _lib = None
@@ -133,6 +135,8 @@ def lib():
         L.orc_rms.argtypes = [C.c_int, dp]
         L.orc_rms.restype = C.c_double
         L.orc_num_levels.argtypes = [C.c_int]
+        L.orc_guard_hits.argtypes = [C.c_int]
+        L.orc_guard_hits.restype = C.c_longlong
         L.orc_solve.argtypes = [C.POINTER(_Model), C.POINTER(_Cfg), C.c_int, C.c_double, dp,
                                 dp, C.c_int, C.c_double, C.POINTER(_Stats)]
         L.orc_force.argtypes = [C.POINTER(_Model), C.c_int, C.c_double, dp, C.c_void_p, dp, dp,
@@ -242,6 +246,12 @@ def cold_start(m: Model, eta) -> np.ndarray:
     return out
 
 
+def guard_hits(reset: bool = True) -> int:
+    """Symmetron updates made with the safeguarded denominator since the last
+    reset (halfsweep/sweep calls; a solve resets and reports its own)."""
+    return int(lib().orc_guard_hits(1 if reset else 0))
+
+
 def rms(r) -> float:
     r = _f64(r)
     return float(lib().orc_rms(r.shape[0], r))
@@ -265,7 +275,7 @@ def solve(m: Model, eta, box: float, tol: float = 1e-10, phi0=None, cfg: Cfg | N
     if s == INVALID:
         raise ValueError("oracle: invalid arguments")
     hist = np.array(st.rel_hist[: st.cycles + 1])
-    return Result(s, phi, st.cycles, st.r_ref, st.r0, hist, st.wall_s)
+    return Result(s, phi, st.cycles, st.r_ref, st.r0, hist, st.wall_s, int(st.guard_hits))
 
 
 def vcycles(m: Model, eta, box: float, phi0, k: int, cfg: Cfg | None = None) -> Result:

@@ -58,6 +58,12 @@ MUTATIONS = {
         "if (m->model == ORC_FR_HS) {"),
     "chameleon_step_unbounded": ("if (m->model == ORC_CHAMELEON) /* reading R15 */",
                                  "if (0) /* reading R15 */"),
+    "rms_missing_sqrt": ("return sqrt(sumsq(nn, r) / (double)(nn * nn * nn));",
+                         "return sumsq(nn, r) / (double)(nn * nn * nn);"),
+    "rms_cell_count": ("return sqrt(sumsq(nn, r) / (double)(nn * nn * nn));",
+                       "return sqrt(sumsq(nn, r) / (double)(nn * nn));"),
+    "r_ref_not_normalised": ("double r_ref = orc_rms(n, lv[0].work);",
+                             "double r_ref = sqrt(sumsq(n, lv[0].work));"),
     "paper_u_a4_factor": ("- om * a * a * a * a * H2 * g * c * e +",
                           "- om * a * a * a * H2 * g * c * e +"),
     "paper_u_cold_shift_missing": ("if (m->paper_u) phi[c] += log(m->a * m->a * m->fR0_abs);",
@@ -67,6 +73,18 @@ MUTATIONS = {
 }
 PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py", "test_oracle_models.py",
              "test_oracle_newton.py"]
+# The pin file that catches a mutation runs first (the suite stops at its first
+# failure); the other files follow, so every pin still gets its chance.
+FIRST_FILE = {
+    "force_": "test_oracle_force.py",
+    "chameleon_": "test_oracle_models.py",
+    "paper_u_": "test_oracle_models.py",
+}
+
+
+def _pin_order(name):
+    first = next((f for pre, f in FIRST_FILE.items() if name.startswith(pre)), PIN_FILES[0])
+    return [first] + [f for f in PIN_FILES if f != first]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -81,7 +99,7 @@ def test_planted_mistake_fails_a_pin(tmp_path, name):
     O.build(force=True, src=str(mut), out=so)
     env = dict(os.environ, ORACLE_LIB=so, OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] +
-                       [os.path.join(ROOT, "tests", f) for f in PIN_FILES],
+                       [os.path.join(ROOT, "tests", f) for f in _pin_order(name)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, f"{name}: pins did not fail\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout

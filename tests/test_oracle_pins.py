@@ -440,6 +440,66 @@ def test_linear_sine_exact_discrete_solution(orc, m2):
     assert np.max(np.abs(r.phi - exact)) < 1e-11 * np.max(np.abs(exact))
 
 
+def test_rms_and_r_ref_closed_form(orc):
+    """The stop test's norm and reference residual (reading 12): RMS over the
+    N^3 fine cells, r_ref = RMS of L_0 at the cold start.  For the linear model
+    the cold start is phi = 0, so L_0 = -kappa (eta - 1); with eta - 1 = amp s,
+    s a product of sines of modes 0 < m < N/2 at the cell centres, the mean of
+    s^2 over the grid is exactly 1/8, hence r_ref = |kappa| amp 2^(-3/2).
+    From the guess phi0 = c s, L_0 = -(c (lambda_k + m2) + kappa amp) s, so
+    r0 = |c (lambda_k + m2) + kappa amp| 2^(-3/2) while r_ref does not move."""
+    n, box, kappa, amp, m2 = 16, 24.0, -1.7, 0.3, 0.45
+    h = box / n
+    modes = (1, 3, 2)
+    s = synth.sine_mode(n, box, modes)
+    eta = 1.0 + amp * s
+    m = orc.Model(model=orc.LINEAR, kappa=kappa, m2=m2)
+    closed = abs(kappa) * amp * 2.0 ** -1.5
+    r = orc.solve(m, eta, box, tol=1e-30, cfg=orc.Cfg(max_cycles=1))
+    assert abs(r.r_ref - closed) <= 1e-13 * closed
+    assert abs(r.r0 - closed) <= 1e-13 * closed      # cold start: r0 = r_ref
+    assert abs(r.rel_hist[0] - 1.0) <= 1e-13
+    c = 0.37
+    r = orc.solve(m, eta, box, tol=1e-30, phi0=c * s, cfg=orc.Cfg(max_cycles=1))
+    r0 = abs(c * (lam_k(modes, n, h) + m2) + kappa * amp) * 2.0 ** -1.5
+    assert abs(r.r_ref - closed) <= 1e-13 * closed
+    assert abs(r.r0 - r0) <= 1e-12 * r0
+    assert abs(r.rel_hist[0] - r0 / closed) <= 1e-12 * r0 / closed
+    # the norm itself: a constant field and a +-v checkerboard have RMS |v|
+    assert orc.rms(np.full((8, 8, 8), -2.5)) == 2.5
+    i, j, k = np.indices((8, 8, 8))
+    assert abs(orc.rms(3.0 * (-1.0) ** (i + j + k)) - 3.0) <= 1e-15 * 3.0
+
+
+def test_safeguard_count_is_the_number_of_negative_derivatives(orc):
+    """Reading 14: the count of safeguarded updates.  In one red half-sweep
+    every red cell is updated once from its own value before the sweep (cells
+    of one colour never neighbour each other), so the count is the number of
+    red cells with dS/dchi = K (A eta - 1 + 3 chi^2) < 0 at the input field.
+    The linear model has no safeguard and counts nothing; a solve from the
+    cold start at a uniform screened density counts nothing either."""
+    n, box, a, lam, assb = 8, 16.0, 0.8, 1.0, 0.5
+    K, A = a * a / (2 * lam * lam), (assb / a) ** 3
+    phi = 0.4 * synth.random_field(n, 31)
+    eta = 4.0 * synth.random_field(n, 32)
+    m = orc.Model(model=orc.SYMMETRON, a=a, lambda0=lam, a_ssb=assb)
+    i, j, k = np.indices((n, n, n))
+    for colour in (0, 1):
+        orc.guard_hits(reset=True)
+        orc.halfsweep(m, box / n, phi, eta, colour=colour)
+        dS = K * (A * eta - 1.0 + 3.0 * phi ** 2)
+        want = int(np.sum((((i + j + k) & 1) == colour) & (dS < 0)))
+        assert 0 < want < n ** 3 // 2
+        assert orc.guard_hits() == want
+    orc.guard_hits(reset=True)
+    orc.halfsweep(orc.Model(model=orc.LINEAR, kappa=1.0, m2=0.1), box / n, phi, eta)
+    assert orc.guard_hits() == 0
+    r = orc.solve(m, np.full((n, n, n), 3.0 / A), box, tol=1e-10)  # A eta = 3: screened
+    assert r.status == orc.OK and r.guard_hits == 0
+    r = orc.solve(m, eta, box, tol=1e-10, phi0=phi)
+    assert r.status == orc.OK and r.guard_hits > 0
+
+
 def _mats_1d(n, h):
     D = np.zeros((n, n))
     for i in range(n):
