@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define ISIS_MG_ABI_VERSION 1
+#define ISIS_MG_ABI_VERSION 2
 #define ISIS_MG_MAX_HIST 128
 
 typedef enum {
@@ -118,6 +118,11 @@ typedef struct {
     void* stream;      /* hipStream_t                                              */
     void* workspace;   /* device scratch, >= isis_mg_workspace_size bytes          */
     size_t workspace_bytes;
+    double guess_accept;/* use_guess = 2 keeps the caller's field when its RMS
+                          residual is <= guess_accept * r_ref; 0 (the default):
+                          the relative residual after the first V-cycle of the
+                          handle's last converged cold-started solve of the same
+                          model, or 1e-2 before there is one; else in (0, 1]    */
 } isis_mg_desc;
 
 typedef struct {
@@ -145,6 +150,17 @@ typedef struct {
                                      one sweep, or temporal_block sweeps when
                                      blocked                                      */
     int temporal_block;           /* the temporal block the solve used (0..2)     */
+    double rho_hist[ISIS_MG_MAX_HIST]; /* convergence factors: [k] = rel_hist[k] /
+                                     rel_hist[k-1] for 1 <= k <= cycles; [0] = 0  */
+    long long safeguard_hits;     /* ISIS_SYMMETRON: Newton-Gauss-Seidel updates
+                                     (every level, both precisions) at which
+                                     dS/dchi < 0, so that the safeguarded
+                                     denominator -6/h^2 - |dS/dchi| replaced the
+                                     Jacobian -6/h^2 - dS/dchi (Sec. 3.3); each
+                                     cell update counts once; 0 for other models */
+    double ms_smooth;             /* profiling on: summed kernel time of every
+                                     smoothing step of every level, the coarsest
+                                     grid's sweeps included, milliseconds         */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;
@@ -163,14 +179,17 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
  *  density: device, N^3 doubles, eta > 0, read-only.
  *  field:   device, N^3 doubles.  In: initial guess if use_guess != 0, else
  *           ignored (the pointwise homogeneous root is used).  Out: solution.
- *  use_guess: 0 cold start; 1 the caller's field; 2 the caller's field
- *           unless its residual is not below r_ref (or not finite), in which
- *           case the cold start is used (stats->used_guess tells which).
+ *  use_guess: 0 cold start; 1 the caller's field; 2 the caller's field if
+ *           it cannot cost a V-cycle over the cold start: its RMS residual is
+ *           at most desc.guess_accept * r_ref (see isis_mg_desc), else the cold
+ *           start (stats->used_guess tells which).
  *  tol > 0.  stats may be NULL.
  * Symmetron: the positive branch is the one reached from the cold start.
  * ISIS_MIXED: FP32 V-cycles (FP32 fields, FP32 smoothing and coarse-grid
  * work; the f(R) source in FP64), each followed by the FP64 defect of the
- * FP32 iterate on the finest level, while that residual falls by at least
+ * FP32 iterate on the finest level (skipped when the initial field's relative
+ * residual is already <= 1e-6, near the FP32 round-off floor), while that
+ * residual falls by at least
  * 0.6x per cycle, no cycle at a relative residual <= 1e-6 has a factor
  * above both 0.2 and 3x the previous one's (the FP32 round-off floor coming
  * into view: ~2e-7 relative for the symmetron, below 1e-8 for f(R) on the
@@ -178,7 +197,10 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out);
  * default, one more cycle at the last factor rho is not expected to reach tol
  * (residual * rho > 0.7 tol; with desc.fp32_floor set: the residual is above
  * that level); then FP64 V-cycles from the promoted iterate to tol, by default
- * a single one.  The FP64 defect decides convergence in both phases.
+ * a single one.  The FP64 defect decides convergence in both phases.  If the
+ * FP32 cycles fail (residual non-finite or above 1e3 x the initial one) or
+ * end no better than the initial field, the FP64 cycles start from the
+ * initial field instead.
  * Returns ISIS_OK, ISIS_ERR_NOT_CONVERGED (field = last iterate) or
  * ISIS_ERR_DIVERGED (field = last iterate, may be non-finite). */
 int isis_mg_solve(isis_mg_t* h, const double* density, double* field,
@@ -294,6 +316,46 @@ int isis_unet_train_step(float* params, float* adam_m, float* adam_v, int step, 
                          const double* eta, const double* phi_cold, const double* phi_target,
                          double a, int n, void* workspace, size_t workspace_bytes,
                          float* loss_out, float* grad_out, void* stream);
+
+/* The training step in its three parts (the same kernels; isis_unet_train_step
+ * is forward + backward + Adam).  They share a training-size workspace
+ * (isis_unet_workspace_size(n, 1)), which carries the activations from
+ * isis_unet_forward to isis_unet_backward; calls on one workspace must not
+ * overlap.
+ *
+ * isis_unet_forward: the network on (log eta, a, phi_cold), every activation
+ * kept in the workspace (bf16), the head output (FP32) also in out (device n^3
+ * floats, may be NULL). */
+int isis_unet_forward(const float* params, const double* eta, const double* phi_cold, double a,
+                      int n, float* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* isis_unet_backward: after isis_unet_forward on the same workspace, the
+ * gradient of loss = mean((out - (phi_target - phi_cold))^2) with respect to
+ * params (ReLU, pooling, upsampling, concatenation and the 14 convolutions:
+ * data gradients by the adjoint convolution, weight gradients by fixed-order
+ * sums, so the result is deterministic).  grad: device FP32 vector of
+ * isis_unet_param_count() entries (may be NULL: the gradient then stays in the
+ * workspace for isis_unet_train_step).  loss_out (host, may be NULL) receives
+ * the loss (synchronises the stream). */
+int isis_unet_backward(const float* params, const double* phi_cold, const double* phi_target,
+                       int n, void* workspace, size_t workspace_bytes, float* grad,
+                       float* loss_out, void* stream);
+
+/* isis_unet_adam_step: one Adam update of count parameters in place (beta1
+ * 0.9, beta2 0.999, eps 1e-8, bias correction with the 1-based step):
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * All four arrays are device FP32. */
+int isis_unet_adam_step(float* params, const float* grad, float* adam_m, float* adam_v,
+                        long count, int step, float lr, void* stream);
+
+/* A tensor of a training-size workspace after isis_unet_forward (for
+ * inspection): *ptr = its device address, *voxels and *channels its shape
+ * (channels-last bf16, except id 21).  id 0..13: output of convolution id
+ * (after bias and ReLU); 14: the input; 15, 16, 17: the pooled inputs of
+ * levels 1, 2, 3; 18, 19, 20: the concatenations [upsampled, skip] read by
+ * convolutions 8, 10, 12; 21: the head output (FP32). */
+int isis_unet_tensor(void* workspace, int n, int id, void** ptr, long* voxels, int* channels);
 
 /* Message of the last error of the isis_unet_* / isis_conv3_* calls
  * (thread-local). */

@@ -30,8 +30,9 @@ class ModelParamsC(C.Structure):
 class DescC(C.Structure):
     _fields_ = [("N", C.c_int), ("box", C.c_double), ("nu_pre", C.c_int), ("nu_post", C.c_int),
                 ("nu_coarse", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int),
-                ("fp32_floor", C.c_double), ("temporal_block", C.c_int), ("stream", C.c_void_p), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t)]
+                ("fp32_floor", C.c_double), ("temporal_block", C.c_int), ("stream", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("guess_accept", C.c_double)]
 
 
 class StatsC(C.Structure):
@@ -41,7 +42,8 @@ class StatsC(C.Structure):
                 ("cell_updates", C.c_double), ("used_guess", C.c_int),
                 ("fine_sweep_ms", C.c_double * 2), ("fine_sweep_launches", C.c_int * 2),
                 ("fine_sweep_updates", C.c_double * 2), ("fine_sweep_bytes", C.c_double * 2),
-                ("temporal_block", C.c_int)]
+                ("temporal_block", C.c_int), ("rho_hist", C.c_double * MAX_HIST),
+                ("safeguard_hits", C.c_longlong), ("ms_smooth", C.c_double)]
 
 
 _lib = None
@@ -73,6 +75,11 @@ SIGNATURES = [
     ("isis_unet_predict", _I, [_P, _P, _P, _D, _I, _P, _P, _P, C.c_size_t, _P]),
     ("isis_unet_train_step", _I, [_P, _P, _P, _I, C.c_float, _P, _P, _P, _D, _I, _P, C.c_size_t,
                                   C.POINTER(C.c_float), _P, _P]),
+    ("isis_unet_forward", _I, [_P, _P, _P, _D, _I, _P, _P, C.c_size_t, _P]),
+    ("isis_unet_backward", _I, [_P, _P, _P, _I, _P, C.c_size_t, _P, C.POINTER(C.c_float), _P]),
+    ("isis_unet_adam_step", _I, [_P, _P, _P, _P, C.c_long, _I, C.c_float, _P]),
+    ("isis_unet_tensor", _I, [_P, _I, _I, C.POINTER(_P), C.POINTER(C.c_long),
+                              C.POINTER(_I)]),
     ("isis_unet_last_error", C.c_char_p, []),
     ("isis_conv3_fwd", _I, [_P, _I, _I, _P, _P, _I, _I, _P, _P, _P]),
     ("isis_conv3_flip_weights", _I, [_P, _I, _I, _P, _P]),

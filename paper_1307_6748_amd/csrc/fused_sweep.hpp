@@ -161,6 +161,11 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
     unsigned goff[NK][G::MAXI][2];
     int loff[NK][G::MAXI][2];
     int zoff[NK][G::MAXI][2];  // LDS offset of the z- neighbour; z+ is the next word
+    // Safeguard counting (models with kGuard): bit (k-1, q, pb) is set when the
+    // item's cell lies in this workgroup's own TY x TZ tile, so updates of the
+    // halo, which neighbouring tiles also make, are counted once.
+    static_assert(!M::kGuard || NK * G::MAXI * 2 <= 32, "ownership mask needs 32 bits");
+    unsigned own = 0;
     static_for<0, NK>([&](auto kc) {
         constexpr int k = decltype(kc)::value + 1;
         constexpr int colour = (k - 1) & 1;  // stages 1, 3: red; 2, 4: black
@@ -178,6 +183,10 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                                                  ((z0 - G::H + c) & msk)) * SZ);
                 loff[k - 1][q][pb] = lds(r, c);
                 zoff[k - 1][q][pb] = lds(r, c - 1);  // lds(r, c + 1) == lds(r, c - 1) + 1
+                if constexpr (M::kGuard) {
+                    const bool mine = r >= G::H && r < G::H + TY && c >= G::H && c < G::H + TZ;
+                    own |= (mine ? 1u : 0u) << (((k - 1) * G::MAXI + q) * 2 + pb);
+                }
             }
         });
     });
@@ -193,6 +202,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
         wl[j] = lds(G::H + rr, G::H + 2 * cp);  // even column (H is even)
     }
 
+    unsigned hits = 0;  // safeguard activations on owned cells (kGuard models)
     V pA[G::LPT], pB[G::LPT];
     T eA[NK][G::MAXI], eB[NK][G::MAXI];
     T sA[SIG ? NK : 1][SIG ? G::MAXI : 1], sB[SIG ? NK : 1][SIG ? G::MAXI : 1];
@@ -278,6 +288,11 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                             SO::eval(m, pc, nb, xcur[o], enb, e[k - 1][q], ih2, L, D);
                         } else {
                             SO::eval(m, pc, nb, T(0), nullptr, e[k - 1][q], ih2, L, D);
+                        }
+                        if constexpr (M::kGuard) {
+                            constexpr int bit = ((k - 1) * G::MAXI + q) * 2 + PB;
+                            if ((own >> bit) & 1u)
+                                hits += (p >= x0 && p < x1) ? m.guarded(pc, e[k - 1][q]) : 0u;
                         }
                         T eps = L;
                         if constexpr (SIG) eps -= sg[k - 1][q];
@@ -375,6 +390,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
             }
         });
     }
+    guard_flush(m, hits);
 }
 
 // ---------------------------------------------------------------------------

@@ -112,13 +112,15 @@ bool valid_params(const isis_model_params* p, double a, char* err)
     return true;
 }
 
+// hits: device counter of safeguard activations (NULL: not counted).
 template <class T>
-Symmetron<T> make_symmetron(const isis_model_params& p, double a)
+Symmetron<T> make_symmetron(const isis_model_params& p, double a,
+                            unsigned long long* hits = nullptr)
 {
     double K = a * a / (2.0 * p.lambda0 * p.lambda0);
     double r = p.a_ssb / a;
     double A = r * r * r;
-    return Symmetron<T>{(T)K, (T)A};
+    return Symmetron<T>{(T)K, (T)A, hits};
 }
 
 // Hu-Sawicki f(R), Sec. 4.2.  In u = ln(f_R/f_R0):
@@ -374,18 +376,24 @@ struct isis_mg {
     LevP<double> L64[kMaxLevels];
     LevP<float> L32[kMaxLevels];
     double* partial;  // kReduceBlocks
-    double* scal;     // 16
+    double* scal;     // 16: [0] reduction result, [8] safeguard counter (64-bit)
     double* host;     // pinned, 16
     double* tmp0;     // finest-level scratch field (workspace)
     char err[512];
-    // finest-level sweep timing
-    static constexpr int kMaxTimed = 2 * ISIS_MG_MAX_HIST + 8;
+    // smoothing timing (profiling on): one event pair per smoothing step of
+    // any level, created on the first isis_mg_set_profiling(h, 1)
+    static constexpr int kMaxTimed = 2048;
     int tb;  // temporal block of the current solve (desc.temporal_block resolved)
     int profile;
     int ntimed;
+    int events_ready;
     hipEvent_t ev0[kMaxTimed], ev1[kMaxTimed];
-    int tlaunch[kMaxTimed], tprec[kMaxTimed];  // tprec: 0 FP64, 1 FP32
+    int tlaunch[kMaxTimed], tprec[kMaxTimed], tlevel[kMaxTimed];  // tprec: 0 FP64, 1 FP32
     double tupd[kMaxTimed], tbytes[kMaxTimed];
+    // use_guess = 2: relative residual after the first V-cycle of the last
+    // cold-started solve of each model on this handle (0: none yet)
+    double cold_first[4];
+    unsigned long long* hits() const { return reinterpret_cast<unsigned long long*>(scal + 8); }
 };
 
 namespace {
@@ -475,6 +483,10 @@ bool valid_desc(const isis_mg_desc* d, char* err)
         fmt_err(err, "fp32_floor must be 0 (default) or in [1e-12, 1]");
         return false;
     }
+    if (!(d->guess_accept == 0.0 || (d->guess_accept > 0.0 && d->guess_accept <= 1.0))) {
+        fmt_err(err, "guess_accept must be 0 (automatic) or in (0, 1]");
+        return false;
+    }
     return true;
 }
 
@@ -520,13 +532,14 @@ int sub_mean(isis_mg* H, T* f, long n3)
     return ISIS_OK;
 }
 
-// Smoothing step of level l; on the finest level with profiling on, the
-// launches are bracketed by HIP events on the solver stream.
+// Smoothing step of level l; with profiling on, the launches are bracketed by
+// HIP events on the solver stream (all levels; the finest level's are also
+// reported per precision).
 template <class T, class M>
 int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
 {
     const int tb = H->tb;
-    const bool timed = H->profile && l == 0 && count > 0 && H->ntimed < isis_mg::kMaxTimed;
+    const bool timed = H->profile && count > 0 && H->ntimed < isis_mg::kMaxTimed;
     const int q = H->ntimed;
     if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
     int r = launch_sweeps<T, M>(m, f.n, f.h, &f.phi, &f.tmp, f.eta, f.sigma, count, tb, H->s,
@@ -542,6 +555,7 @@ int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
         H->tupd[q] = n3 * count;
         H->tbytes[q] = (double)passes * n3 * 3.0 * sizeof(T);
         H->tprec[q] = sizeof(T) == 4 ? 1 : 0;
+        H->tlevel[q] = l;
         H->ntimed = q + 1;
     }
     return ISIS_OK;
@@ -556,7 +570,21 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
     int r;
     if (l == H->nlev - 1) {
         *updates += (double)d.nu_coarse * n3;
-        return launch_coarse<T, M>(m, f.h, f.phi, f.eta, f.sigma, d.nu_coarse, H->s, H->err);
+        const bool timed = H->profile && H->ntimed < isis_mg::kMaxTimed;
+        const int q = H->ntimed;
+        if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
+        if ((r = launch_coarse<T, M>(m, f.h, f.phi, f.eta, f.sigma, d.nu_coarse, H->s, H->err)))
+            return r;
+        if (timed) {
+            HIP_TRY(H->err, hipEventRecord(H->ev1[q], H->s));
+            H->tlaunch[q] = 1;
+            H->tupd[q] = (double)d.nu_coarse * n3;
+            H->tbytes[q] = 0.0;
+            H->tprec[q] = sizeof(T) == 4 ? 1 : 0;
+            H->tlevel[q] = l;
+            H->ntimed = q + 1;
+        }
+        return ISIS_OK;
     }
     LevP<T>& c = L[l + 1];
     const int tb = H->tb;
@@ -593,6 +621,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     const bool mixed = (d.precision == ISIS_MIXED);
     int r;
     H->ntimed = 0;
+    HIP_TRY(H->err, hipMemsetAsync(H->hits(), 0, sizeof(unsigned long long), H->s));
     H->L64[0].phi = field;
     H->L64[0].tmp = H->tmp0;
     H->L64[0].eta = const_cast<double*>(density);
@@ -639,8 +668,16 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     LevP<double>& F = H->L64[0];  // F.phi: the current finest field (may move to tmp0)
     double r0 = r_ref;            // the field is the cold start (zero-mean for LINEAR m2 = 0)
     if (use_guess && (r = fine_rms<double, M64>(H, m64, field, density, nullptr, &r0))) return r;
-    if (use_guess == 2 && !(r0 < r_ref)) {
-        // the supplied guess is no better than the cold start: use the latter
+    // use_guess = 2: keep the guess only if it is at least as close to the
+    // root as one cold-started V-cycle gets (so that it cannot cost a cycle):
+    // RMS residual <= accept * r_ref, accept = desc.guess_accept, else the
+    // first-cycle factor of this handle's last cold solve of the model, else
+    // 1e-2 (the first cold cycle reduces the residual by ~100x or more on the
+    // lognormal + halo densities).
+    const double accept = d.guess_accept > 0.0 ? d.guess_accept
+                          : H->cold_first[p.model] > 0.0 ? H->cold_first[p.model] : 1e-2;
+    if (use_guess == 2 && !(r0 <= accept * r_ref)) {
+        // the supplied guess cannot save a cycle over the cold start: use the latter
         HIP_TRY(H->err, hipMemcpyAsync(field, cold, sizeof(double) * n3,
                                        hipMemcpyDeviceToDevice, H->s));
         if (singular && (r = sub_mean<double>(H, field, n3))) return r;
@@ -654,14 +691,17 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         st->used_guess = use_guess ? 1 : 0;
     }
     double updates = 0.0, rcur = r0;
+    double first_rel = 0.0;  // relative residual after the first cycle
     int cyc = 0, cyc32 = 0;
     int status = ISIS_ERR_NOT_CONVERGED;
     if (!std::isfinite(r0)) status = ISIS_ERR_DIVERGED;
     else if (r0 <= tol * rnorm) status = ISIS_OK;
 
     // Mixed precision, phase 1: FP32 V-cycles on the FP32 copy of the
-    // problem, monitored by the FP64 defect of the FP32 iterate.
-    if (mixed && status == ISIS_ERR_NOT_CONVERGED) {
+    // problem, monitored by the FP64 defect of the FP32 iterate.  Skipped when
+    // the initial field is already near the FP32 round-off floor, where FP32
+    // cycles cannot lower the residual.
+    if (mixed && status == ISIS_ERR_NOT_CONVERGED && r0 > kFloorJumpMax * rnorm) {
         {  // the coarsest density (the finer ones came with the restrictions)
             const int l = H->nlev - 1;
             long c3 = (long)H->L32[l].n * H->L32[l].n * H->L32[l].n;
@@ -687,6 +727,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         const bool predict = !(d.fp32_floor > 0.0);
         const double fp32_floor = predict ? 0.0 : d.fp32_floor;
         double rprev = r0, rho_prev = 1.0;
+        bool fp32_failed = false;
         while (cyc < d.max_cycles) {
             if ((r = vcycle<float, M32>(H, m32, H->L32, 0, &updates))) return r;
             if (singular && (r = sub_mean<float>(H, H->L32[0].phi, n3))) return r;
@@ -697,9 +738,12 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                                           M32::kVarInv, shift32)))
                 return r;
             if (st) st->rel_hist[cyc] = rc / rnorm;
+            if (cyc == 1) first_rel = rc / rnorm;
             rcur = rc;
             if (!std::isfinite(rc) || rc > 1e3 * r0) {
-                status = ISIS_ERR_DIVERGED;
+                // the FP32 cycles failed: the FP64 cycles start over from the
+                // FP64 field, which the FP32 phase has not touched
+                fp32_failed = true;
                 break;
             }
             if (rc <= tol * rnorm) {
@@ -722,9 +766,16 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             rho_prev = rho;
             rprev = rc;
         }
-        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
-                           n3, H->L32[0].phi, F.phi, M32::kVarInv, shift32);
-        LAUNCH_CHECK(H->err, "k_convert");
+        // Promote the FP32 iterate unless it is no better than the field the
+        // phase started from (then the FP64 cycles continue from that field).
+        if (!fp32_failed && rcur < r0) {
+            hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0,
+                               H->s, n3, H->L32[0].phi, F.phi, M32::kVarInv, shift32);
+            LAUNCH_CHECK(H->err, "k_convert");
+        } else {
+            status = ISIS_ERR_NOT_CONVERGED;
+            rcur = r0;
+        }
     }
 
     // FP64 V-cycles (the whole solve in ISIS_FP64; the refinement phase in
@@ -736,6 +787,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         double rc;
         if ((r = fine_rms<double, M64>(H, m64, F.phi, density, nullptr, &rc))) return r;
         if (st) st->rel_hist[cyc] = rc / rnorm;
+        if (cyc == 1) first_rel = rc / rnorm;
         rcur = rc;
         if (!std::isfinite(rc) || rc > 1e3 * r0) status = ISIS_ERR_DIVERGED;
         else if (rc <= tol * rnorm) status = ISIS_OK;
@@ -746,11 +798,16 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         F.tmp = F.phi;
         F.phi = field;
     }
+    unsigned long long* hits_host = reinterpret_cast<unsigned long long*>(H->host + 8);
+    HIP_TRY(H->err, hipMemcpyAsync(hits_host, H->hits(), sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, H->s));
     HIP_TRY(H->err, hipStreamSynchronize(H->s));
     if (st && H->profile) {
         for (int q = 0; q < H->ntimed; ++q) {
             float e = 0.f;
             HIP_TRY(H->err, hipEventElapsedTime(&e, H->ev0[q], H->ev1[q]));
+            st->ms_smooth += e;
+            if (H->tlevel[q] != 0) continue;
             const int k = H->tprec[q];
             st->fine_sweep_ms[k] += e;
             st->fine_sweep_launches[k] += H->tlaunch[q];
@@ -758,11 +815,17 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             st->fine_sweep_bytes[k] += H->tbytes[q];
         }
     }
+    if (!use_guess && status == ISIS_OK && first_rel > 0.0 && first_rel < 1.0)
+        H->cold_first[p.model] = first_rel;
     if (st) {
         st->cycles = cyc;
         st->cycles_fp32 = cyc32;
         st->rel_res = rcur / rnorm;
         st->cell_updates = updates;
+        st->safeguard_hits = (long long)*hits_host;
+        for (int k = 1; k <= cyc; ++k)
+            st->rho_hist[k] = st->rel_hist[k - 1] > 0.0 ? st->rel_hist[k] / st->rel_hist[k - 1]
+                                                        : 0.0;
     }
     if (status == ISIS_ERR_NOT_CONVERGED)
         fmt_err(H->err, "not converged after %d cycles (rel. residual %.3e)", cyc, rcur / rnorm);
@@ -845,13 +908,6 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out)
         delete H;
         return ISIS_ERR_HIP;
     }
-    for (int q = 0; q < isis_mg::kMaxTimed; ++q) {
-        if (hipEventCreate(&H->ev0[q]) != hipSuccess || hipEventCreate(&H->ev1[q]) != hipSuccess) {
-            fmt_err(g_err, "hipEventCreate failed");
-            isis_mg_destroy(H);
-            return ISIS_ERR_HIP;
-        }
-    }
     carve(*desc, (char*)desc->workspace, H);
     *out = H;
     return ISIS_OK;
@@ -862,6 +918,15 @@ int isis_mg_set_profiling(isis_mg_t* h, int enable)
     if (!h) {
         fmt_err(g_err, "handle is NULL");
         return ISIS_ERR_INVALID_ARG;
+    }
+    if (enable && !h->events_ready) {
+        if (hipSetDevice(h->device) != hipSuccess)
+            return hip_fail(h->err, hipGetLastError(), "hipSetDevice");
+        for (int q = 0; q < isis_mg::kMaxTimed; ++q) {
+            if (!h->ev0[q]) HIP_TRY(h->err, hipEventCreate(&h->ev0[q]));
+            if (!h->ev1[q]) HIP_TRY(h->err, hipEventCreate(&h->ev1[q]));
+        }
+        h->events_ready = 1;
     }
     h->profile = enable ? 1 : 0;
     return ISIS_OK;
@@ -914,8 +979,9 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
     int r;
     switch (params->model) {
     case ISIS_SYMMETRON:
-        r = solve_impl(H, make_symmetron<double>(*params, a), make_symmetron<float>(*params, a),
-                       *params, density, field, tol, use_guess, stats);
+        r = solve_impl(H, make_symmetron<double>(*params, a, H->hits()),
+                       make_symmetron<float>(*params, a, H->hits()), *params, density, field, tol,
+                       use_guess, stats);
         break;
     case ISIS_FR_HS: {
         isis_model_params q = *params;  // FP32 cycles in ln(f_R/f_R0) (see solve_impl)

@@ -89,6 +89,20 @@ __device__ __forceinline__ T gather(const T* __restrict__ f, int n, int i, int j
     return f[cell(n, i, j, k)];
 }
 
+// Adds this wave's safeguard activations (per-lane counts) to the model's
+// device counter: a wave64 sum, then one 64-bit atomic per wave.  Integer
+// sums do not depend on the order, so the total is deterministic.  Every lane
+// of the wave must call it.
+template <class M>
+__device__ __forceinline__ void guard_flush(const M& m, unsigned cnt)
+{
+    if constexpr (M::kGuard) {
+        if (!m.hits) return;
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+        if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(m.hits, (unsigned long long)cnt);
+    }
+}
+
 // One colour of a red-black Newton-Gauss-Seidel sweep, in place (Sec. 3.2).
 // Cells of one colour only read cells of the other colour, so the update is
 // race-free and independent of the order.
@@ -99,6 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_halfsweep(M m, int n, T ih2, T* __re
 {
     const int hn = n >> 1;
     const long total = (long)n * n * hn;
+    unsigned hits = 0;
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (long)gridDim.x * blockDim.x) {
         int kk = (int)(t % hn);
@@ -110,10 +125,13 @@ __global__ __launch_bounds__(kBlock) void k_halfsweep(M m, int n, T ih2, T* __re
         T p = gather(phi, n, i, j, k, nb);
         long c = cell(n, i, j, k);
         T L, D;
-        m.op(p, nb, eta[c], ih2, L, D);
+        const T e = eta[c];
+        m.op(p, nb, e, ih2, L, D);
+        if constexpr (M::kGuard) hits += m.guarded(p, e);
         T eps = L - (sigma ? sigma[c] : T(0));
         phi[c] = p - m.limit(eps / D);
     }
+    guard_flush(m, hits);
 }
 
 // out = L(phi) - sigma.
@@ -380,6 +398,7 @@ __global__ __launch_bounds__(64) void k_coarse_solve(M m, T ih2, T* __restrict__
     const T e = eta[t];
     const T s = sigma ? sigma[t] : T(0);
     __syncthreads();
+    unsigned hits = 0;
     for (int it = 0; it < nu_c; ++it) {
         for (int colour = 0; colour < 2; ++colour) {
             if (((i + j + k) & 1) == colour) {
@@ -387,12 +406,14 @@ __global__ __launch_bounds__(64) void k_coarse_solve(M m, T ih2, T* __restrict__
                 T p = gather(f, 4, i, j, k, nb);
                 T L, D;
                 m.op(p, nb, e, ih2, L, D);
+                if constexpr (M::kGuard) hits += m.guarded(p, e);
                 f[t] = p - m.limit((L - s) / D);
             }
             __syncthreads();
         }
     }
     phi[t] = f[t];
+    guard_flush(m, hits);
 }
 
 // The cold start written into phi64, its FP32 copy (cold - shift) * kVar into

@@ -31,18 +31,32 @@ __device__ __forceinline__ T lap7(T p, const T nb[6], T ih2)
 // Newton step would point away from the positive branch on coarse grids
 // (K h^2 >> 6), so the denominator is safeguarded as -6/h^2 - |dS/dchi|;
 // this changes only the iteration, not the root.
+//
+// kGuard: the smoothing kernels count the Gauss-Seidel updates at which the
+// safeguard is active (dS/dchi < 0) into *hits when hits is not NULL.
 template <class T>
 struct Symmetron {
     static constexpr double kVar = 1.0, kVarInv = 1.0;  // stored value = phi
+    static constexpr bool kGuard = true;
     T K, A;
+    unsigned long long* hits;  // safeguard activations (device counter), or NULL
     __device__ __forceinline__ T limit(T step) const { return step; }
+    __device__ __forceinline__ T dsource(T p, T eta) const
+    {
+        return K * (A * eta - T(1) + T(3) * p * p);
+    }
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
         T lap = lap7(p, nb, ih2);
         T S = K * (A * eta * p - p + p * p * p);
-        T dS = K * (A * eta - T(1) + T(3) * p * p);
+        T dS = dsource(p, eta);
         L = lap - S;
         D = -T(6) * ih2 - fabs(dS);
+    }
+    // 1 if the safeguard replaced dS/dchi by |dS/dchi| at this cell
+    __device__ __forceinline__ unsigned guarded(T p, T eta) const
+    {
+        return dsource(p, eta) < T(0) ? 1u : 0u;
     }
     __device__ __forceinline__ T cold(T eta) const
     {
@@ -143,6 +157,8 @@ struct FofR {
     static constexpr bool kW = sizeof(T) == 4;    // carried as w = u / ln 2
     static constexpr double kVar = kW ? kLog2e : 1.0;     // stored value = u * kVar
     static constexpr double kVarInv = kW ? kLn2 : 1.0;    // u = stored value * kVarInv
+    static constexpr bool kGuard = false;  // no safeguard: D < 0 always
+    __device__ __forceinline__ unsigned guarded(T, T) const { return 0u; }
     double Q, cLa3, c1, inv_np1;
     double a3, cL, np1;  // for the cold start
     double ushift;       // added to the cold start (variable offset)
@@ -240,7 +256,9 @@ struct FofR {
 template <class T>
 struct Linear {
     static constexpr double kVar = 1.0, kVarInv = 1.0;  // stored value = phi
+    static constexpr bool kGuard = false;
     T kappa, m2;
+    __device__ __forceinline__ unsigned guarded(T, T) const { return 0u; }
     __device__ __forceinline__ T limit(T step) const { return step; }
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {

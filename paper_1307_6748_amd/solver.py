@@ -110,13 +110,17 @@ class Stats:
     fine_sweep_updates: list = field(default_factory=lambda: [0.0, 0.0])
     fine_sweep_bytes: list = field(default_factory=lambda: [0.0, 0.0])
     temporal_block: int = 0  # the temporal block the solve used
+    rho_hist: list = field(default_factory=list)  # per-cycle factors, [0] = 0
+    safeguard_hits: int = 0  # symmetron: updates with the safeguarded denominator
+    ms_smooth: float = 0.0   # profiling on: all smoothing kernels, all levels
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
         return Stats(status, s.cycles, s.cycles_fp32, s.r_ref, s.r0, s.rel_res,
                      list(s.rel_hist[: s.cycles + 1]), s.ms_total, s.cell_updates,
                      bool(s.used_guess), list(s.fine_sweep_ms), list(s.fine_sweep_launches),
-                     list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block)
+                     list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block,
+                     list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth)
 
 
 def _ptr(t: torch.Tensor | None):
@@ -147,12 +151,13 @@ class Solver:
 
     def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = 2,
                  nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
-                 temporal_block: int = -1, fp32_floor: float = 0.0):
+                 temporal_block: int = -1, fp32_floor: float = 0.0, guess_accept: float = 0.0):
         self.N, self.box = int(N), float(box)
         self._h = None
         lib = A.lib()
         d = A.DescC(self.N, self.box, nu_pre, nu_post, nu_coarse, max_cycles,
-                    PRECISIONS[precision], float(fp32_floor), temporal_block, _stream(), None, 0)
+                    PRECISIONS[precision], float(fp32_floor), temporal_block, _stream(), None, 0,
+                    float(guess_accept))
         nbytes = lib.isis_mg_workspace_size(C.byref(d))
         if nbytes == 0:
             raise ValueError("invalid solver description (N, box, nu_*, max_cycles, precision, "
@@ -192,7 +197,9 @@ class Solver:
               check: bool = True) -> tuple[torch.Tensor, Stats]:
         """Solve L(phi, eta) = 0.  If `phi` is given it receives the solution.
         use_guess: False/0 cold start; True/1 start from `phi`; 2 start from
-        `phi` unless its residual is not below the cold start's."""
+        `phi` only if it cannot cost a V-cycle over the cold start (its
+        residual is at most guess_accept, or the handle's measured first-cycle
+        factor, times r_ref)."""
         _check_field(eta, self.N, "eta")
         if phi is None:
             phi = torch.empty_like(eta)

@@ -53,7 +53,8 @@ def test_workspace_size_validation():
                 dict(nu_coarse=0), dict(max_cycles=0), dict(max_cycles=A.MAX_HIST),
                 dict(precision=7), dict(temporal_block=3), dict(temporal_block=-2), dict(nu_pre=0, nu_post=0),
                 dict(fp32_floor=-1e-6), dict(fp32_floor=2.0), dict(fp32_floor=1e-13),
-                dict(fp32_floor=float("nan"))):
+                dict(fp32_floor=float("nan")), dict(guess_accept=-0.1),
+                dict(guess_accept=1.5), dict(guess_accept=float("nan"))):
         assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad
 
 
@@ -135,3 +136,47 @@ def test_force_validates_on_host():
         A.ISIS_ERR_UNSUPPORTED
     assert b"chameleon" in lib.isis_mg_last_error(None)
     assert lib.isis_force(C.byref(fr), 1.0, 8, 1.0, ok, None, ok, bad, ok, None) == -1
+
+
+def test_unet_training_parts_reject_bad_arguments_without_gpu():
+    """The split training step (forward, backward, Adam) and the tensor
+    accessor validate their arguments before any GPU work."""
+    lib = A.lib()
+    buf = C.c_void_p(256)  # never dereferenced: every call below fails validation
+    P = C.c_void_p
+    assert lib.isis_unet_forward(None, buf, buf, 1.0, 32, None, buf, 1 << 40, None) == \
+        A.ISIS_ERR_INVALID_ARG
+    assert lib.isis_unet_forward(buf, buf, buf, 1.0, 24, None, buf, 1 << 40, None) == \
+        A.ISIS_ERR_INVALID_ARG
+    assert lib.isis_unet_forward(buf, buf, buf, 0.0, 32, None, buf, 1 << 40, None) == \
+        A.ISIS_ERR_INVALID_ARG
+    small = lib.isis_unet_workspace_size(32, 1) - 1
+    assert lib.isis_unet_forward(buf, buf, buf, 1.0, 32, None, buf, small, None) == \
+        A.ISIS_ERR_INVALID_ARG
+    assert lib.isis_unet_backward(buf, None, buf, 32, buf, 1 << 40, None, None, None) == \
+        A.ISIS_ERR_INVALID_ARG
+    assert lib.isis_unet_backward(buf, buf, buf, 32, buf, small, None, None, None) == \
+        A.ISIS_ERR_INVALID_ARG
+    for bad in ((None, buf, buf, buf, 10, 1, 1e-3), (buf, buf, buf, buf, -1, 1, 1e-3),
+                (buf, buf, buf, buf, 10, 0, 1e-3), (buf, buf, buf, buf, 10, 1, -1.0)):
+        assert lib.isis_unet_adam_step(*bad, None) == A.ISIS_ERR_INVALID_ARG, bad
+    assert lib.isis_unet_adam_step(buf, buf, buf, buf, 0, 1, 1e-3, None) == A.ISIS_OK
+    ptr, vox, ch = P(), C.c_long(), C.c_int()
+    for bad in ((None, 32, 0), (buf, 24, 0), (buf, 32, -1), (buf, 32, 22)):
+        assert lib.isis_unet_tensor(*bad, C.byref(ptr), C.byref(vox), C.byref(ch)) == \
+            A.ISIS_ERR_INVALID_ARG, bad
+    # the layout is host arithmetic: shapes of the tensors of a 32^3 workspace
+    base = 1 << 20
+    shapes = {}
+    for tid in range(22):
+        assert lib.isis_unet_tensor(C.c_void_p(base), 32, tid, C.byref(ptr), C.byref(vox),
+                                    C.byref(ch)) == A.ISIS_OK
+        shapes[tid] = (vox.value, ch.value, ptr.value)
+    assert shapes[0][:2] == (32 ** 3, 16) and shapes[7][:2] == (4 ** 3, 64)
+    assert shapes[8][:2] == (8 ** 3, 64) and shapes[12][:2] == (32 ** 3, 16)
+    assert shapes[14][:2] == (32 ** 3, 16) and shapes[17][:2] == (4 ** 3, 64)
+    assert shapes[18][:2] == (8 ** 3, 128) and shapes[20][:2] == (32 ** 3, 48)
+    assert shapes[21][:2] == (32 ** 3, 1)
+    ends = sorted((p, p + v * c * (4 if t == 21 else 2)) for t, (v, c, p) in shapes.items())
+    assert all(b[0] >= a[1] for a, b in zip(ends, ends[1:]))  # disjoint
+    assert ends[-1][1] <= base + lib.isis_unet_workspace_size(32, 1)

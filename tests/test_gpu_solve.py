@@ -212,7 +212,8 @@ def test_not_converged_and_errors(orc):
     assert e.value.code == -1
 
 
-@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "linear", "chameleon", "fofr_paper_u"])
+@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "fofr_a07", "linear", "chameleon",
+                                  "fofr_paper_u"])
 @pytest.mark.parametrize("n", [64, 256])
 def test_mixed_fp32_cycles_match(orc, name, n):
     """Exactly k FP32 V-cycles of the mixed-precision solve (FP32 fields and
@@ -237,3 +238,74 @@ def test_mixed_fp32_cycles_match(orc, name, n):
     assert err <= 1e-6, err
     r = orc.rms(orc.defect(om, box / n, got, eta)) / ro.r_ref
     assert abs(st.rel_res - r) <= 1e-9 * r, (st.rel_res, r)
+
+
+def test_safeguard_hits_match_oracle(orc):
+    """The count of symmetron updates made with the safeguarded denominator
+    (reading 14) over a whole solve from a poor guess equals the oracle's
+    count for the same solve (cells where dS/dchi is within rounding of zero
+    may go either way, hence the small allowance)."""
+    from paper_1307_6748_amd import synth
+    om, sp, a = models("symmetron_a1")
+    w = _wl("small_symmetron")
+    guess = 0.3 * synth.random_field(32, 77)
+    ro = orc.solve(om, w["eta"], w["box"], tol=1e-10, phi0=guess)
+    for tb in (0, 1, 2):
+        _, st = _solver(32, w["box"], temporal_block=tb).solve(dev(w["eta"]), sp, a, 1e-10,
+                                                              phi=dev(guess), use_guess=1)
+        assert st.cycles == ro.cycles
+        assert ro.guard_hits > 1000
+        assert abs(st.safeguard_hits - ro.guard_hits) <= 2 + 1e-4 * ro.guard_hits, \
+            (tb, st.safeguard_hits, ro.guard_hits)
+    # f(R) has no safeguard
+    _, st = _solver(32, w["box"]).solve(dev(w["eta"]), models("fofr")[1], 1.0, 1e-8)
+    assert st.safeguard_hits == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_safeguard_hits_fused_equal_per_colour(precision):
+    """On a 256^3 finest level the fused sweeps recompute halo cells of
+    neighbouring tiles; each update is still counted once: one or two sweeps
+    per pass count what the per-colour kernels count."""
+    from paper_1307_6748_amd import synth
+    _, sp, a = models("symmetron_a1")
+    n, box = 256, 256.0
+    eta = dev(synth.lognormal(n, box, 3.0, 2))
+    guess = dev(0.3 * synth.random_field(n, 78))
+    hits = {}
+    for tb in (0, 1, 2):
+        _, st = _solver(n, box, temporal_block=tb, precision=precision).solve(
+            eta, sp, a, 1e-8, phi=guess.clone(), use_guess=1)
+        hits[tb] = st.safeguard_hits
+    assert hits[0] > 100_000
+    for tb in (1, 2):
+        assert abs(hits[tb] - hits[0]) <= 1e-4 * hits[0], hits
+
+
+def test_rho_hist_is_the_per_cycle_factor():
+    om, sp, a = models("fofr")
+    w = _wl("small_symmetron")
+    _, st = _solver(32, w["box"], precision="mixed").solve(dev(w["eta"]), sp, 1.0, 1e-9)
+    assert st.status == 0 and len(st.rho_hist) == st.cycles + 1 and st.rho_hist[0] == 0.0
+    for k in range(1, st.cycles + 1):
+        assert st.rho_hist[k] == pytest.approx(st.rel_hist[k] / st.rel_hist[k - 1], rel=1e-15)
+
+
+@pytest.mark.parametrize("name", ["symmetron_a1", "fofr"])
+def test_mixed_from_a_near_converged_guess(orc, name):
+    """A guess already below the FP32 round-off floor: the mixed solve skips
+    its FP32 phase (FP32 cycles could only raise the residual) and converges
+    to a tolerance far below that floor in no more cycles than the FP64 solve
+    from the same guess."""
+    from paper_1307_6748_amd import synth
+    om, sp, a = models(name)
+    w = _wl("small_symmetron")
+    eta = dev(w["eta"])
+    ref, st0 = _solver(32, w["box"]).solve(eta, sp, a, 1e-12)
+    guess = ref + 1e-11 * dev(synth.random_field(32, 5))
+    _, st64 = _solver(32, w["box"]).solve(eta, sp, a, 1e-11, phi=guess.clone(), use_guess=1)
+    phi, stm = _solver(32, w["box"], precision="mixed").solve(eta, sp, a, 1e-11,
+                                                              phi=guess.clone(), use_guess=1)
+    assert stm.status == 0 and stm.rel_res <= 1e-11
+    assert stm.cycles_fp32 == 0 and stm.cycles <= st64.cycles
+    assert float((phi - ref).abs().max()) <= 1e-9 * float(ref.abs().max()) + 1e-12
