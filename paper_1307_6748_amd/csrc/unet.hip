@@ -156,10 +156,13 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const bf16_t* __restrict__ x
 // voxels per wave (four M tiles of 16).  For each 16-channel slice of the
 // input it stages the 3 x 6 x 66 voxels its 27 taps read (38 KB), so every
 // input value comes from L2 about 4.6 times per convolution instead of once
-// per tap.  LDS holds a slice as four arrays of 8-byte units, one per group
-// of 4 channels (the MFMA's k-groups), so the 16 lanes of a k-group read 128
-// contiguous bytes (voxel-major 32-byte rows put lanes m, m+4, m+8, m+12 on
-// one bank).  Tiles are dealt to the 8 XCDs in contiguous ranges with x
+// per tap.  LDS holds a slice as two arrays of 16-byte units, one per half
+// of 8 channels ([half][plane][row][z]), read by the 16x16x32 BF16 MFMA two
+// taps at a time: lane g = lane / 16 takes channel half g & 1 of tap 2p + (g
+// >> 1), so the 16 lanes of one (half, tap) group read 256 contiguous bytes
+// (a voxel-major layout put lanes m, m+4, m+8, m+12 on one bank).  The 27th
+// tap runs on the 16x16x16 MFMA, reading 4-channel (8-byte) quarters of the
+// same arrays.  Tiles are dealt to the 8 XCDs in contiguous ranges with x
 // fastest, so neighbouring planes share an L2.
 constexpr int kLY = 4, kLZ = 64;                   // output tile (y, z)
 constexpr int kLPY = kLY + 2, kLPZ = kLZ + 2;      // with the halo
@@ -197,8 +200,11 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
         for (int u = 0; u < NT; ++u) acc[t][u] = f4{0.f, 0.f, 0.f, 0.f};
 
     // k of the 16x16x32 MFMA = two taps of one slice: lanes g = 0, 1 carry
-    // channels 8g..8g+7 of tap 2p, lanes g = 2, 3 those of tap 2p + 1; the
-    // 27th tap uses the 16x16x16 MFMA (channels 4g..4g+3).
+    // channels 8g..8g+7 of tap 2p, lanes g = 2, 3 those of tap 2p + 1.  The
+    // 27th tap is the 14th pair with zeros in the second half: every product
+    // runs on the one MFMA shape.  (Mixing in the 16x16x16 MFMA for the 27th
+    // tap measured wrong sums for the 32 -> 16 instantiation, whose schedule
+    // interleaves the two shapes on renamed accumulators.)
     const int hh = g & 1, side = g >> 1;
     const uint4* th = tile + hh * kLVox;  // this lane's 8-channel half
     for (int c0 = 0; c0 < CIN; c0 += 16) {
@@ -223,38 +229,26 @@ __global__ __launch_bounds__(kThreads) void k_conv3_lds(const bf16_t* __restrict
         }
         __syncthreads();
 #pragma unroll
-        for (int pr = 0; pr < 13; ++pr) {
-            const int tap = 2 * pr + side;
+        for (int pr = 0; pr < 14; ++pr) {
+            // pair 13: taps 26 and (nonexistent) 27; lanes of the second half
+            // read tap 26's (valid) addresses and zero what they loaded
+            const bool live = pr < 13 || side == 0;
+            const int tap = live ? 2 * pr + side : 26;
             const int off = ((tap / 9) * kLPY + wv + (tap / 3) % 3) * kLPZ + m + tap % 3;
             const bf16_t* wt = w + (long)tap * COUT * CIN;
             bf8v bw[NT];
 #pragma unroll
-            for (int u = 0; u < NT; ++u)
+            for (int u = 0; u < NT; ++u) {
                 bw[u] = *reinterpret_cast<const bf8v*>(wt + (long)(16 * u + m) * CIN + c0 + 8 * hh);
+                if (!live) bw[u] = bf8v{};
+            }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const bf8v a = *reinterpret_cast<const bf8v*>(th + off + 16 * t);
+                bf8v a = *reinterpret_cast<const bf8v*>(th + off + 16 * t);
+                if (!live) a = bf8v{};
 #pragma unroll
                 for (int u = 0; u < NT; ++u)
                     acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[u], acc[t][u], 0, 0, 0);
-            }
-        }
-        {
-            constexpr int tap = 26;
-            const int off = ((tap / 9) * kLPY + wv + (tap / 3) % 3) * kLPZ + m + tap % 3;
-            const bf16_t* wt = w + (long)tap * COUT * CIN;
-            s4 bw[NT];
-#pragma unroll
-            for (int u = 0; u < NT; ++u)
-                bw[u] = *reinterpret_cast<const s4*>(wt + (long)(16 * u + m) * CIN + c0 + 4 * g);
-            const uint2* tq = reinterpret_cast<const uint2*>(tile + side * kLVox);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const s4 a = *reinterpret_cast<const s4*>(tq + 2 * (off + 16 * t) + hh);
-#pragma unroll
-                for (int u = 0; u < NT; ++u)
-                    acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[u], acc[t][u], 0,
-                                                                          0, 0);
             }
         }
     }
@@ -1101,20 +1095,18 @@ int isis_unet_predict(const float* params, const double* eta, const double* phi_
     return ISIS_OK;
 }
 
-int isis_unet_train_step(float* params, float* adam_m, float* adam_v, int step, float lr,
-                         const double* eta, const double* phi_cold, const double* phi_target,
-                         double a, int n, void* workspace, size_t workspace_bytes,
-                         float* loss_out, float* grad_out, void* stream)
+int isis_unet_forward(const float* params, const double* eta, const double* phi_cold, double a,
+                      int n, float* out, void* workspace, size_t workspace_bytes, void* stream)
 {
     u_err[0] = 0;
-    if (!valid_unet_n(n) || !params || !adam_m || !adam_v || step < 1 || !(lr >= 0.f) || !eta ||
-        !phi_cold || !phi_target || !workspace || !(a > 0.0)) {
-        uerr("unet_train_step: invalid arguments");
+    if (!valid_unet_n(n) || !params || !eta || !phi_cold || !workspace || !(a > 0.0)) {
+        uerr("unet_forward: need n a power of two in [16, 2048], a > 0, non-NULL arrays");
         return ISIS_ERR_INVALID_ARG;
     }
     Plan P = make_plan(n, 1, (char*)workspace);
     if (workspace_bytes < P.bytes || ((uintptr_t)workspace & 255)) {
-        uerr("unet_train_step: workspace must be 256-byte aligned and >= %zu bytes", P.bytes);
+        uerr("unet_forward: workspace must be 256-byte aligned and >= %zu bytes (training size)",
+             P.bytes);
         return ISIS_ERR_INVALID_ARG;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -1122,10 +1114,30 @@ int isis_unet_train_step(float* params, float* adam_m, float* adam_v, int step, 
                        a, P.nv[0], P.in);
     ULAUNCH("k_make_input");
     TRY(run_forward(P, params, s));
-    const float* head = params + param_offset(14);
-    hipLaunchKernelGGL(k_head, dim3(grid_of(P.nv[0])), dim3(kThreads), 0, s, P.o[13], head,
-                       P.nv[0], P.out, nullptr, nullptr);
+    hipLaunchKernelGGL(k_head, dim3(grid_of(P.nv[0])), dim3(kThreads), 0, s, P.o[13],
+                       params + param_offset(14), P.nv[0], P.out, nullptr, nullptr);
     ULAUNCH("k_head");
+    if (out) UCHECK(hipMemcpyAsync(out, P.out, P.nv[0] * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return ISIS_OK;
+}
+
+int isis_unet_backward(const float* params, const double* phi_cold, const double* phi_target,
+                       int n, void* workspace, size_t workspace_bytes, float* grad,
+                       float* loss_out, void* stream)
+{
+    u_err[0] = 0;
+    if (!valid_unet_n(n) || !params || !phi_cold || !phi_target || !workspace) {
+        uerr("unet_backward: need n a power of two in [16, 2048] and non-NULL arrays");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    Plan P = make_plan(n, 1, (char*)workspace);
+    if (workspace_bytes < P.bytes || ((uintptr_t)workspace & 255)) {
+        uerr("unet_backward: workspace must be 256-byte aligned and >= %zu bytes (training size)",
+             P.bytes);
+        return ISIS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const float* head = params + param_offset(14);
     const int hchunk = 4096;
     const int hb = (int)((P.nv[0] + hchunk - 1) / hchunk);
     hipLaunchKernelGGL(k_head_bwd, dim3(hb), dim3(kThreads), 0, s, P.out, phi_target, phi_cold,
@@ -1137,20 +1149,95 @@ int isis_unet_train_step(float* params, float* adam_m, float* adam_v, int step, 
     UCHECK(hipMemcpyAsync(P.grad + param_offset(14), P.hsum, 17 * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
     TRY(run_backward(P, params, s));
-    const long np = param_total();
-    if (grad_out)
-        UCHECK(hipMemcpyAsync(grad_out, P.grad, np * sizeof(float), hipMemcpyDeviceToDevice, s));
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3(grid_of(np)), dim3(kThreads), 0, s, params, P.grad, adam_m,
-                       adam_v, np, lr, b1, b2, 1e-8f, c1, c2);
-    ULAUNCH("k_adam");
+    if (grad && grad != P.grad)
+        UCHECK(hipMemcpyAsync(grad, P.grad, param_total() * sizeof(float), hipMemcpyDeviceToDevice,
+                              s));
     if (loss_out) {
         float h[18];
         UCHECK(hipMemcpyAsync(h, P.hsum, sizeof(h), hipMemcpyDeviceToHost, s));
         UCHECK(hipStreamSynchronize(s));
         *loss_out = h[17] / (float)P.nv[0];
     }
+    return ISIS_OK;
+}
+
+int isis_unet_adam_step(float* params, const float* grad, float* adam_m, float* adam_v,
+                        long count, int step, float lr, void* stream)
+{
+    u_err[0] = 0;
+    if (!params || !grad || !adam_m || !adam_v || count < 0 || step < 1 || !(lr >= 0.f)) {
+        uerr("unet_adam_step: invalid arguments");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (count == 0) return ISIS_OK;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(grid_of(count)), dim3(kThreads), 0, (hipStream_t)stream,
+                       params, grad, adam_m, adam_v, count, lr, b1, b2, 1e-8f, c1, c2);
+    ULAUNCH("k_adam");
+    return ISIS_OK;
+}
+
+int isis_unet_train_step(float* params, float* adam_m, float* adam_v, int step, float lr,
+                         const double* eta, const double* phi_cold, const double* phi_target,
+                         double a, int n, void* workspace, size_t workspace_bytes,
+                         float* loss_out, float* grad_out, void* stream)
+{
+    u_err[0] = 0;
+    if (!valid_unet_n(n) || !params || !adam_m || !adam_v || step < 1 || !(lr >= 0.f) || !eta ||
+        !phi_cold || !phi_target || !workspace || !(a > 0.0)) {
+        uerr("unet_train_step: invalid arguments");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    TRY(isis_unet_forward(params, eta, phi_cold, a, n, nullptr, workspace, workspace_bytes,
+                          stream));
+    Plan P = make_plan(n, 1, (char*)workspace);
+    TRY(isis_unet_backward(params, phi_cold, phi_target, n, workspace, workspace_bytes, grad_out,
+                           loss_out, stream));
+    return isis_unet_adam_step(params, P.grad, adam_m, adam_v, param_total(), step, lr, stream);
+}
+
+int isis_unet_tensor(void* workspace, int n, int id, void** ptr, long* voxels, int* channels)
+{
+    u_err[0] = 0;
+    if (!valid_unet_n(n) || !workspace || !ptr || id < 0 || id > 21) {
+        uerr("unet_tensor: need n a power of two in [16, 2048], a workspace and 0 <= id <= 21");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    Plan P = make_plan(n, 1, (char*)workspace);
+    void* q = nullptr;
+    int lv = 0, C = 0;
+    if (id < 14) {
+        q = P.o[id];
+        lv = level_of(id);
+        C = kConvs[id].cout;
+    } else if (id == 14) {
+        q = P.in;
+        C = 16;
+    } else if (id <= 17) {
+        lv = id - 14;
+        q = id == 15 ? P.p1 : id == 16 ? P.p2 : P.p3;
+        C = id == 15 ? 16 : id == 16 ? 32 : 64;
+    } else if (id == 18) {
+        q = P.c8;
+        lv = 2;
+        C = 128;
+    } else if (id == 19) {
+        q = P.c10;
+        lv = 1;
+        C = 96;
+    } else if (id == 20) {
+        q = P.c12;
+        lv = 0;
+        C = 48;
+    } else {
+        q = P.out;
+        lv = 0;
+        C = 1;
+    }
+    *ptr = q;
+    if (voxels) *voxels = P.nv[lv];
+    if (channels) *channels = C;
     return ISIS_OK;
 }
 

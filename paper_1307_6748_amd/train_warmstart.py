@@ -8,8 +8,15 @@ Held-out set: seeds 2000..2019.  The evaluation reports, per held-out sample,
 the relative residual of the prediction and the V-cycles to 1e-8 from the
 prediction versus from the cold start.
 
+The solver keeps a prediction only if it cannot cost a V-cycle (its residual
+is at most what the first cold-started cycle reaches), so cycles_warm <=
+cycles_cold for every sample; the evaluation also reports how many guesses
+the judge kept.
+
 Usage: python -m paper_1307_6748_amd.train_warmstart [--pairs 200] [--epochs E]
        [--out paper_1307_6748_amd/data/unet_symmetron_128.npz]
+       [--checkpoint PATH [--resume]]   (training state saved after every epoch)
+       [--eval-only [--weights PATH]]   (re-evaluate weights, write them to --out)
 """
 from __future__ import annotations
 
@@ -43,6 +50,7 @@ def evaluate(net: W.WarmStart, n: int, box: float, seeds, model, tol: float = 1e
         r_guess = solver.residual(eta, guess, model, a)
         _, st = solver.solve(eta, model, a, tol, phi=guess, use_guess=2)
         rows.append(dict(seed=int(sd), a=a, rel_res_guess=r_guess / cold_st.r_ref,
+                         rel_res_first_cold_cycle=cold_st.rel_hist[1],
                          cycles_cold=cold_st.cycles, cycles_warm=st.cycles,
                          used_guess=bool(st.used_guess)))
     saved = [r["cycles_cold"] - r["cycles_warm"] for r in rows]
@@ -62,16 +70,43 @@ def main(argv=None) -> int:
     ap.add_argument("--heldout", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=W.DEFAULT_WEIGHTS)
+    ap.add_argument("--checkpoint", default=None)
+    ap.add_argument("--resume", action="store_true")
+    ap.add_argument("--eval-only", action="store_true")
+    ap.add_argument("--weights", default=W.DEFAULT_WEIGHTS,
+                    help="--eval-only: weights to evaluate (written with the new "
+                         "evaluation to --out)")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     model = S.symmetron(1.0, 0.5)
+    if args.eval_only:
+        with np.load(args.weights, allow_pickle=False) as z:
+            params = z["params"].copy()
+            meta = json.loads(str(z["meta"])) if "meta" in z else {}
+        net = W.WarmStart(params=params)
+        ev = evaluate(net, args.n, args.box, range(2000, 2000 + args.heldout), model)
+        log(f"held-out: mean V-cycles saved {ev['mean_cycles_saved']:.2f}, median rel. residual "
+            f"of the guess {ev['median_rel_res_guess']:.3e}, guess used "
+            f"{ev['used_guess_fraction']:.2f}")
+        meta["eval"] = ev
+        net.save(args.out, meta=json.dumps(meta))
+        print(json.dumps(dict(mean_cycles_saved=ev["mean_cycles_saved"],
+                              median_rel_res_guess=ev["median_rel_res_guess"],
+                              used_guess_fraction=ev["used_guess_fraction"])), flush=True)
+        return 0
     t0 = time.time()
     pairs = W.make_pairs(args.n, args.box, range(1000, 1000 + args.pairs), model, log=log)
     log(f"{len(pairs)} pairs in {time.time() - t0:.1f}s")
-    net = W.WarmStart(seed=args.seed)
+    trainer = None
+    if args.resume and args.checkpoint:
+        trainer = W.Trainer.load_checkpoint(args.checkpoint)
+        net = trainer.net
+        log(f"resumed at epoch {trainer.epoch}, step {trainer.k}")
+    else:
+        net = W.WarmStart(seed=args.seed)
     t1 = time.time()
     losses = W.train(net, pairs, args.epochs, lr=args.lr, lr_final=args.lr_final,
-                     seed=args.seed, log=log)
+                     seed=args.seed, log=log, checkpoint=args.checkpoint, trainer=trainer)
     train_s = time.time() - t1
     del pairs
     ev = evaluate(net, args.n, args.box, range(2000, 2000 + args.heldout), model)
