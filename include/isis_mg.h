@@ -214,6 +214,22 @@ int isis_mg_residual(isis_mg_t* h, const double* density, const double* field,
                      const isis_model_params* params, double a, double* out_res,
                      double* out_rms);
 
+/* isis_mg_residual without a handle or workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels, with the norm's partial
+ * sums in a static device array of 8208 doubles (64.1 KiB) that each device
+ * holds until the process ends.  It allocates nothing.
+ *  N: power of two in [8, 4096] (ISIS_ERR_INVALID_ARG beyond), box > 0.
+ *  density, field: device N^3 doubles; out_res: device N^3 doubles or NULL.
+ *  out_rms: host double or NULL; when set, the call synchronises the stream.
+ * All calls on one device share the array: calls that overlap (other
+ * streams, other threads, or a second call before the first one's kernels
+ * have finished when out_rms is NULL) race and give wrong norms.  Nothing in
+ * the array needs clearing between calls. */
+int isis_mg_residual_noalloc(const isis_model_params* params, double a, int N, double box,
+                             const double* density, const double* field, double* out_res,
+                             double* out_rms, void* stream);
+
 void isis_mg_destroy(isis_mg_t* h);
 
 /* Turn the finest-level sweep timing of isis_mg_stats on (1) or off (0).  On

@@ -57,6 +57,8 @@ SIGNATURES = [
     ("isis_mg_create", _I, [C.POINTER(DescC), C.POINTER(_P)]),
     ("isis_mg_solve", _I, [_P, _P, _P, C.POINTER(ModelParamsC), _D, _D, _I, C.POINTER(StatsC)]),
     ("isis_mg_residual", _I, [_P, _P, _P, C.POINTER(ModelParamsC), _D, _P, C.POINTER(_D)]),
+    ("isis_mg_residual_noalloc", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P,
+                                      C.POINTER(_D), _P]),
     ("isis_mg_destroy", None, [_P]),
     ("isis_mg_last_error", C.c_char_p, [_P]),
     ("isis_mg_set_profiling", _I, [_P, _I]),

@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/isis_mg.h"
@@ -490,6 +491,33 @@ bool valid_desc(const isis_mg_desc* d, char* err)
     return true;
 }
 
+// The FP64 defect L(phi) of an n^3 level with spacing h (into res unless
+// NULL) and the sum of its squares: per-block partial sums in
+// partial[0 .. kReduceBlocks), their fixed-order total in *total (device).
+template <class TF, class M>
+int launch_defect_norm(const M& m, int n, double h, const TF* phi, const double* eta,
+                       double* res, double* partial, double* total, hipStream_t s, char* err,
+                       double uscale = 1.0, double uoffset = 0.0)
+{
+    const long n3 = (long)n * n * n;
+    int g = std::min(kReduceBlocks, grid_for(n3 / 2));
+    using NG = NormTileF;
+    const bool tiled = (n & (n - 1)) == 0 && n % NG::TZ == 0 && n % NG::TY == 0 && n % NG::XC == 0;
+    if (tiled) {
+        const long tiles = (long)(n / NG::TZ) * (n / NG::TY) * (n / NG::XC);
+        g = (int)std::min<long>(kReduceBlocks, tiles);
+        hipLaunchKernelGGL((k_defect_norm_tiled<TF, M>), dim3(g), dim3(kBlock), 0, s, m, n,
+                           1.0 / (h * h), uscale, uoffset, phi, eta, res, partial);
+    }
+    if (!tiled)
+        hipLaunchKernelGGL((k_defect_norm_pairs<TF, M>), dim3(g), dim3(kBlock), 0, s, m, n,
+                           1.0 / (h * h), uscale, uoffset, phi, eta, res, partial);
+    LAUNCH_CHECK(err, "k_defect_norm");
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partial, g, total);
+    LAUNCH_CHECK(err, "k_reduce");
+    return ISIS_OK;
+}
+
 // sqrt(mean(L_0(phi)^2)) of the finest level, in double; res may be NULL.
 template <class TF, class M>
 int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* res, double* out,
@@ -497,22 +525,9 @@ int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* r
 {
     const int n = H->d.N;
     const long n3 = (long)n * n * n;
-    const double h = H->L64[0].h;
-    int g = std::min(kReduceBlocks, grid_for(n3 / 2));
-    using NG = NormTileF;
-    const bool tiled = (n & (n - 1)) == 0 && n % NG::TZ == 0 && n % NG::TY == 0 && n % NG::XC == 0;
-    if (tiled) {
-        const long tiles = (long)(n / NG::TZ) * (n / NG::TY) * (n / NG::XC);
-        g = (int)std::min<long>(kReduceBlocks, tiles);
-        hipLaunchKernelGGL((k_defect_norm_tiled<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
-                           1.0 / (h * h), uscale, uoffset, phi, eta, res, H->partial);
-    }
-    if (!tiled)
-        hipLaunchKernelGGL((k_defect_norm_pairs<TF, M>), dim3(g), dim3(kBlock), 0, H->s, m, n,
-                           1.0 / (h * h), uscale, uoffset, phi, eta, res, H->partial);
-    LAUNCH_CHECK(H->err, "k_defect_norm");
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
-    LAUNCH_CHECK(H->err, "k_reduce");
+    int r = launch_defect_norm<TF, M>(m, n, H->L64[0].h, phi, eta, res, H->partial, H->scal, H->s,
+                                      H->err, uscale, uoffset);
+    if (r) return r;
     HIP_TRY(H->err, hipMemcpyAsync(H->host, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->s));
     HIP_TRY(H->err, hipStreamSynchronize(H->s));
     *out = std::sqrt(H->host[0] / (double)n3);
@@ -869,6 +884,41 @@ int launch_force(int n, double h, double c, const double* field, const double* p
                : launch_force_t<SF, false>(n, h, c, field, pot, fx, fy, fz, s, err);
 }
 
+// Scratch of isis_mg_residual_noalloc: the defect norm's per-block partial
+// sums and their total, in a static device array (every device the library
+// runs on holds its own copy until the process ends).  Host code never passes
+// the array's name to a kernel or copy: it uses the device's address of it,
+// looked up once per device with hipGetSymbolAddress.
+constexpr int kStaticScratch = kReduceBlocks + 16;  // doubles: 64 KiB + 128 B
+static __device__ __align__(256) double scratch[kStaticScratch];
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices];
+
+// The current device's address of `scratch`.
+int static_scratch(double** out, char* err)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(err, e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        fmt_err(err, "device %d: the static scratch supports devices 0..%d", dev, kMaxDevices - 1);
+        return ISIS_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(err, e, "hipGetSymbolAddress(scratch)");
+        if (!p) {
+            fmt_err(err, "hipGetSymbolAddress(scratch) returned NULL");
+            return ISIS_ERR_HIP;
+        }
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return ISIS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1028,6 +1078,46 @@ int isis_mg_residual(isis_mg_t* H, const double* density, const double* field,
     });
     if (r) return r;
     if (out_rms) *out_rms = rms;
+    return ISIS_OK;
+}
+
+int isis_mg_residual_noalloc(const isis_model_params* params, double a, int N, double box,
+                             const double* density, const double* field, double* out_res,
+                             double* out_rms, void* stream)
+{
+    g_err[0] = 0;
+    if (!valid_params(params, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!is_pow2_ge(N, 8) || N > 4096) {
+        fmt_err(g_err, "residual_noalloc: N must be a power of two in [8, 4096] (got %d)", N);
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!finite_pos(box)) {
+        fmt_err(g_err, "residual_noalloc: box must be finite and > 0");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!density || !field || !aligned(density, 16) || !aligned(field, 16) ||
+        (out_res && !aligned(out_res, 16))) {
+        fmt_err(g_err, "residual_noalloc: density, field (and out_res) must be 16-byte aligned "
+                       "device pointers");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    double* sc = nullptr;
+    int r = static_scratch(&sc, g_err);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    const double h = box / N;
+    r = with_model<double>(*params, a, [&](auto m) {
+        return launch_defect_norm<double, decltype(m)>(m, N, h, field, density, out_res, sc,
+                                                       sc + kReduceBlocks, s, g_err);
+    });
+    if (r) return r;
+    if (out_rms) {
+        double total = 0.0;
+        HIP_TRY(g_err, hipMemcpyAsync(&total, sc + kReduceBlocks, sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+        HIP_TRY(g_err, hipStreamSynchronize(s));
+        *out_rms = std::sqrt(total / ((double)N * N * N));
+    }
     return ISIS_OK;
 }
 
