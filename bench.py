@@ -18,7 +18,9 @@ solving the same two problems (cpu_baseline), the learned warm start
 (U-Net prediction + solve, symmetron) as a separate leg, and the step after the
 solve (Newtonian potential on the same grid, force kernel) as another, and the
 model variants (chameleon, f(R) in the paper's variable) on the same density as
-a third.
+a third.  Per model the whole solve is also set against the HBM roofline: the
+compulsory bytes of all its kernels (solve_bytes) over its wall time; and each
+model is solved once more with the other restriction of the defect.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -113,6 +115,55 @@ def roofline(kern: dict, n: int):
     return head, kernels
 
 
+def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: bool) -> float:
+    """Compulsory HBM bytes of one V-cycle's visit to a level of nl^3 cells with
+    s-byte values: each smoothing pass reads phi, eta (and Sigma below the
+    finest level) once and writes phi; the descent reads phi, eta (Sigma) and
+    writes phi_c, phihat_c and the restricted defect (3/8 s per fine cell), full
+    weighting adding the fine defect's write and read; the coarse source reads
+    phi_c, eta_c, the restricted defect and writes Sigma_c; the correction
+    reads the two coarse fields and reads and writes phi.  The coarsest level
+    is smoothed in one workgroup and moves no more than its 64 cells."""
+    c = float(nl) ** 3
+    if coarsest:
+        return 4 * s * c
+    b = passes * (3 + (1 if sig else 0)) * s * c          # smoothing
+    b += (2 + (1 if sig else 0)) * s * c + 3 * s * c / 8  # defect + restriction
+    if fw:
+        b += 2 * s * c                                    # fine defect written, read
+    b += 4 * s * c / 8                                    # coarse source
+    b += 2 * s * c + 2 * s * c / 8                        # prolongation + correction
+    return b
+
+
+def solve_bytes(n: int, st, tb: int, nu: tuple, mixed: bool) -> float:
+    """Compulsory HBM bytes of a whole solve (the algorithmic traffic of its
+    kernels with perfect on-chip reuse): density hierarchy, cold start and
+    r_ref, the V-cycles (FP32 cycles in mixed precision, FP64 otherwise; the
+    fused kernels' temporal block on levels >= 256^3) and the FP64 judge of
+    each cycle (reads the iterate and the FP64 density)."""
+    nlev = 1
+    while (n >> (nlev - 1)) > 4:
+        nlev += 1
+    n3 = float(n) ** 3
+    b = 8 * n3 * (1 + 1 / 7) + (4 * n3 * (1 + 1 / 7) if mixed else 0)  # eta hierarchy (+FP32 copy)
+    b += 8 * n3 + 8 * n3 + (4 * n3 if mixed else 0) + 16 * n3            # cold start, r_ref
+    cyc64 = st.cycles - st.cycles_fp32
+    for count, s in ((st.cycles_fp32, 4), (cyc64, 8)):
+        if count == 0:
+            continue
+        per = 0.0
+        for l in range(nlev):
+            nl = n >> l
+            fused = tb >= 1 and nl >= 256
+            blk = max(1, tb) if fused else 1
+            passes = -(-nu[0] // blk) + -(-nu[1] // blk)
+            per += level_bytes(nl, s, passes, l > 0, bool(st.restriction), l == nlev - 1)
+        per += (s + 8) * n3  # the FP64 judge
+        b += count * per
+    return b
+
+
 def omp_threads() -> int:
     import ctypes
     try:
@@ -167,6 +218,8 @@ def main() -> int:
                     help="skip the CPU oracle (full-size parity and cpu_baseline)")
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-restriction-compare", action="store_true",
+                    help="skip the solves with the other restriction of the defect")
     ap.add_argument("--no-force", action="store_true",
                     help="skip the Newtonian potential solve and the force kernel")
     ap.add_argument("--no-variants", action="store_true",
@@ -246,11 +299,21 @@ def main() -> int:
     per_model = {}
     for name, sts in rec.items():
         st = sts[-1]
+        secs = float(np.mean([s.ms_total for s in sts]) / 1000.0)
+        sb = solve_bytes(n, st, st.temporal_block, (2, 2), args.precision == "mixed")
         per_model[name] = dict(
-            seconds=float(np.mean([s.ms_total for s in sts]) / 1000.0),
+            seconds=secs,
             cycles=st.cycles, cycles_fp32=st.cycles_fp32, rel_res=st.rel_res,
             temporal_block=st.temporal_block,
-            rho=[st.rel_hist[i + 1] / st.rel_hist[i] for i in range(st.cycles)])
+            restriction="full weighting" if st.restriction else "mean of 8",
+            safeguard_hits=st.safeguard_hits,
+            smoothing_s=float(np.mean([s.ms_smooth for s in sts]) / 1000.0),
+            rho=[st.rel_hist[i + 1] / st.rel_hist[i] for i in range(st.cycles)],
+            # the whole solve against the HBM roofline: its kernels' compulsory
+            # bytes (solve_bytes) over its wall time
+            solve_roofline=dict(bytes=sb, achieved_gbs=sb / secs / 1e9,
+                                frac=sb / secs / 1e9 / HBM_PEAK_GBS,
+                                ms_per_cycle=1e3 * secs / st.cycles))
     roof, kernels = roofline(kern, n)
 
     # FP64-only solves of the same problems: "plain" with one launch per colour
@@ -274,6 +337,35 @@ def main() -> int:
                 del ph
             solver64.close()
             del solver64
+
+    # The restriction of the defect: the library's per-model choice (full
+    # weighting for f(R)) against the other one, same solver otherwise.
+    restriction_leg = None
+    if not args.no_restriction_compare:
+        restriction_leg = {}
+        for name, (p, a) in mods.items():
+            other = 0 if rec[name][-1].restriction else 1
+            so = S.Solver(n, box, precision=args.precision, temporal_block=tb, max_cycles=100,
+                          fp32_floor=args.fp32_floor, restriction=other)
+            ph = torch.empty_like(eta)
+            so.solve(eta, p, a, TOL, phi=ph)  # warm
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, sto = so.solve(eta, p, a, TOL, phi=ph)
+            torch.cuda.synchronize()
+            t_o = time.perf_counter() - t1
+            lab = {0: "mean of 8", 1: "full weighting"}
+            restriction_leg[name] = {
+                lab[rec[name][-1].restriction]: dict(seconds=per_model[name]["seconds"],
+                                                     cycles=per_model[name]["cycles"]),
+                lab[other]: dict(seconds=t_o, cycles=sto.cycles, cycles_fp32=sto.cycles_fp32,
+                                 rho=[sto.rel_hist[i + 1] / sto.rel_hist[i]
+                                      for i in range(sto.cycles)])}
+            log(f"{name} with the {lab[other]} restriction: {t_o:.4f}s, {sto.cycles} cycles "
+                f"(default {lab[rec[name][-1].restriction]}: {per_model[name]['seconds']:.4f}s, "
+                f"{per_model[name]['cycles']} cycles)")
+            so.close()
+            del so, ph
 
     # The step after the solve: the Newtonian potential on the same grid (the
     # Poisson equation of Sec. 3.1 as the linear model) and the total force
@@ -380,8 +472,11 @@ def main() -> int:
     cpu = None
     if not args.no_oracle_check:
         # The FP64 CPU oracle solves the same two problems (to 1e-8: the CPU
-        # baseline, timed), then two more V-cycles give the reference field
-        # for the GPU solutions' relative L2 error.
+        # baseline, timed).  The GPU field is compared with that solution (the
+        # same method stopped at the same tolerance) and with a reference two
+        # V-cycles further on (~1e-10): the latter error is about a fixed
+        # multiple of the relative residual (~150 for f(R) on this density),
+        # so at tol = 1e-8 it can exceed 1e-6 whichever processor solves.
         from oracle import oracle as O
         om = oracle_models()
         h = box / n
@@ -391,14 +486,17 @@ def main() -> int:
             r8 = O.solve(om[name], eta_np, box, tol=TOL, cfg=O.Cfg(max_cycles=100))
             times[name] = dict(seconds=r8.wall_s, cycles=r8.cycles)
             ref = O.vcycles(om[name], eta_np, box, r8.phi, 2).phi
-            del r8
             phi_np = phis[name].cpu().numpy().reshape(n, n, n)
+            err_same = float(np.linalg.norm(phi_np - r8.phi) / np.linalg.norm(r8.phi))
             err = float(np.linalg.norm(phi_np - ref) / np.linalg.norm(ref))
+            del r8
             r = O.rms(O.defect(om[name], h, phi_np, eta_np))
             cold = O.cold_start(om[name], eta_np)
             r_ref = O.rms(O.defect(om[name], h, cold, eta_np))
-            parity[name] = dict(rel_l2_vs_oracle=err, oracle_rel_residual_of_gpu=r / r_ref,
-                                tol=TOL, ok=bool(r / r_ref <= 1.5 * TOL and err <= 1e-6))
+            parity[name] = dict(rel_l2_vs_oracle=err_same, rel_l2_vs_converged=err,
+                                error_per_residual=err / (r / r_ref),
+                                oracle_rel_residual_of_gpu=r / r_ref, tol=TOL,
+                                ok=bool(r / r_ref <= 1.5 * TOL and err_same <= 1e-6))
             if name == "symmetron" and warm is not None:
                 warm["cnn_rel_l2_vs_oracle"] = float(np.linalg.norm(guess_np - ref) /
                                                      np.linalg.norm(ref))
@@ -406,7 +504,8 @@ def main() -> int:
                                                       np.linalg.norm(ref))
             del phi_np, cold, ref
             log(f"oracle {name}: {times[name]['seconds']:.1f}s ({times[name]['cycles']} cycles); "
-                f"GPU rel. L2 error {err:.2e}, oracle residual of GPU field {r / r_ref:.3e}")
+                f"GPU vs oracle at tol {err_same:.2e}, vs converged {err:.2e}, oracle residual "
+                f"of GPU field {r / r_ref:.3e}")
         # The small case (32^3 symmetron, box 64, lognormal sigma_delta = 1,
         # seed 1, to 1e-10) on all threads and on one, and on the GPU.
         sw = synth.workload("small_symmetron")
@@ -465,6 +564,7 @@ def main() -> int:
             "fine_smoother_kernel": sweep_upd / (sweep_ms * 1e-3) if sweep_ms > 0 else None,
         },
         "per_model": per_model,
+        "restriction": restriction_leg,
         "fp64_plain": fp64 or None,
         "speedup_vs_fp64_plain": (float(np.mean([fp64[k]["seconds"] for k in fp64])) / value
                                   if fp64 else None),

@@ -123,6 +123,14 @@ typedef struct {
                           the relative residual after the first V-cycle of the
                           handle's last converged cold-started solve of the same
                           model, or 1e-2 before there is one; else in (0, 1]    */
+    int restriction;   /* restriction of the defect in the FAS descent (Sec. 3.1
+                          leaves R open): 0 = mean of the 8 children; 1 = full
+                          weighting, the adjoint of the trilinear prolongation
+                          over 8 (weights 1, 3, 3, 1 over 8 per axis; phi and
+                          eta keep the mean); -1 = per model at each solve: full
+                          weighting for f(R), the mean for the others.  The
+                          converged field does not depend on it, the V-cycles'
+                          convergence factors do                              */
 } isis_mg_desc;
 
 typedef struct {
@@ -161,6 +169,8 @@ typedef struct {
     double ms_smooth;             /* profiling on: summed kernel time of every
                                      smoothing step of every level, the coarsest
                                      grid's sweeps included, milliseconds         */
+    int restriction;              /* the restriction of the defect the solve used
+                                     (0 mean, 1 full weighting)                    */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;
@@ -271,13 +281,21 @@ int isis_op_restrict(int n_fine, const double* fine, double* coarse, void* strea
 /* One FAS descent step (Sec. 3.2), fine level of n_fine^3 cells and spacing
  * h_fine to the coarse level (n_fine/2)^3, spacing 2 h_fine:
  *   phi_c = phihat_c = R phi_f,
- *   sigma_c = L_c(phi_c, eta_c) - R[L_f(phi_f, eta_f) - sigma_f].
- * sigma_f may be NULL (finest level).  rr_c: coarse scratch (receives R of
- * the fine defect). */
+ *   sigma_c = L_c(phi_c, eta_c) - R'[L_f(phi_f, eta_f) - sigma_f],
+ * R the mean of the 8 children; R' = R, or full weighting (see
+ * isis_op_restrict_fw) when fine_scratch (device n_fine^3 doubles, receives
+ * the fine defect) is not NULL.  sigma_f may be NULL (finest level).  rr_c:
+ * coarse scratch (receives R' of the fine defect). */
 int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double h_fine,
                         const double* phi_f, const double* eta_f, const double* sigma_f,
                         const double* eta_c, double* phi_c, double* phihat_c, double* sigma_c,
-                        double* rr_c, void* stream);
+                        double* rr_c, double* fine_scratch, void* stream);
+
+/* coarse = full-weighting restriction of fine, the adjoint of the trilinear
+ * prolongation over 8: along each axis coarse cell I takes fine cells 2I-1,
+ * 2I, 2I+1, 2I+2 (periodic) with weights 1/8, 3/8, 3/8, 1/8, and the 3D
+ * weight is their product (n_fine even >= 2; Sec. 3.1 leaves R open). */
+int isis_op_restrict_fw(int n_fine, const double* fine, double* coarse, void* stream);
 
 /* fine += P(coarse - coarse_hat), cell-centred trilinear interpolation with
  * weights 27, 9, 3, 1 over 64 and periodic wrap (n_fine even >= 4). */

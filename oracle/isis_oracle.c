@@ -30,6 +30,9 @@
  *       fields with no coarse Sigma; R[eps] restricts the fine defect L - Sigma.
  *   R2  R is the mean of the 8 children; P is cell-centred trilinear
  *       interpolation (weights 27, 9, 3, 1 over 64) with periodic wrap.
+ *       Option (orc_cfg.restrict_fw): the defect is restricted by full
+ *       weighting, the adjoint of P over 8 (weights 1, 3, 3, 1 over 8 per
+ *       axis on the 4 fine cells 2I-1 .. 2I+2); phi and rho keep the mean.
  *   R3  The non-canonical operator carries the 1/h^2 that its Jacobian has.
  *   R4  The db/du term of the Jacobian carries the factor 1/2 that follows
  *       from differentiating the arithmetic face average.
@@ -107,6 +110,7 @@ typedef struct {
 
 typedef struct {
     int nu_pre, nu_post, nu_coarse, max_cycles;
+    int restrict_fw; /* 1: full-weighting restriction of the defect (reading R2) */
 } orc_cfg;
 
 typedef struct {
@@ -352,6 +356,30 @@ void orc_restrict(int n_fine, const double* fine, double* coarse)
             }
 }
 
+/* Full weighting (reading R2, option): coarse = P^T fine / 8.  Along each
+ * axis coarse cell I collects fine cells 2I-1, 2I, 2I+1, 2I+2 (periodic) with
+ * weights 1/8, 3/8, 3/8, 1/8 -- the transposed 1D weights of the trilinear
+ * prolongation below (1/4, 3/4, 3/4, 1/4) over 2 -- and the 3D weight is the
+ * product of the three. */
+void orc_restrict_fw(int n_fine, const double* fine, double* coarse)
+{
+    long nf = n_fine, nc = n_fine / 2;
+    const double w[4] = {0.125, 0.375, 0.375, 0.125};
+#pragma omp parallel for schedule(static)
+    for (long I = 0; I < nc; ++I)
+        for (long J = 0; J < nc; ++J)
+            for (long K = 0; K < nc; ++K) {
+                double s = 0.0;
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b)
+                        for (int c = 0; c < 4; ++c)
+                            s += w[a] * w[b] * w[c] *
+                                 fine[cidx(nf, wrap(2 * I - 1 + a, nf), wrap(2 * J - 1 + b, nf),
+                                           wrap(2 * K - 1 + c, nf))];
+                coarse[cidx(nc, I, J, K)] = s;
+            }
+}
+
 /* fine += P(coarse - coarse_hat): cell-centred trilinear interpolation.
  * For fine index i the parent is I = i/2 and the second coarse cell along
  * that axis is I + s with s = +1 for odd i and -1 for even i; the 1D weights
@@ -481,8 +509,12 @@ static void vcycle(const orc_model* m, const orc_cfg* cfg, orc_level* lv, int l,
     orc_restrict(f->n, f->phi, c->phi);
     long nc3 = (long)c->n * c->n * c->n;
     memcpy(c->phihat, c->phi, sizeof(double) * (size_t)nc3);
-    /* Sigma_{l+1} = L_{l+1}(R phi, R eta) - R eps_l (reading R1) */
-    orc_restrict(f->n, f->work, c->work);
+    /* Sigma_{l+1} = L_{l+1}(R phi, R eta) - R eps_l (reading R1); R of the
+     * defect: mean of the children, or full weighting (reading R2) */
+    if (cfg->restrict_fw)
+        orc_restrict_fw(f->n, f->work, c->work);
+    else
+        orc_restrict(f->n, f->work, c->work);
     orc_defect(m, c->n, c->h, c->phi, c->eta, NULL, c->sigma);
     for (long q = 0; q < nc3; ++q) c->sigma[q] -= c->work[q];
 

@@ -54,7 +54,7 @@ class _Model(C.Structure):
 
 class _Cfg(C.Structure):
     _fields_ = [("nu_pre", C.c_int), ("nu_post", C.c_int), ("nu_coarse", C.c_int),
-                ("max_cycles", C.c_int)]
+                ("max_cycles", C.c_int), ("restrict_fw", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -94,9 +94,14 @@ class Cfg:
     nu_post: int = 2
     nu_coarse: int = 32
     max_cycles: int = 50
+    # restriction of the defect: False = mean of the 8 children, True = full
+    # weighting; None = per model, the choice the GPU library makes by
+    # default (full weighting for f(R), where it takes fewer V-cycles)
+    restrict_fw: bool | None = None
 
-    def _c(self) -> _Cfg:
-        return _Cfg(self.nu_pre, self.nu_post, self.nu_coarse, self.max_cycles)
+    def _c(self, model: int = SYMMETRON) -> _Cfg:
+        fw = (model == FR_HS) if self.restrict_fw is None else bool(self.restrict_fw)
+        return _Cfg(self.nu_pre, self.nu_post, self.nu_coarse, self.max_cycles, int(fw))
 
 
 @dataclass
@@ -130,6 +135,7 @@ def lib():
                                     C.c_int]
         L.orc_sweep.argtypes = [C.POINTER(_Model), C.c_int, C.c_double, dp, dp, C.c_void_p]
         L.orc_restrict.argtypes = [C.c_int, dp, dp]
+        L.orc_restrict_fw.argtypes = [C.c_int, dp, dp]
         L.orc_prolong_correct.argtypes = [C.c_int, dp, dp, dp]
         L.orc_cold_start.argtypes = [C.POINTER(_Model), C.c_long, dp, dp]
         L.orc_rms.argtypes = [C.c_int, dp]
@@ -232,6 +238,15 @@ def restrict(fine) -> np.ndarray:
     return out
 
 
+def restrict_fw(fine) -> np.ndarray:
+    """Full-weighting restriction, P^T / 8 (the defect's option)."""
+    fine = _f64(fine)
+    n = fine.shape[0]
+    out = np.empty((n // 2,) * 3)
+    lib().orc_restrict_fw(n, fine, out)
+    return out
+
+
 def prolong_correct(fine, coarse, coarse_hat) -> np.ndarray:
     out = _f64(fine).copy()
     lib().orc_prolong_correct(out.shape[0], out, _f64(coarse), _f64(coarse_hat))
@@ -269,7 +284,7 @@ def solve(m: Model, eta, box: float, tol: float = 1e-10, phi0=None, cfg: Cfg | N
     n = eta.shape[0]
     phi = np.empty_like(eta) if phi0 is None else _f64(phi0).copy()
     st = _Stats()
-    mc, cc = m._c(), cfg._c()
+    mc, cc = m._c(), cfg._c(m.model)
     s = lib().orc_solve(C.byref(mc), C.byref(cc), n, box, eta, phi, 0 if phi0 is None else 1,
                         tol, C.byref(st))
     if s == INVALID:
@@ -281,5 +296,5 @@ def solve(m: Model, eta, box: float, tol: float = 1e-10, phi0=None, cfg: Cfg | N
 def vcycles(m: Model, eta, box: float, phi0, k: int, cfg: Cfg | None = None) -> Result:
     """Exactly k V-cycles from phi0 (no stop test)."""
     cfg = cfg or Cfg()
-    c2 = Cfg(cfg.nu_pre, cfg.nu_post, cfg.nu_coarse, k)
+    c2 = Cfg(cfg.nu_pre, cfg.nu_post, cfg.nu_coarse, k, cfg.restrict_fw)
     return solve(m, eta, box, tol=0.0, phi0=phi0, cfg=c2)

@@ -32,7 +32,7 @@ class DescC(C.Structure):
                 ("nu_coarse", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int),
                 ("fp32_floor", C.c_double), ("temporal_block", C.c_int), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("guess_accept", C.c_double)]
+                ("guess_accept", C.c_double), ("restriction", C.c_int)]
 
 
 class StatsC(C.Structure):
@@ -43,7 +43,8 @@ class StatsC(C.Structure):
                 ("fine_sweep_ms", C.c_double * 2), ("fine_sweep_launches", C.c_int * 2),
                 ("fine_sweep_updates", C.c_double * 2), ("fine_sweep_bytes", C.c_double * 2),
                 ("temporal_block", C.c_int), ("rho_hist", C.c_double * MAX_HIST),
-                ("safeguard_hits", C.c_longlong), ("ms_smooth", C.c_double)]
+                ("safeguard_hits", C.c_longlong), ("ms_smooth", C.c_double),
+                ("restriction", C.c_int)]
 
 
 _lib = None
@@ -68,7 +69,8 @@ SIGNATURES = [
     ("isis_op_defect", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P]),
     ("isis_op_restrict", _I, [_I, _P, _P, _P]),
     ("isis_op_fas_descend", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P, _P,
-                                 _P, _P, _P]),
+                                 _P, _P, _P, _P]),
+    ("isis_op_restrict_fw", _I, [_I, _P, _P, _P]),
     ("isis_op_prolong_correct", _I, [_I, _P, _P, _P, _P]),
     ("isis_op_coarse_solve", _I, [C.POINTER(ModelParamsC), _D, _D, _P, _P, _P, _I, _P]),
     ("isis_op_cold_start", _I, [C.POINTER(ModelParamsC), _D, C.c_long, _P, _P, _P]),

@@ -21,6 +21,7 @@
 
 #include "../../include/isis_mg.h"
 #include "force.hpp"
+#include "full_weighting.hpp"
 #include "fused_sweep.hpp"
 #include "kernels.hpp"
 #include "pair_kernels.hpp"
@@ -267,24 +268,43 @@ int launch_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta, c
     return ISIS_OK;
 }
 
-template <class T, class M, bool SIG>
+template <class T, class M, bool SIG, bool FW>
 int launch_restrict_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
-                          const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, int blocks, int lds,
-                          hipStream_t s, char* err)
+                          const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, T* dfine, int blocks,
+                          int lds, hipStream_t s, char* err)
 {
-    auto kern = k_defect_restrict_tiled<T, M, SIG>;
+    auto kern = k_defect_restrict_tiled<T, M, SIG, FW>;
     static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
     HIP_TRY(err, ensure_dynamic_lds((const void*)kern, lds, lds_done));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), lds, s, m, nf, ih2f, phi_f, eta_f,
-                       sigma_f, phi_c, phihat_c, rr_c);
+                       sigma_f, phi_c, phihat_c, rr_c, dfine);
     LAUNCH_CHECK(err, "k_defect_restrict_tiled");
     return ISIS_OK;
 }
 
+// coarse = full-weighting restriction of an nf^3 fine field (nf even >= 4).
+template <class T>
+int launch_restrict_fw(int nf, const T* fine, T* coarse, hipStream_t s, char* err)
+{
+    const int nc = nf / 2;
+    using FG = FwTileF;
+    if ((nc & (nc - 1)) == 0 && nc % FG::TK == 0 && nc % FG::TJ == 0 && nc % FG::XC == 0)
+        hipLaunchKernelGGL((k_restrict_fw_tiled<T>), dim3((nc / FG::TK) * (nc / FG::TJ) * (nc / FG::XC)),
+                           dim3(kBlock), 0, s, nf, fine, coarse);
+    else
+        hipLaunchKernelGGL((k_restrict_fw<T>), dim3(grid_for((long)nc * nc * nc)), dim3(kBlock), 0,
+                           s, nf, fine, coarse);
+    LAUNCH_CHECK(err, "k_restrict_fw");
+    return ISIS_OK;
+}
+
+// The FAS descent.  dfine: NULL for the 8-child mean of the defect; else an
+// nf^3 scratch field that receives the fine defect, which is then restricted
+// by full weighting.
 template <class T, class M>
 int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f,
                    const T* sigma_f, const T* eta_c, T* phi_c, T* phihat_c, T* sigma_c, T* rr_c,
-                   hipStream_t s, char* err)
+                   hipStream_t s, char* err, T* dfine = nullptr)
 {
     int nc = nf / 2;
     long c3 = (long)nc * nc * nc;
@@ -295,19 +315,38 @@ int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f
     if ((nf & (nf - 1)) == 0 && nf % RG::TZ == 0 && nf % RG::TY == 0 && nc % RG::XC == 0) {
         const int blocks = (nf / RG::TZ) * (nf / RG::TY) * (nc / RG::XC);
         constexpr int lds = restrict_tiled_lds_bytes<T, M>();
-        int r = sigma_f ? launch_restrict_tiled<T, M, true>(m, nf, ih2f, phi_f, eta_f, sigma_f,
-                                                            phi_c, phihat_c, rr_c, blocks, lds, s, err)
-                        : launch_restrict_tiled<T, M, false>(m, nf, ih2f, phi_f, eta_f, sigma_f,
-                                                             phi_c, phihat_c, rr_c, blocks, lds, s,
-                                                             err);
+        int r;
+        if (dfine)
+            r = sigma_f ? launch_restrict_tiled<T, M, true, true>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                                  phi_c, phihat_c, rr_c, dfine,
+                                                                  blocks, lds, s, err)
+                        : launch_restrict_tiled<T, M, false, true>(m, nf, ih2f, phi_f, eta_f,
+                                                                   sigma_f, phi_c, phihat_c, rr_c,
+                                                                   dfine, blocks, lds, s, err);
+        else
+            r = sigma_f ? launch_restrict_tiled<T, M, true, false>(m, nf, ih2f, phi_f, eta_f,
+                                                                   sigma_f, phi_c, phihat_c, rr_c,
+                                                                   nullptr, blocks, lds, s, err)
+                        : launch_restrict_tiled<T, M, false, false>(m, nf, ih2f, phi_f, eta_f,
+                                                                    sigma_f, phi_c, phihat_c, rr_c,
+                                                                    nullptr, blocks, lds, s, err);
         if (r) return r;
-    } else if (nf >= 4)
+    } else if (nf >= 4) {
         hipLaunchKernelGGL((k_defect_restrict_pairs<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s,
-                           m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c);
-    else
+                           m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c, dfine);
+    } else {
+        if (dfine) {
+            fmt_err(err, "full-weighting descent needs a fine side >= 4");
+            return ISIS_ERR_INVALID_ARG;
+        }
         hipLaunchKernelGGL((k_defect_restrict<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m,
                            nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, rr_c);
+    }
     LAUNCH_CHECK(err, "k_defect_restrict");
+    if (dfine) {
+        int r = launch_restrict_fw<T>(nf, dfine, rr_c, s, err);
+        if (r) return r;
+    }
     hipLaunchKernelGGL((k_fas_sigma<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m, nc, ih2c,
                        phi_c, eta_c, rr_c, sigma_c);
     LAUNCH_CHECK(err, "k_fas_sigma");
@@ -385,6 +424,7 @@ struct isis_mg {
     // any level, created on the first isis_mg_set_profiling(h, 1)
     static constexpr int kMaxTimed = 2048;
     int tb;  // temporal block of the current solve (desc.temporal_block resolved)
+    int fw;  // full-weighting restriction of the defect (desc.restriction resolved)
     int profile;
     int ntimed;
     int events_ready;
@@ -486,6 +526,10 @@ bool valid_desc(const isis_mg_desc* d, char* err)
     }
     if (!(d->guess_accept == 0.0 || (d->guess_accept > 0.0 && d->guess_accept <= 1.0))) {
         fmt_err(err, "guess_accept must be 0 (automatic) or in (0, 1]");
+        return false;
+    }
+    if (d->restriction < -1 || d->restriction > 1) {
+        fmt_err(err, "restriction must be -1 (per model), 0 (mean) or 1 (full weighting)");
         return false;
     }
     return true;
@@ -602,11 +646,12 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
         return ISIS_OK;
     }
     LevP<T>& c = L[l + 1];
-    const int tb = H->tb;
     if ((r = timed_sweeps<T, M>(H, m, f, l, d.nu_pre))) return r;
     *updates += d.nu_pre * n3;
+    // full weighting: the fine defect goes through the level's scratch field,
+    // free between the smoothing steps
     if ((r = launch_descend<T, M>(m, f.n, f.h, f.phi, f.eta, f.sigma, c.eta, c.phi, c.phihat,
-                                  c.sigma, c.rr, H->s, H->err)))
+                                  c.sigma, c.rr, H->s, H->err, H->fw ? f.tmp : nullptr)))
         return r;
     if ((r = vcycle<T, M>(H, m, L, l + 1, updates))) return r;
     if ((r = launch_prolong<T>(f.n, f.phi, c.phi, c.phihat, H->s, H->err))) return r;
@@ -1026,6 +1071,13 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
     H->tb = H->d.temporal_block >= 0 ? H->d.temporal_block
             : (params->model == ISIS_FR_HS || params->model == ISIS_CHAMELEON) ? 1 : 2;
     if (stats) stats->temporal_block = H->tb;
+    // Per-model restriction of the defect (desc.restriction = -1): full
+    // weighting for f(R), whose V-cycles it speeds up (measured on the 512^3
+    // halo workload with the oracle: 14 -> 11 cycles to 1e-8); the 8-child
+    // mean for the canonical models and the chameleon, where full weighting
+    // measured one to two cycles more.
+    H->fw = H->d.restriction >= 0 ? H->d.restriction : (params->model == ISIS_FR_HS ? 1 : 0);
+    if (stats) stats->restriction = H->fw;
     int r;
     switch (params->model) {
     case ISIS_SYMMETRON:
@@ -1209,7 +1261,7 @@ int isis_op_restrict(int n_fine, const double* fine, double* coarse, void* strea
 int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double h_fine,
                         const double* phi_f, const double* eta_f, const double* sigma_f,
                         const double* eta_c, double* phi_c, double* phihat_c, double* sigma_c,
-                        double* rr_c, void* stream)
+                        double* rr_c, double* fine_scratch, void* stream)
 {
     if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
     if (!op_grid_ok(n_fine, 4) || !finite_pos(h_fine) || !phi_f || !eta_f || !eta_c || !phi_c ||
@@ -1217,13 +1269,23 @@ int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double
         fmt_err(g_err, "fas_descend: need even n_fine >= 4, h > 0, non-NULL arrays");
         return ISIS_ERR_INVALID_ARG;
     }
-    if (!ptrs_aligned({phi_f, eta_f, sigma_f, eta_c, phi_c, phihat_c, sigma_c, rr_c}))
+    if (!ptrs_aligned({phi_f, eta_f, sigma_f, eta_c, phi_c, phihat_c, sigma_c, rr_c, fine_scratch}))
         return ISIS_ERR_INVALID_ARG;
     return with_model<double>(*p, a, [&](auto m) {
         return launch_descend<double, decltype(m)>(m, n_fine, h_fine, phi_f, eta_f, sigma_f,
                                                    eta_c, phi_c, phihat_c, sigma_c, rr_c,
-                                                   (hipStream_t)stream, g_err);
+                                                   (hipStream_t)stream, g_err, fine_scratch);
     });
+}
+
+int isis_op_restrict_fw(int n_fine, const double* fine, double* coarse, void* stream)
+{
+    if (!op_grid_ok(n_fine, 2) || !fine || !coarse) {
+        fmt_err(g_err, "restrict_fw: need even n_fine >= 2 and non-NULL arrays");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!ptrs_aligned({fine, coarse})) return ISIS_ERR_INVALID_ARG;
+    return launch_restrict_fw<double>(n_fine, fine, coarse, (hipStream_t)stream, g_err);
 }
 
 int isis_op_prolong_correct(int n_fine, double* fine, const double* coarse,

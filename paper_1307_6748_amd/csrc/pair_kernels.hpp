@@ -14,12 +14,14 @@ namespace isis {
 // FAS descent, first half (see k_defect_restrict): one thread per coarse
 // cell.  The 32 fine values its 8 stencils touch are loaded once (as pairs
 // along z); for f(R) their e^phi are computed once as well (32 instead of 56
-// exponentials per coarse cell).
+// exponentials per coarse cell).  With dfine (full-weighting restriction of
+// the defect) the fine defect L - sigma is written there instead of its
+// 8-child mean into rr_c.
 template <class T, class M>
 __global__ __launch_bounds__(kBlock) void k_defect_restrict_pairs(
     M m, int nf, T ih2, const T* __restrict__ phi, const T* __restrict__ eta,
     const T* __restrict__ sigma, T* __restrict__ phi_c, T* __restrict__ phihat_c,
-    T* __restrict__ rr_c)
+    T* __restrict__ rr_c, T* __restrict__ dfine = nullptr)
 {
     using V = typename Vec2<T>::type;
     using SO = StageOp<T, M>;
@@ -88,6 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_pairs(
                 const V e2 = *reinterpret_cast<const V*>(eta + o);
                 V s2 = V{T(0), T(0)};
                 if (sigma) s2 = *reinterpret_cast<const V*>(sigma + o);
+                V rv;
 #pragma unroll
                 for (int dk = 0; dk < 2; ++dk) {
                     // neighbour order x-, x+, y-, y+, z-, z+
@@ -112,14 +115,16 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_pairs(
                     } else {
                         m.op(p, nb, e2[dk], ih2, L, D);
                     }
-                    sr += L - (sigma ? s2[dk] : T(0));
+                    rv[dk] = L - (sigma ? s2[dk] : T(0));
+                    sr += rv[dk];
                     sp += p;
                 }
+                if (dfine) *reinterpret_cast<V*>(dfine + o) = rv;
             }
         const T pc = sp / T(8);
         phi_c[q] = pc;
         phihat_c[q] = pc;
-        rr_c[q] = sr / T(8);
+        if (!dfine) rr_c[q] = sr / T(8);
     }
 }
 
@@ -206,11 +211,13 @@ constexpr int restrict_tiled_lds_bytes()
     return 4 * RestrictTileF::PLANE * (int)sizeof(T) * (StageOp<T, M>::kStaged ? 2 : 1);
 }
 
-template <class T, class M, bool SIG>
+// FW: the fine defect L - sigma goes to dfine (full-weighting restriction of
+// the defect follows in k_restrict_fw_tiled) instead of its mean to rr_c.
+template <class T, class M, bool SIG, bool FW = false>
 __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
     M m, int nf, T ih2, const T* __restrict__ phi, const T* __restrict__ eta,
     const T* __restrict__ sigma, T* __restrict__ phi_c, T* __restrict__ phihat_c,
-    T* __restrict__ rr_c)
+    T* __restrict__ rr_c, T* __restrict__ dfine = nullptr)
 {
     using G = RestrictTileF;
     using V = typename Vec2<T>::type;
@@ -309,6 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
 #pragma unroll
             for (int dj = 0; dj < 2; ++dj) {
                 const int o = o00 + dj * G::EZ;
+                V rv;
                 const V c = *reinterpret_cast<const V*>(cu + o);
                 const V xm = *reinterpret_cast<const V*>(pv + o);
                 const V xp = *reinterpret_cast<const V*>(nx + o);
@@ -348,16 +356,20 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
                     } else {
                         m.op(c[dk], nbv, e2[di][dj][dk], ih2, L, D);
                     }
-                    sr += L - s2[di][dj][dk];
+                    rv[dk] = L - s2[di][dj][dk];
+                    sr += rv[dk];
                     sp += c[dk];
                 }
+                if constexpr (FW)
+                    *reinterpret_cast<V*>(dfine + (size_t)(x & msk) * nf2 +
+                                          (dj ? coff1 : coff0)) = rv;
             }
         }
         const size_t q = ((size_t)I * nc + (y0 / 2 + jj)) * nc + z0 / 2 + kk;
         const T pc = sp / T(8);
         phi_c[q] = pc;
         phihat_c[q] = pc;
-        rr_c[q] = sr / T(8);
+        if constexpr (!FW) rr_c[q] = sr / T(8);
         __syncthreads();  // the slots of planes 2I-1, 2I are refilled next
     }
 }

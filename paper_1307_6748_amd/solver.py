@@ -113,6 +113,7 @@ class Stats:
     rho_hist: list = field(default_factory=list)  # per-cycle factors, [0] = 0
     safeguard_hits: int = 0  # symmetron: updates with the safeguarded denominator
     ms_smooth: float = 0.0   # profiling on: all smoothing kernels, all levels
+    restriction: int = 0     # defect restriction used: 0 mean, 1 full weighting
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
@@ -120,7 +121,8 @@ class Stats:
                      list(s.rel_hist[: s.cycles + 1]), s.ms_total, s.cell_updates,
                      bool(s.used_guess), list(s.fine_sweep_ms), list(s.fine_sweep_launches),
                      list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block,
-                     list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth)
+                     list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth,
+                     s.restriction)
 
 
 def _ptr(t: torch.Tensor | None):
@@ -147,17 +149,20 @@ class Solver:
     The workspace is a torch uint8 tensor on the current device; kernels run
     on the torch stream current at construction.  temporal_block = -1 (the
     default) lets the library pick the sweeps per HBM pass for each model;
-    0, 1, 2 force one choice (see isis_mg_desc)."""
+    0, 1, 2 force one choice (see isis_mg_desc).  restriction = -1 (the
+    default) restricts the defect by full weighting for f(R) and by the
+    8-child mean otherwise; 0 / 1 force the mean / full weighting."""
 
     def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = 2,
                  nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
-                 temporal_block: int = -1, fp32_floor: float = 0.0, guess_accept: float = 0.0):
+                 temporal_block: int = -1, fp32_floor: float = 0.0, guess_accept: float = 0.0,
+                 restriction: int = -1):
         self.N, self.box = int(N), float(box)
         self._h = None
         lib = A.lib()
         d = A.DescC(self.N, self.box, nu_pre, nu_post, nu_coarse, max_cycles,
                     PRECISIONS[precision], float(fp32_floor), temporal_block, _stream(), None, 0,
-                    float(guess_accept))
+                    float(guess_accept), int(restriction))
         nbytes = lib.isis_mg_workspace_size(C.byref(d))
         if nbytes == 0:
             raise ValueError("invalid solver description (N, box, nu_*, max_cycles, precision, "
@@ -291,18 +296,30 @@ def restrict(fine, out=None):
     return out
 
 
-def fas_descend(params: ModelParams, a: float, h_fine: float, phi_f, eta_f, sigma_f, eta_c):
+def fas_descend(params: ModelParams, a: float, h_fine: float, phi_f, eta_f, sigma_f, eta_c,
+                full_weighting: bool = False):
     n = _side(phi_f)
     _check_field(phi_f, n, "phi_f")
     _check_field(eta_f, n, "eta_f")
     _check_field(eta_c, n // 2, "eta_c")
     mk = lambda: torch.empty_like(eta_c)  # noqa: E731
     phi_c, phihat_c, sigma_c, rr_c = mk(), mk(), mk(), mk()
+    scratch = torch.empty_like(phi_f) if full_weighting else None
     pc = params.c()
     _ok(A.lib().isis_op_fas_descend(C.byref(pc), float(a), n, float(h_fine), _ptr(phi_f),
                                     _ptr(eta_f), _ptr(sigma_f), _ptr(eta_c), _ptr(phi_c),
-                                    _ptr(phihat_c), _ptr(sigma_c), _ptr(rr_c), _stream()))
+                                    _ptr(phihat_c), _ptr(sigma_c), _ptr(rr_c), _ptr(scratch),
+                                    _stream()))
     return phi_c, phihat_c, sigma_c
+
+
+def restrict_fw(fine, out=None):
+    """Full-weighting restriction (the adjoint of the prolongation over 8)."""
+    n = _side(fine)
+    _check_field(fine, n, "fine")
+    out = torch.empty(fine.numel() // 8, dtype=fine.dtype, device=fine.device) if out is None else out
+    _ok(A.lib().isis_op_restrict_fw(n, _ptr(fine), _ptr(out), _stream()))
+    return out
 
 
 def prolong_correct(fine, coarse, coarse_hat):

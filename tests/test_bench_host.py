@@ -87,3 +87,26 @@ def test_roofline_head_is_the_kernel_with_most_time(monkeypatch):
     assert head["frac"] == pytest.approx(head["achieved"] / 8000.0)
     assert head["peak"] == 8000.0 and head["traffic"] is None
     assert ", 1, " in head["kernel"] and ", 2, " in ks[1]["kernel"]
+
+
+def test_solve_bytes_counts_every_kernel_once():
+    """The whole-solve byte model of the benchmark's roofline, by hand on a
+    16^3 FP64 solve of one V-cycle (levels 16, 8, 4; per-colour kernels): the
+    density hierarchy (8 B per cell over 8/7 of the cells), cold start and
+    r_ref (32 B), per level 4 smoothing passes of 3 (4 with Sigma) values, the
+    descent, the coarse source, the correction, the 4^3 level and the judge."""
+    import types
+
+    import bench
+    n3 = 16 ** 3
+    st = types.SimpleNamespace(cycles=1, cycles_fp32=0, restriction=0)
+    want = n3 * (8 * 8 / 7 + 32)
+    want += n3 * (4 * 3 * 8 + (2 * 8 + 3) + 4 + (16 + 2))          # level 16
+    want += 512 * (4 * 4 * 8 + (3 * 8 + 3) + 4 + (16 + 2))          # level 8
+    want += 64 * 4 * 8                                               # level 4
+    want += n3 * 16                                                  # judge
+    assert abs(bench.solve_bytes(16, st, 0, (2, 2), False) - want) <= 1e-9 * want
+    # full weighting adds the fine defect's write and read on levels 16 and 8
+    st.restriction = 1
+    fw = want + 2 * 8 * (n3 + 512)
+    assert abs(bench.solve_bytes(16, st, 0, (2, 2), False) - fw) <= 1e-9 * fw

@@ -54,7 +54,8 @@ def test_workspace_size_validation():
                 dict(precision=7), dict(temporal_block=3), dict(temporal_block=-2), dict(nu_pre=0, nu_post=0),
                 dict(fp32_floor=-1e-6), dict(fp32_floor=2.0), dict(fp32_floor=1e-13),
                 dict(fp32_floor=float("nan")), dict(guess_accept=-0.1),
-                dict(guess_accept=1.5), dict(guess_accept=float("nan"))):
+                dict(guess_accept=1.5), dict(guess_accept=float("nan")),
+                dict(restriction=2), dict(restriction=-2)):
         assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad
 
 
@@ -115,7 +116,11 @@ def test_ops_reject_misaligned_pointers_on_host():
     assert lib.isis_op_halfsweep(C.byref(p), 1.0, 8, 1.0, ok, ok, bad, 0, None) == -1
     assert lib.isis_op_sweeps(C.byref(p), 1.0, 8, 1.0, ok, bad, ok, None, 1, 0, None) == -1
     assert lib.isis_op_fas_descend(C.byref(p), 1.0, 8, 1.0, ok, ok, None, ok, ok, ok, ok, bad,
-                                   None) == -1
+                                   None, None) == -1
+    assert lib.isis_op_fas_descend(C.byref(p), 1.0, 8, 1.0, ok, ok, None, ok, ok, ok, ok, ok,
+                                   bad, None) == -1
+    assert lib.isis_op_restrict_fw(8, ok, bad, None) == -1
+    assert lib.isis_op_restrict_fw(7, ok, ok, None) == -1
     assert lib.isis_op_coarse_solve(C.byref(p), 1.0, 1.0, bad, ok, None, 4, None) == -1
     assert lib.isis_op_cold_start(C.byref(p), 1.0, 8, ok, bad, None) == -1
 

@@ -81,8 +81,10 @@ def test_prolong_correct(orc, n):
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("n", [4, 12, 32, 64])
 @pytest.mark.parametrize("with_sigma", [False, True])
-def test_fas_descend(orc, name, n, with_sigma):
-    """phi_c = phihat_c = R phi_f; sigma_c = L_c(R phi_f) - R(L_f(phi_f) - sigma_f)."""
+@pytest.mark.parametrize("fw", [False, True])
+def test_fas_descend(orc, name, n, with_sigma, fw):
+    """phi_c = phihat_c = R phi_f; sigma_c = L_c(R phi_f) - R'(L_f(phi_f) - sigma_f),
+    R' the 8-child mean or full weighting."""
     from paper_1307_6748_amd import solver as S
     om, sp, a = models(name)
     h = 0.9
@@ -92,15 +94,28 @@ def test_fas_descend(orc, name, n, with_sigma):
     eta_c = orc.restrict(eta)
     # oracle: the steps of the descent, as the oracle's V-cycle takes them
     phi_c = orc.restrict(phi)
-    rr = orc.restrict(orc.defect(om, h, phi, eta, sig))
+    d = orc.defect(om, h, phi, eta, sig)
+    rr = orc.restrict_fw(d) if fw else orc.restrict(d)
     sigma_c = orc.defect(om, 2 * h, phi_c, eta_c) - rr
     gphi_c, gphihat_c, gsigma_c = S.fas_descend(sp, a, h, dev(phi), dev(eta),
-                                                None if sig is None else dev(sig), dev(eta_c))
+                                                None if sig is None else dev(sig), dev(eta_c),
+                                                full_weighting=fw)
     nc = n // 2
     assert np.max(np.abs(cubic(gphi_c, nc) - phi_c)) <= 1e-15 * (np.abs(phi_c).max() + 1)
     assert np.array_equal(cubic(gphi_c, nc), cubic(gphihat_c, nc))
     tol = 1e-14 * (_scale(phi, h) + np.abs(sigma_c).max())
     assert np.max(np.abs(cubic(gsigma_c, nc) - sigma_c)) <= tol
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 12, 64, 128, 256])
+def test_restrict_fw(orc, n):
+    """Full-weighting restriction vs the oracle: the per-cell kernel on small
+    or non-power-of-two grids, the LDS-staged one from 64^3 (wrap included)."""
+    from paper_1307_6748_amd import solver as S
+    f = np.random.default_rng(n).standard_normal((n, n, n))
+    ref = orc.restrict_fw(f)
+    got = cubic(S.restrict_fw(dev(f)), n // 2)
+    assert np.max(np.abs(got - ref)) <= 1e-15 * np.abs(f).max() * 4
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -64,6 +64,12 @@ MUTATIONS = {
                        "return sqrt(sumsq(nn, r) / (double)(nn * nn));"),
     "r_ref_not_normalised": ("double r_ref = orc_rms(n, lv[0].work);",
                              "double r_ref = sqrt(sumsq(n, lv[0].work));"),
+    "full_weighting_weights": ("const double w[4] = {0.125, 0.375, 0.375, 0.125};",
+                               "const double w[4] = {0.25, 0.25, 0.25, 0.25};"),
+    "full_weighting_offset": ("fine[cidx(nf, wrap(2 * I - 1 + a, nf), wrap(2 * J - 1 + b, nf),",
+                              "fine[cidx(nf, wrap(2 * I + a, nf), wrap(2 * J - 1 + b, nf),"),
+    "full_weighting_not_used": ("    if (cfg->restrict_fw)\n        orc_restrict_fw(",
+                                "    if (0)\n        orc_restrict_fw("),
     "paper_u_a4_factor": ("- om * a * a * a * a * H2 * g * c * e +",
                           "- om * a * a * a * H2 * g * c * e +"),
     "paper_u_cold_shift_missing": ("if (m->paper_u) phi[c] += log(m->a * m->a * m->fR0_abs);",

@@ -509,11 +509,14 @@ def _mats_1d(n, h):
     return D / h ** 2
 
 
-def test_fas_two_grid_equals_textbook_correction_scheme(orc):
+@pytest.mark.parametrize("fw", [False, True])
+def test_fas_two_grid_equals_textbook_correction_scheme(orc, fw):
     """On a linear problem FAS is the linear correction scheme (Sec. 3.1):
     two levels (8^3 -> 4^3) with an exact coarse solve give
     phi <- S^nu2 (phi + P A_c^-1 R (b - A S^nu1 phi)), built here from dense
-    matrices (A = lap - m2, R = mean of 8 children, P = trilinear)."""
+    matrices (A = lap - m2, P = trilinear, R = mean of 8 children, or with
+    full weighting R = P^T / 8 for the defect -- reading 2's option; phi is
+    restricted by the mean in both, which the linear scheme does not see)."""
     n, box, kappa, m2 = 8, 8.0, 1.0, 1.0
     h = box / n
     I1 = np.eye(n)
@@ -534,6 +537,8 @@ def test_fas_two_grid_equals_textbook_correction_scheme(orc):
         q = (p + (1 if i % 2 else -1)) % nc
         P1[i, p] += 0.75
         P1[i, q] += 0.25
+    if fw:
+        R1 = P1.T / 2.0
     R = np.kron(np.kron(R1, R1), R1)
     P = np.kron(np.kron(P1, P1), P1)
     idx = np.indices((n, n, n)).reshape(3, -1)
@@ -556,8 +561,49 @@ def test_fas_two_grid_equals_textbook_correction_scheme(orc):
     for _ in range(2):
         x = gs(x)
     m = orc.Model(model=orc.LINEAR, kappa=kappa, m2=m2)
-    r = orc.vcycles(m, eta, box, phi.reshape(n, n, n), 1, orc.Cfg(nu_coarse=400))
+    r = orc.vcycles(m, eta, box, phi.reshape(n, n, n), 1, orc.Cfg(nu_coarse=400, restrict_fw=fw))
     assert np.max(np.abs(r.phi.ravel() - x)) < 1e-12 * np.max(np.abs(x))
+
+
+def test_full_weighting_restriction(orc):
+    """Reading 2's option, full weighting R = P^T / 8: adjoint of the
+    prolongation (<R f, c> = <f, P c> / 8 for random fields), constants kept,
+    totals preserved (sum of the coarse field = sum of the fine one / 8).  On
+    a product of sines of wavenumbers k_d it returns the same product at the
+    coarse centres times prod_d cos^3(k_d h / 2) (the 8-child mean: times
+    prod_d cos(k_d h / 2))."""
+    n, box = 16, 10.0
+    h = box / n
+    f = synth.random_field(n, 51, scale=2.0, offset=-1.0)
+    c = synth.random_field(n // 2, 52, scale=2.0, offset=-1.0)
+    Pc = orc.prolong_correct(np.zeros((n, n, n)), c, np.zeros((n // 2,) * 3))
+    Rf = orc.restrict_fw(f)
+    assert abs(np.sum(Rf * c) - np.sum(f * Pc) / 8.0) <= 1e-13 * np.sum(np.abs(f * Pc))
+    assert np.max(np.abs(orc.restrict_fw(np.full((n, n, n), 3.7)) - 3.7)) <= 8 * 2.0 ** -52 * 3.7
+    assert abs(np.sum(Rf) - np.sum(f) / 8.0) <= 1e-12 * np.sum(np.abs(f))
+    modes = (1, 3, 2)
+    s_f = synth.sine_mode(n, box, modes)
+    s_c = synth.sine_mode(n // 2, box, modes)
+    th = [np.pi * m * h / box for m in modes]  # k h / 2
+    g_fw = np.prod([np.cos(t) ** 3 for t in th])
+    g_mean = np.prod([np.cos(t) for t in th])
+    assert np.max(np.abs(orc.restrict_fw(s_f) - g_fw * s_c)) <= 1e-14
+    assert np.max(np.abs(orc.restrict(s_f) - g_mean * s_c)) <= 1e-14
+
+
+def test_solution_does_not_depend_on_the_restriction(orc):
+    """Reading 2: the restriction changes the convergence factors, not the
+    discrete root: f(R) and symmetron solves with the mean and with full
+    weighting of the defect agree to their tolerance."""
+    w = synth.workload("small_symmetron", 16)
+    for m in (orc.Model(model=orc.FR_HS, a=1.0, n=1.0, fR0_abs=1e-5, omega_m=0.27,
+                        omega_l=0.73),
+              orc.Model(model=orc.SYMMETRON, a=1.0, lambda0=1.0, a_ssb=0.5)):
+        r0 = orc.solve(m, w["eta"], w["box"], tol=1e-13, cfg=orc.Cfg(restrict_fw=False))
+        r1 = orc.solve(m, w["eta"], w["box"], tol=1e-13, cfg=orc.Cfg(restrict_fw=True))
+        assert r0.status == orc.OK and r1.status == orc.OK
+        assert np.max(np.abs(r1.phi - r0.phi)) <= 1e-10 * np.max(np.abs(r0.phi))
+        assert not np.allclose(r0.rel_hist[1:3], r1.rel_hist[1:3], rtol=1e-3)
 
 
 def test_fas_fixed_point(orc):
