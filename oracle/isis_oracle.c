@@ -716,3 +716,190 @@ void orc_force(const orc_model* m, int n, double h, const double* field, const d
                 }
             }
 }
+
+/* ------------------------------------------------------------------ */
+/* Refinement boundaries with masks (Sec. 3.3.1, 3.4.1).               */
+/* ------------------------------------------------------------------ */
+/* A refinement patch is an n^3 grid at spacing h whose cells carry a mask
+ * m: m > 0 for cells whose centre lies inside the refinement (they are
+ * relaxed with the discretisation above), m <= 0 for cells outside it
+ * (m = -1: the cell does not exist on this level; -1 < m <= 0: it exists,
+ * its centre outside the boundary, on coarser levels where the mask is
+ * restricted).  The boundary lies where the linear interpolation of the mask
+ * between two cell centres crosses zero.  Indices wrap periodically; a patch
+ * keeps a layer of m = -1 cells around its inside, so the wrap never joins
+ * inside cells.
+ *
+ * At an inside cell c with a masked neighbour f (m_f <= 0) the neighbour's
+ * value is replaced by the ghost value of eq. ueq,
+ *     u_G = u_f^Int + (m_f / m_c) (u_c - u_c^Pre),
+ * u_f^Int = u_f^Pre if -1 < m_f <= 0, else the value interpolated from the
+ * coarse grid (given in u_int); u^Pre is the field at the time the boundary
+ * values were set (given in u_pre).  This is the linear extrapolation through
+ * u_c and the boundary value u_# of eq. bpsi.  For the non-canonical operator
+ * the face coefficient uses b(u_G) (the consistent choice of Sec. 3.4.1).
+ * Since u_G depends on u_c, the Newton denominator gains
+ *     canonical:     (m_f/m_c) / h^2                       (d L/d u_f = 1/h^2),
+ *     non-canonical: (m_f/m_c) [b_f + b'(u_G) (u_G - u_c)/2] / h^2
+ * per masked face (the two extra terms printed in Sec. 3.4.1).  Cells with
+ * m <= 0 are not relaxed and have no residual. */
+
+static int orc_inside(double mk) { return mk > 0.0; }
+
+/* L(phi)_c at an inside cell with ghost values for masked neighbours; D gets
+ * the Newton denominator with the extra ghost terms. */
+static double op_cell_masked(const orc_model* m, long n, double h, const double* phi,
+                             const double* eta, const double* mask, const double* u_int,
+                             const double* u_pre, long i, long j, long k, double* D)
+{
+    const long c = cidx(n, i, j, k);
+    const long nbi[6] = {cidx(n, wrap(i - 1, n), j, k), cidx(n, wrap(i + 1, n), j, k),
+                         cidx(n, i, wrap(j - 1, n), k), cidx(n, i, wrap(j + 1, n), k),
+                         cidx(n, i, j, wrap(k - 1, n)), cidx(n, i, j, wrap(k + 1, n))};
+    const double p = phi[c];
+    const double mc = mask[c];
+    double v[6], r[6]; /* neighbour values (ghost where masked), d v / d u_c */
+    for (int f = 0; f < 6; ++f) {
+        const long q = nbi[f];
+        if (orc_inside(mask[q])) {
+            v[f] = phi[q];
+            r[f] = 0.0;
+        } else {
+            const double uint_f = mask[q] > -1.0 ? u_pre[q] : u_int[q]; /* eq. bpsi */
+            r[f] = mask[q] / mc;
+            v[f] = uint_f + r[f] * (p - u_pre[c]); /* eq. ueq */
+        }
+    }
+    const double ih2 = 1.0 / (h * h);
+    double S, dS;
+    orc_source(m, p, eta[c], &S, &dS);
+    if (m->model == ORC_FR_HS || m->model == ORC_CHAMELEON) {
+        const double bc = exp(p);
+        double flux = 0.0, dflux = 0.0;
+        for (int f = 0; f < 6; ++f) {
+            const double bg = exp(v[f]);
+            const double bf = 0.5 * (bc + bg);
+            flux += bf * (v[f] - p);
+            dflux += 0.5 * bc * (v[f] - p) - bf;
+            dflux += r[f] * (bf + 0.5 * bg * (v[f] - p)); /* ghost terms, Sec. 3.4.1 */
+        }
+        if (D) *D = dflux * ih2 - dS;
+        return flux * ih2 - S;
+    }
+    double sum = v[0] + v[1] + v[2] + v[3] + v[4] + v[5];
+    double lap = (sum - 6.0 * p) * ih2;
+    if (D) {
+        double g = 0.0;
+        for (int f = 0; f < 6; ++f) g += r[f];
+        if (m->model == ORC_SYMMETRON)
+            *D = -6.0 * ih2 - fabs(dS) + g * ih2; /* reading R10 */
+        else
+            *D = -6.0 * ih2 - dS + g * ih2;
+    }
+    return lap - S;
+}
+
+/* out = L(phi) - Sigma at inside cells (Sigma may be NULL), 0 elsewhere. */
+void orc_masked_defect(const orc_model* m, int n, double h, const double* phi, const double* eta,
+                       const double* sigma, const double* mask, const double* u_int,
+                       const double* u_pre, double* out)
+{
+    long nn = n;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nn; ++i)
+        for (long j = 0; j < nn; ++j)
+            for (long k = 0; k < nn; ++k) {
+                long c = cidx(nn, i, j, k);
+                if (!orc_inside(mask[c])) {
+                    out[c] = 0.0;
+                    continue;
+                }
+                double L = op_cell_masked(m, nn, h, phi, eta, mask, u_int, u_pre, i, j, k, NULL);
+                out[c] = L - (sigma ? sigma[c] : 0.0);
+            }
+}
+
+/* The Newton denominator at inside cells (0 elsewhere). */
+void orc_masked_newton_diag(const orc_model* m, int n, double h, const double* phi,
+                            const double* eta, const double* mask, const double* u_int,
+                            const double* u_pre, double* out)
+{
+    long nn = n;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nn; ++i)
+        for (long j = 0; j < nn; ++j)
+            for (long k = 0; k < nn; ++k) {
+                long c = cidx(nn, i, j, k);
+                double D = 0.0;
+                if (orc_inside(mask[c]))
+                    op_cell_masked(m, nn, h, phi, eta, mask, u_int, u_pre, i, j, k, &D);
+                out[c] = D;
+            }
+}
+
+/* One colour of the red-black Newton-Gauss-Seidel sweep over the inside
+ * cells (Sec. 3.2 with the ghost values above); masked cells keep their
+ * values. */
+void orc_masked_halfsweep(const orc_model* m, int n, double h, double* phi, const double* eta,
+                          const double* sigma, const double* mask, const double* u_int,
+                          const double* u_pre, int colour)
+{
+    long nn = n;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nn; ++i)
+        for (long j = 0; j < nn; ++j)
+            for (long k = (i + j + colour) & 1; k < nn; k += 2) {
+                long c = cidx(nn, i, j, k);
+                if (!orc_inside(mask[c])) continue;
+                double D;
+                double L = op_cell_masked(m, nn, h, phi, eta, mask, u_int, u_pre, i, j, k, &D);
+                double eps = L - (sigma ? sigma[c] : 0.0);
+                double step = eps / D;
+                if (m->model == ORC_CHAMELEON) /* reading R15 */
+                    step = fmax(-ORC_CHAM_MAX_STEP, fmin(ORC_CHAM_MAX_STEP, step));
+                phi[c] = phi[c] - step;
+            }
+}
+
+/* RMS of the masked defect over the inside cells. */
+static double masked_rms(const orc_model* m, int n, double h, const double* phi,
+                         const double* eta, const double* mask, const double* u_int,
+                         const double* u_pre, double* work)
+{
+    orc_masked_defect(m, n, h, phi, eta, NULL, mask, u_int, u_pre, work);
+    long n3 = (long)n * n * n, inside = 0;
+    for (long q = 0; q < n3; ++q) inside += orc_inside(mask[q]);
+    return inside ? sqrt(sumsq(n, work) / (double)inside) : 0.0;
+}
+
+/* Relaxation solve of a refinement patch: blocks of `block` red-black sweeps,
+ * each block starting with u_pre = phi (the boundary values are set again,
+ * Sec. 3.4.1), until the RMS defect over the inside cells is <= tol (absolute)
+ * or max_sweeps sweeps are done.  Returns the sweeps made (negative on bad
+ * arguments); *rms receives the final RMS defect. */
+int orc_patch_solve(const orc_model* m, int n, double h, double* phi, const double* eta,
+                    const double* mask, const double* u_int, int block, int max_sweeps,
+                    double tol, double* rms)
+{
+    if (n < 2 || (n & 1) || block < 1 || max_sweeps < 0 || !valid_model(m)) return -1;
+    long n3 = (long)n * n * n;
+    double* pre = (double*)malloc(sizeof(double) * (size_t)n3);
+    double* work = (double*)malloc(sizeof(double) * (size_t)n3);
+    memcpy(pre, phi, sizeof(double) * (size_t)n3);
+    double r = masked_rms(m, n, h, phi, eta, mask, u_int, pre, work);
+    int sweeps = 0;
+    while (r > tol && sweeps < max_sweeps) {
+        memcpy(pre, phi, sizeof(double) * (size_t)n3);
+        for (int b = 0; b < block && sweeps < max_sweeps; ++b, ++sweeps) {
+            orc_masked_halfsweep(m, n, h, phi, eta, NULL, mask, u_int, pre, 0);
+            orc_masked_halfsweep(m, n, h, phi, eta, NULL, mask, u_int, pre, 1);
+        }
+        /* the residual with the boundary values of the final field */
+        memcpy(pre, phi, sizeof(double) * (size_t)n3);
+        r = masked_rms(m, n, h, phi, eta, mask, u_int, pre, work);
+    }
+    if (rms) *rms = r;
+    free(pre);
+    free(work);
+    return sweeps;
+}

@@ -141,6 +141,14 @@ def lib():
         L.orc_rms.argtypes = [C.c_int, dp]
         L.orc_rms.restype = C.c_double
         L.orc_num_levels.argtypes = [C.c_int]
+        L.orc_masked_defect.argtypes = [C.POINTER(_Model), C.c_int, C.c_double, dp, dp, C.c_void_p,
+                                        dp, dp, dp, dp]
+        L.orc_masked_newton_diag.argtypes = [C.POINTER(_Model), C.c_int, C.c_double, dp, dp, dp,
+                                             dp, dp, dp]
+        L.orc_masked_halfsweep.argtypes = [C.POINTER(_Model), C.c_int, C.c_double, dp, dp,
+                                           C.c_void_p, dp, dp, dp, C.c_int]
+        L.orc_patch_solve.argtypes = [C.POINTER(_Model), C.c_int, C.c_double, dp, dp, dp, dp, C.c_int,
+                                      C.c_int, C.c_double, C.POINTER(C.c_double)]
         L.orc_guard_hits.argtypes = [C.c_int]
         L.orc_guard_hits.restype = C.c_longlong
         L.orc_solve.argtypes = [C.POINTER(_Model), C.POINTER(_Cfg), C.c_int, C.c_double, dp,
@@ -259,6 +267,53 @@ def cold_start(m: Model, eta) -> np.ndarray:
     mc = m._c()
     lib().orc_cold_start(C.byref(mc), eta.size, eta, out)
     return out
+
+
+def masked_defect(m: Model, h: float, phi, eta, mask, u_int, u_pre, sigma=None) -> np.ndarray:
+    """L - Sigma at the inside cells (mask > 0) of a refinement patch, with
+    ghost values for masked neighbours (Sec. 3.3.1, 3.4.1); 0 elsewhere."""
+    phi, eta, mask, u_int, u_pre = (_f64(x) for x in (phi, eta, mask, u_int, u_pre))
+    out = np.empty_like(phi)
+    sig = None if sigma is None else _f64(sigma)
+    mc = m._c()
+    lib().orc_masked_defect(C.byref(mc), phi.shape[0], h, phi, eta, _ptr_or_null(sig), mask,
+                            u_int, u_pre, out)
+    return out
+
+
+def masked_newton_diag(m: Model, h: float, phi, eta, mask, u_int, u_pre) -> np.ndarray:
+    phi, eta, mask, u_int, u_pre = (_f64(x) for x in (phi, eta, mask, u_int, u_pre))
+    out = np.empty_like(phi)
+    mc = m._c()
+    lib().orc_masked_newton_diag(C.byref(mc), phi.shape[0], h, phi, eta, mask, u_int, u_pre, out)
+    return out
+
+
+def masked_halfsweep(m: Model, h: float, phi, eta, mask, u_int, u_pre, sigma=None,
+                     colour: int = 0) -> np.ndarray:
+    out = _f64(phi).copy()
+    eta, mask, u_int, u_pre = (_f64(x) for x in (eta, mask, u_int, u_pre))
+    sig = None if sigma is None else _f64(sigma)
+    mc = m._c()
+    lib().orc_masked_halfsweep(C.byref(mc), out.shape[0], h, out, eta, _ptr_or_null(sig), mask,
+                               u_int, u_pre, int(colour))
+    return out
+
+
+def patch_solve(m: Model, h: float, phi0, eta, mask, u_int, block: int = 4,
+                max_sweeps: int = 10000, tol: float = 1e-10):
+    """Relaxation solve of a refinement patch (blocks of red-black sweeps, the
+    boundary values reset from the field before each block).  Returns
+    (phi, sweeps, rms) with rms the absolute RMS defect over inside cells."""
+    phi = _f64(phi0).copy()
+    eta, mask, u_int = (_f64(x) for x in (eta, mask, u_int))
+    rms = C.c_double()
+    mc = m._c()
+    sw = lib().orc_patch_solve(C.byref(mc), phi.shape[0], h, phi, eta, mask, u_int, int(block),
+                               int(max_sweeps), float(tol), C.byref(rms))
+    if sw < 0:
+        raise ValueError("oracle: invalid patch-solve arguments")
+    return phi, int(sw), rms.value
 
 
 def guard_hits(reset: bool = True) -> int:

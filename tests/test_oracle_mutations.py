@@ -70,6 +70,16 @@ MUTATIONS = {
                               "fine[cidx(nf, wrap(2 * I + a, nf), wrap(2 * J - 1 + b, nf),"),
     "full_weighting_not_used": ("    if (cfg->restrict_fw)\n        orc_restrict_fw(",
                                 "    if (0)\n        orc_restrict_fw("),
+    "amr_ghost_jacobian_dropped": (
+        "            dflux += r[f] * (bf + 0.5 * bg * (v[f] - p)); /* ghost terms, Sec. 3.4.1 */\n",
+        ""),
+    "amr_canonical_ghost_jacobian_dropped": (
+        "            *D = -6.0 * ih2 - fabs(dS) + g * ih2; /* reading R10 */",
+        "            *D = -6.0 * ih2 - fabs(dS); /* reading R10 */"),
+    "amr_int_ignored": ("const double uint_f = mask[q] > -1.0 ? u_pre[q] : u_int[q]; /* eq. bpsi */",
+                        "const double uint_f = u_pre[q]; /* eq. bpsi */"),
+    "amr_ghost_sign": ("v[f] = uint_f + r[f] * (p - u_pre[c]); /* eq. ueq */",
+                       "v[f] = uint_f - r[f] * (p - u_pre[c]); /* eq. ueq */"),
     "paper_u_a4_factor": ("- om * a * a * a * a * H2 * g * c * e +",
                           "- om * a * a * a * H2 * g * c * e +"),
     "paper_u_cold_shift_missing": ("if (m->paper_u) phi[c] += log(m->a * m->a * m->fR0_abs);",
@@ -78,13 +88,14 @@ MUTATIONS = {
                              "const double eup = m->paper_u ? m->a * m->fR0_abs * exp(field[c])"),
 }
 PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py", "test_oracle_models.py",
-             "test_oracle_newton.py"]
+             "test_oracle_newton.py", "test_oracle_amr.py"]
 # The pin file that catches a mutation runs first (the suite stops at its first
 # failure); the other files follow, so every pin still gets its chance.
 FIRST_FILE = {
     "force_": "test_oracle_force.py",
     "chameleon_": "test_oracle_models.py",
     "paper_u_": "test_oracle_models.py",
+    "amr_": "test_oracle_amr.py",
 }
 
 
