@@ -416,6 +416,54 @@ int isis_conv3_bwd_weight(const uint16_t* x, int n, int cin, const uint16_t* dy,
                           float* dw, float* db, void* workspace, size_t workspace_bytes,
                           void* stream);
 
+/* ------------------------------------------------------------------------
+ * Refinement boundaries with masks (Sec. 3.3.1 canonical, Sec. 3.4.1
+ * non-canonical): the operator on a refinement patch, an n^3 grid of spacing
+ * h (indices periodic; n even >= 2) whose cells carry a mask.  Cells with
+ * mask > 0 lie inside the refinement and are relaxed; cells with mask <= 0
+ * lie outside (mask = -1: the cell does not exist on this level and u_int
+ * holds its value interpolated from the coarser grid; -1 < mask <= 0: the
+ * cell exists with its centre outside the boundary and its u_pre value is
+ * used).  The boundary is where the linear interpolation of the mask between
+ * two centres crosses zero.  An inside cell c with a masked neighbour f uses
+ * the ghost value u_G = u_int_f + (mask_f / mask_c)(phi_c - u_pre_c) (eqs.
+ * bpsi, intpsi, ueq; u_int_f replaced by u_pre_f when mask_f > -1), u_pre
+ * being the field when the boundary values were set; the non-canonical face
+ * coefficient is b(u_G), and the Newton denominator gains the ghosts'
+ * dependence on phi_c.  A patch needs a layer of mask = -1 cells around its
+ * inside so that the wrap never joins inside cells.  All arrays are device
+ * n^3 doubles (sigma may be NULL). */
+
+/* out = L(phi) - sigma at inside cells, 0 at the others. */
+int isis_op_masked_defect(const isis_model_params* p, double a, int n, double h,
+                          const double* phi, const double* eta, const double* sigma,
+                          const double* mask, const double* u_int, const double* u_pre,
+                          double* out, void* stream);
+
+/* One colour ((i+j+k) % 2 == colour) of the red-black Newton-Gauss-Seidel
+ * sweep over the inside cells; cells with mask <= 0 keep their values. */
+int isis_op_masked_halfsweep(const isis_model_params* p, double a, int n, double h, double* phi,
+                             const double* eta, const double* sigma, const double* mask,
+                             const double* u_int, const double* u_pre, int colour, void* stream);
+
+/* Bytes of workspace isis_patch_solve needs for an n^3 patch (0 if n is
+ * invalid). */
+size_t isis_patch_workspace_size(int n);
+
+/* Relaxation solve of a refinement patch: blocks of `block` red-black
+ * sweeps, the boundary values (u_pre) set from phi before each block, until
+ * the RMS defect over the inside cells (boundary values from the final
+ * field) is <= tol (absolute) or max_sweeps sweeps are done.  phi: in the
+ * initial field (its outside values are not changed), out the solution.
+ * workspace: device, 256-byte aligned, >= isis_patch_workspace_size(n).
+ * *sweeps_out, *rms_out (host, may be NULL): sweeps made, final RMS.
+ * Returns ISIS_OK, ISIS_ERR_NOT_CONVERGED or ISIS_ERR_DIVERGED; synchronises
+ * the stream once per block. */
+int isis_patch_solve(const isis_model_params* p, double a, int n, double h, double* phi,
+                     const double* eta, const double* mask, const double* u_int, int block,
+                     int max_sweeps, double tol, void* workspace, size_t workspace_bytes,
+                     int* sweeps_out, double* rms_out, void* stream);
+
 /* Acceleration on the grid, the step after the solve in the paper's
  * pipeline: f = -grad(potential) - F, F the scalar-field term of the model's
  * geodesic equation in super-comoving variables:

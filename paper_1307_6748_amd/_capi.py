@@ -71,6 +71,13 @@ SIGNATURES = [
     ("isis_op_fas_descend", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P, _P,
                                  _P, _P, _P, _P]),
     ("isis_op_restrict_fw", _I, [_I, _P, _P, _P]),
+    ("isis_op_masked_defect", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P, _P,
+                                   _P, _P]),
+    ("isis_op_masked_halfsweep", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P,
+                                      _P, _I, _P]),
+    ("isis_patch_workspace_size", C.c_size_t, [_I]),
+    ("isis_patch_solve", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _I, _I, _D,
+                              _P, C.c_size_t, C.POINTER(_I), C.POINTER(_D), _P]),
     ("isis_op_prolong_correct", _I, [_I, _P, _P, _P, _P]),
     ("isis_op_coarse_solve", _I, [C.POINTER(ModelParamsC), _D, _D, _P, _P, _P, _I, _P]),
     ("isis_op_cold_start", _I, [C.POINTER(ModelParamsC), _D, C.c_long, _P, _P, _P]),

@@ -20,6 +20,7 @@
 #include <new>
 
 #include "../../include/isis_mg.h"
+#include "amr.hpp"
 #include "force.hpp"
 #include "full_weighting.hpp"
 #include "fused_sweep.hpp"
@@ -1275,6 +1276,133 @@ int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double
         return launch_descend<double, decltype(m)>(m, n_fine, h_fine, phi_f, eta_f, sigma_f,
                                                    eta_c, phi_c, phihat_c, sigma_c, rr_c,
                                                    (hipStream_t)stream, g_err, fine_scratch);
+    });
+}
+
+static bool masked_args_ok(int n, double h, std::initializer_list<const void*> need)
+{
+    if (!op_grid_ok(n, 2) || !finite_pos(h)) {
+        fmt_err(g_err, "masked operators: need even n >= 2 and h > 0");
+        return false;
+    }
+    for (const void* q : need)
+        if (!q) {
+            fmt_err(g_err, "masked operators: NULL array");
+            return false;
+        }
+    return true;
+}
+
+int isis_op_masked_defect(const isis_model_params* p, double a, int n, double h,
+                          const double* phi, const double* eta, const double* sigma,
+                          const double* mask, const double* u_int, const double* u_pre,
+                          double* out, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!masked_args_ok(n, h, {phi, eta, mask, u_int, u_pre, out})) return ISIS_ERR_INVALID_ARG;
+    if (!ptrs_aligned({phi, eta, sigma, mask, u_int, u_pre, out})) return ISIS_ERR_INVALID_ARG;
+    return with_model<double>(*p, a, [&](auto m) {
+        hipLaunchKernelGGL((k_masked_defect<decltype(m)>), dim3(grid_for((long)n * n * n)),
+                           dim3(kBlock), 0, (hipStream_t)stream, m, n, 1.0 / (h * h), phi, eta,
+                           sigma, mask, u_int, u_pre, out, nullptr);
+        LAUNCH_CHECK(g_err, "k_masked_defect");
+        return (int)ISIS_OK;
+    });
+}
+
+int isis_op_masked_halfsweep(const isis_model_params* p, double a, int n, double h, double* phi,
+                             const double* eta, const double* sigma, const double* mask,
+                             const double* u_int, const double* u_pre, int colour, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!masked_args_ok(n, h, {phi, eta, mask, u_int, u_pre}) || (colour != 0 && colour != 1)) {
+        if (colour != 0 && colour != 1) fmt_err(g_err, "masked halfsweep: colour must be 0 or 1");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!ptrs_aligned({phi, eta, sigma, mask, u_int, u_pre})) return ISIS_ERR_INVALID_ARG;
+    return with_model<double>(*p, a, [&](auto m) {
+        hipLaunchKernelGGL((k_masked_halfsweep<decltype(m)>),
+                           dim3(grid_for((long)n * n * n / 2)), dim3(kBlock), 0,
+                           (hipStream_t)stream, m, n, 1.0 / (h * h), phi, eta, sigma, mask, u_int,
+                           u_pre, colour);
+        LAUNCH_CHECK(g_err, "k_masked_halfsweep");
+        return (int)ISIS_OK;
+    });
+}
+
+size_t isis_patch_workspace_size(int n)
+{
+    if (!op_grid_ok(n, 2)) return 0;
+    return (size_t)n * n * n * sizeof(double) + (2 * kReduceBlocks + 16) * sizeof(double) + 256;
+}
+
+int isis_patch_solve(const isis_model_params* p, double a, int n, double h, double* phi,
+                     const double* eta, const double* mask, const double* u_int, int block,
+                     int max_sweeps, double tol, void* workspace, size_t workspace_bytes,
+                     int* sweeps_out, double* rms_out, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!masked_args_ok(n, h, {phi, eta, mask, u_int, workspace})) return ISIS_ERR_INVALID_ARG;
+    if (block < 1 || max_sweeps < 0 || !(tol >= 0.0) || !std::isfinite(tol)) {
+        fmt_err(g_err, "patch_solve: need block >= 1, max_sweeps >= 0, finite tol >= 0");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!ptrs_aligned({phi, eta, mask, u_int}) || !aligned(workspace, 256) ||
+        workspace_bytes < isis_patch_workspace_size(n)) {
+        fmt_err(g_err, "patch_solve: aligned arrays and a 256-byte aligned workspace of >= %zu "
+                       "bytes needed", isis_patch_workspace_size(n));
+        return ISIS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const long n3 = (long)n * n * n;
+    double* pre = static_cast<double*>(workspace);
+    double* partial = pre + n3 + 32;  // per-block sums, then their totals
+    double* scal = partial + 2 * kReduceBlocks;
+    const double ih2 = 1.0 / (h * h);
+    return with_model<double>(*p, a, [&](auto m) {
+        using M = decltype(m);
+        const int g = std::min(kReduceBlocks, grid_for(n3));
+        // RMS of the defect over the inside cells, boundary values from phi
+        auto rms = [&](double* out) -> int {
+            HIP_TRY(g_err, hipMemcpyAsync(pre, phi, sizeof(double) * n3, hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL((k_masked_defect<M>), dim3(g), dim3(kBlock), 0, s, m, n, ih2, phi,
+                               eta, nullptr, mask, u_int, pre, nullptr, partial);
+            LAUNCH_CHECK(g_err, "k_masked_defect");
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partial, g, scal);
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, partial + g, g, scal + 1);
+            LAUNCH_CHECK(g_err, "k_reduce");
+            double host[2];
+            HIP_TRY(g_err, hipMemcpyAsync(host, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(g_err, hipStreamSynchronize(s));
+            *out = host[1] > 0.0 ? std::sqrt(host[0] / host[1]) : 0.0;
+            return (int)ISIS_OK;
+        };
+        double r = 0.0;
+        int rc = rms(&r);
+        if (rc) return rc;
+        int sweeps = 0;
+        while (r > tol && sweeps < max_sweeps) {
+            // the boundary values are set from the field before each block
+            HIP_TRY(g_err, hipMemcpyAsync(pre, phi, sizeof(double) * n3, hipMemcpyDeviceToDevice, s));
+            for (int b = 0; b < block && sweeps < max_sweeps; ++b, ++sweeps) {
+                for (int colour = 0; colour < 2; ++colour) {
+                    hipLaunchKernelGGL((k_masked_halfsweep<M>), dim3(grid_for(n3 / 2)),
+                                       dim3(kBlock), 0, s, m, n, ih2, phi, eta, nullptr, mask,
+                                       u_int, pre, colour);
+                    LAUNCH_CHECK(g_err, "k_masked_halfsweep");
+                }
+            }
+            if ((rc = rms(&r))) return rc;
+            if (!std::isfinite(r)) {
+                fmt_err(g_err, "patch_solve: non-finite defect after %d sweeps", sweeps);
+                if (sweeps_out) *sweeps_out = sweeps;
+                if (rms_out) *rms_out = r;
+                return (int)ISIS_ERR_DIVERGED;
+            }
+        }
+        if (sweeps_out) *sweeps_out = sweeps;
+        if (rms_out) *rms_out = r;
+        return r <= tol ? (int)ISIS_OK : (int)ISIS_ERR_NOT_CONVERGED;
     });
 }
 

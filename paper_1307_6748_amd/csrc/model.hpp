@@ -53,6 +53,9 @@ struct Symmetron {
         L = lap - S;
         D = -T(6) * ih2 - fabs(dS);
     }
+    // Refinement boundaries (Sec. 3.3.1): the Newton denominator's term from a
+    // ghost neighbour v = u^Int + r (p - u^Pre), dL/dv * dv/dp = r / h^2.
+    __device__ __forceinline__ T ghost_dD(T, T, T r, T ih2) const { return r * ih2; }
     // 1 if the safeguard replaced dS/dchi by |dS/dchi| at this cell
     __device__ __forceinline__ unsigned guarded(T p, T eta) const
     {
@@ -237,6 +240,15 @@ struct FofR {
             D = (esd - T(6) * ep - se) * hih2 - dS;
         }
     }
+    // Refinement boundaries (Sec. 3.4.1): the Newton denominator's terms from
+    // a ghost neighbour v = u^Int + r (p - u^Pre) whose face coefficient is
+    // b(v): r [b_f + b'(v) (v - p) / 2] / h^2 (double precision only).
+    __device__ __forceinline__ T ghost_dD(T p, T v, T r, T ih2) const
+    {
+        static_assert(!kW, "masked operators run in double precision");
+        const T ev = exp(v);
+        return r * ih2 * (T(0.5) * (exp(p) + ev) + T(0.5) * ev * (v - p));
+    }
     __device__ __forceinline__ void op(T p, const T nb[6], T eta, T ih2, T& L, T& D) const
     {
         T enb[6];
@@ -267,6 +279,7 @@ struct Linear {
         L = lap - S;
         D = -T(6) * ih2 - m2;
     }
+    __device__ __forceinline__ T ghost_dD(T, T, T r, T ih2) const { return r * ih2; }
     __device__ __forceinline__ T cold(T) const { return T(0); }
 };
 

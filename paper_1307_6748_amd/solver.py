@@ -357,3 +357,53 @@ def force(params: ModelParams, a: float, box: float, field=None, potential=None,
     _ok(A.lib().isis_force(C.byref(pc), float(a), n, float(box) / n, _ptr(field),
                            _ptr(potential), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream()))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Refinement boundaries with masks (Sec. 3.3.1, 3.4.1) on an n^3 patch.
+# ---------------------------------------------------------------------------
+
+def masked_defect(params: ModelParams, a: float, h: float, phi, eta, mask, u_int, u_pre,
+                  sigma=None, out=None):
+    """L - sigma at the inside cells (mask > 0) with ghost values for masked
+    neighbours; 0 elsewhere (see isis_op_masked_defect)."""
+    n = _side(phi)
+    for t, nm in ((phi, "phi"), (eta, "eta"), (mask, "mask"), (u_int, "u_int"), (u_pre, "u_pre")):
+        _check_field(t, n, nm)
+    out = torch.empty_like(phi) if out is None else out
+    pc = params.c()
+    _ok(A.lib().isis_op_masked_defect(C.byref(pc), float(a), n, float(h), _ptr(phi), _ptr(eta),
+                                      _ptr(sigma), _ptr(mask), _ptr(u_int), _ptr(u_pre),
+                                      _ptr(out), _stream()))
+    return out
+
+
+def masked_halfsweep(params: ModelParams, a: float, h: float, phi, eta, mask, u_int, u_pre,
+                     sigma=None, colour: int = 0):
+    n = _side(phi)
+    for t, nm in ((phi, "phi"), (eta, "eta"), (mask, "mask"), (u_int, "u_int"), (u_pre, "u_pre")):
+        _check_field(t, n, nm)
+    pc = params.c()
+    _ok(A.lib().isis_op_masked_halfsweep(C.byref(pc), float(a), n, float(h), _ptr(phi),
+                                         _ptr(eta), _ptr(sigma), _ptr(mask), _ptr(u_int),
+                                         _ptr(u_pre), int(colour), _stream()))
+
+
+def patch_solve(params: ModelParams, a: float, h: float, phi, eta, mask, u_int, block: int = 4,
+                max_sweeps: int = 10000, tol: float = 1e-10, check: bool = True):
+    """Relaxation solve of a refinement patch in place (see isis_patch_solve);
+    returns (status, sweeps, rms)."""
+    n = _side(phi)
+    for t, nm in ((phi, "phi"), (eta, "eta"), (mask, "mask"), (u_int, "u_int")):
+        _check_field(t, n, nm)
+    nbytes = A.lib().isis_patch_workspace_size(n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=phi.device)
+    sweeps, rms = C.c_int(), C.c_double()
+    pc = params.c()
+    rc = A.lib().isis_patch_solve(C.byref(pc), float(a), n, float(h), _ptr(phi), _ptr(eta),
+                                  _ptr(mask), _ptr(u_int), int(block), int(max_sweeps),
+                                  float(tol), _ptr(ws), nbytes, C.byref(sweeps), C.byref(rms),
+                                  _stream())
+    if rc in (A.ISIS_ERR_INVALID_ARG, A.ISIS_ERR_HIP) or (check and rc != A.ISIS_OK):
+        _raise(rc, A.lib().isis_mg_last_error(None).decode())
+    return rc, sweeps.value, rms.value
