@@ -131,6 +131,14 @@ typedef struct {
                           weighting for f(R), the mean for the others.  The
                           converged field does not depend on it, the V-cycles'
                           convergence factors do                              */
+    int judge_skip;    /* 0: the FP64 fine defect (the judge of the stop test) is
+                          evaluated after every V-cycle; 1: after a judged cycle,
+                          the cycles that the mean factor per cycle since the
+                          previous judged one predicts to stay above tol (all
+                          but the last two before the predicted end, at most 4
+                          in a row) run without it.  The stop test is unchanged
+                          (the last cycle is always judged); unjudged cycles
+                          have rel_hist = NaN                                   */
 } isis_mg_desc;
 
 typedef struct {
@@ -141,7 +149,8 @@ typedef struct {
     double rel_res;      /* final RMS(L_0(phi)) / r_ref; absolute RMS when r_ref <=
                             1e-14 (6/h^2) RMS(cold start), i.e. when the cold
                             start is an exact root (uniform density)             */
-    double rel_hist[ISIS_MG_MAX_HIST]; /* [0] initial, [k] after cycle k          */
+    double rel_hist[ISIS_MG_MAX_HIST]; /* [0] initial, [k] after cycle k (NaN if
+                                            not judged, see desc.judge_skip)     */
     double ms_total;     /* wall time of the solve call, milliseconds             */
     double cell_updates; /* Newton-GS cell updates performed, all levels          */
     int used_guess;      /* 1 if the caller's field was used as initial guess     */
@@ -159,7 +168,10 @@ typedef struct {
                                      blocked                                      */
     int temporal_block;           /* the temporal block the solve used (0..2)     */
     double rho_hist[ISIS_MG_MAX_HIST]; /* convergence factors: [k] = rel_hist[k] /
-                                     rel_hist[k-1] for 1 <= k <= cycles; [0] = 0  */
+                                     rel_hist[k-1] for 1 <= k <= cycles; [0] = 0;
+                                     with desc.judge_skip, NaN for unjudged cycles
+                                     and the mean factor per cycle since the
+                                     previous judged cycle for judged ones         */
     long long safeguard_hits;     /* ISIS_SYMMETRON: Newton-Gauss-Seidel updates
                                      (every level, both precisions) at which
                                      dS/dchi < 0, so that the safeguarded
@@ -171,6 +183,7 @@ typedef struct {
                                      grid's sweeps included, milliseconds         */
     int restriction;              /* the restriction of the defect the solve used
                                      (0 mean, 1 full weighting)                    */
+    int judged_cycles;            /* V-cycles after which the judge ran          */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;

@@ -32,7 +32,8 @@ class DescC(C.Structure):
                 ("nu_coarse", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int),
                 ("fp32_floor", C.c_double), ("temporal_block", C.c_int), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("guess_accept", C.c_double), ("restriction", C.c_int)]
+                ("guess_accept", C.c_double), ("restriction", C.c_int),
+                ("judge_skip", C.c_int)]
 
 
 class StatsC(C.Structure):
@@ -44,7 +45,7 @@ class StatsC(C.Structure):
                 ("fine_sweep_updates", C.c_double * 2), ("fine_sweep_bytes", C.c_double * 2),
                 ("temporal_block", C.c_int), ("rho_hist", C.c_double * MAX_HIST),
                 ("safeguard_hits", C.c_longlong), ("ms_smooth", C.c_double),
-                ("restriction", C.c_int)]
+                ("restriction", C.c_int), ("judged_cycles", C.c_int)]
 
 
 _lib = None

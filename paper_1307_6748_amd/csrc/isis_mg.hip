@@ -529,6 +529,10 @@ bool valid_desc(const isis_mg_desc* d, char* err)
         fmt_err(err, "guess_accept must be 0 (automatic) or in (0, 1]");
         return false;
     }
+    if (d->judge_skip != 0 && d->judge_skip != 1) {
+        fmt_err(err, "judge_skip must be 0 or 1");
+        return false;
+    }
     if (d->restriction < -1 || d->restriction > 1) {
         fmt_err(err, "restriction must be -1 (per model), 0 (mean) or 1 (full weighting)");
         return false;
@@ -666,6 +670,19 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
 // of the equation's terms (symmetron ~2e-7 relative, f(R) below 1e-8).
 constexpr double kFloorJumpMax = 1e-6;
 
+// Judge schedule (desc.judge_skip): after a judged cycle whose residual rc
+// fell at the mean factor rho per cycle since the previous judged one, the
+// number of cycles until rc rho^m <= tol is m; the next `ahead` cycles then
+// run without the judge, ahead = min(m - 2, 4) >= 0, so the judge resumes two
+// cycles before the predicted end (the factors of these solves rise towards
+// their asymptotic value, so the prediction errs on the early side).
+inline int judge_ahead(bool lazy, int cyc, double rc, double rho, double target)
+{
+    if (!lazy || cyc < 2 || !(rho > 0.0) || !(rho < 0.6) || !(rc > target)) return 0;
+    const double m = std::ceil(std::log(target / rc) / std::log(rho));
+    return (int)std::max(0.0, std::min(m - 2.0, 4.0));
+}
+
 // The solve for one model; M64/M32 are its double and float device models.
 // In mixed precision the FP32 field is (field - shift32) * M32::kVar: f(R) in
 // the paper's variable runs its FP32 cycles in ln(f_R/f_R0) (shift32 =
@@ -758,6 +775,8 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     if (!std::isfinite(r0)) status = ISIS_ERR_DIVERGED;
     else if (r0 <= tol * rnorm) status = ISIS_OK;
 
+    const bool lazy = d.judge_skip != 0;
+    int blind = 0, judged = 0, cprev = 0;  // judge schedule; cprev: last judged cycle
     // Mixed precision, phase 1: FP32 V-cycles on the FP32 copy of the
     // problem, monitored by the FP64 defect of the FP32 iterate.  Skipped when
     // the initial field is already near the FP32 round-off floor, where FP32
@@ -794,6 +813,13 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             if (singular && (r = sub_mean<float>(H, H->L32[0].phi, n3))) return r;
             ++cyc;
             ++cyc32;
+            if (blind > 0 && cyc < d.max_cycles) {  // not judged (desc.judge_skip)
+                --blind;
+                if (st) st->rel_hist[cyc] = std::nan("");
+                continue;
+            }
+            blind = 0;
+            ++judged;
             double rc;
             if ((r = fine_rms<float, M64>(H, m64, H->L32[0].phi, density, nullptr, &rc,
                                           M32::kVarInv, shift32)))
@@ -818,14 +844,19 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             // or once one more cycle is expected to finish (default), or at
             // the caller's hand-over level.  Far above round-off a rising
             // factor is the cycle's own asymptotic rate settling in (f(R)
-            // with three sweeps per side: 0.06 then 0.23 at 3e-5).
-            const double rho = rc / rprev;
+            // with three sweeps per side: 0.06 then 0.23 at 3e-5).  rho is
+            // the mean factor per cycle since the previous judged cycle.
+            const int gap = cyc - cprev;
+            const double rho = gap == 1 ? rc / rprev : std::pow(rc / rprev, 1.0 / gap);
             const bool jump = rho > 0.2 && rho > 3.0 * rho_prev && rc <= kFloorJumpMax * rnorm;
-            if (rc > 0.6 * rprev || jump ||
+            if (rho > 0.6 || jump ||
                 (predict ? rc * rho <= 0.7 * tol * rnorm : rc <= fp32_floor * rnorm))
                 break;
             rho_prev = rho;
             rprev = rc;
+            cprev = cyc;
+            // the FP32 phase hands over one cycle early: aim one cycle short
+            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm / std::max(rho, 1e-300));
         }
         // Promote the FP32 iterate unless it is no better than the field the
         // phase started from (then the FP64 cycles continue from that field).
@@ -841,10 +872,19 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
 
     // FP64 V-cycles (the whole solve in ISIS_FP64; the refinement phase in
     // ISIS_MIXED).
+    double rlast = rcur;  // residual at the last judged cycle (cprev)
+    blind = 0;
     while (status == ISIS_ERR_NOT_CONVERGED && cyc < d.max_cycles) {
         if ((r = vcycle<double, M64>(H, m64, H->L64, 0, &updates))) return r;
         if (singular && (r = sub_mean<double>(H, F.phi, n3))) return r;
         ++cyc;
+        if (blind > 0 && cyc < d.max_cycles) {  // not judged (desc.judge_skip)
+            --blind;
+            if (st) st->rel_hist[cyc] = std::nan("");
+            continue;
+        }
+        blind = 0;
+        ++judged;
         double rc;
         if ((r = fine_rms<double, M64>(H, m64, F.phi, density, nullptr, &rc))) return r;
         if (st) st->rel_hist[cyc] = rc / rnorm;
@@ -852,6 +892,13 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         rcur = rc;
         if (!std::isfinite(rc) || rc > 1e3 * r0) status = ISIS_ERR_DIVERGED;
         else if (rc <= tol * rnorm) status = ISIS_OK;
+        else {
+            const int gap = cyc - cprev;
+            const double rho = std::pow(rc / rlast, 1.0 / std::max(gap, 1));
+            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm);
+        }
+        rlast = rc;
+        cprev = cyc;
     }
     if (F.phi != field) {  // an odd number of fused passes left the result in tmp0
         HIP_TRY(H->err, hipMemcpyAsync(field, F.phi, sizeof(double) * n3,
@@ -884,9 +931,19 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         st->rel_res = rcur / rnorm;
         st->cell_updates = updates;
         st->safeguard_hits = (long long)*hits_host;
-        for (int k = 1; k <= cyc; ++k)
-            st->rho_hist[k] = st->rel_hist[k - 1] > 0.0 ? st->rel_hist[k] / st->rel_hist[k - 1]
-                                                        : 0.0;
+        st->judged_cycles = judged;
+        // per-cycle factors; after cycles without the judge, the mean factor
+        // per cycle since the previous judged one (NaN for the unjudged ones)
+        int prev = 0;
+        for (int k = 1; k <= cyc; ++k) {
+            if (std::isnan(st->rel_hist[k])) {
+                st->rho_hist[k] = std::nan("");
+                continue;
+            }
+            const double a0 = st->rel_hist[prev];
+            st->rho_hist[k] = a0 > 0.0 ? std::pow(st->rel_hist[k] / a0, 1.0 / (k - prev)) : 0.0;
+            prev = k;
+        }
     }
     if (status == ISIS_ERR_NOT_CONVERGED)
         fmt_err(H->err, "not converged after %d cycles (rel. residual %.3e)", cyc, rcur / rnorm);

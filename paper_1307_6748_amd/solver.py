@@ -114,6 +114,7 @@ class Stats:
     safeguard_hits: int = 0  # symmetron: updates with the safeguarded denominator
     ms_smooth: float = 0.0   # profiling on: all smoothing kernels, all levels
     restriction: int = 0     # defect restriction used: 0 mean, 1 full weighting
+    judged_cycles: int = 0   # cycles after which the FP64 judge ran
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
@@ -122,7 +123,7 @@ class Stats:
                      bool(s.used_guess), list(s.fine_sweep_ms), list(s.fine_sweep_launches),
                      list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block,
                      list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth,
-                     s.restriction)
+                     s.restriction, s.judged_cycles)
 
 
 def _ptr(t: torch.Tensor | None):
@@ -151,18 +152,20 @@ class Solver:
     default) lets the library pick the sweeps per HBM pass for each model;
     0, 1, 2 force one choice (see isis_mg_desc).  restriction = -1 (the
     default) restricts the defect by full weighting for f(R) and by the
-    8-child mean otherwise; 0 / 1 force the mean / full weighting."""
+    8-child mean otherwise; 0 / 1 force the mean / full weighting.
+    judge_skip: skip the FP64 judge on cycles predicted to stay above tol
+    (see isis_mg_desc.judge_skip)."""
 
     def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = 2,
                  nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
                  temporal_block: int = -1, fp32_floor: float = 0.0, guess_accept: float = 0.0,
-                 restriction: int = -1):
+                 restriction: int = -1, judge_skip: bool = False):
         self.N, self.box = int(N), float(box)
         self._h = None
         lib = A.lib()
         d = A.DescC(self.N, self.box, nu_pre, nu_post, nu_coarse, max_cycles,
                     PRECISIONS[precision], float(fp32_floor), temporal_block, _stream(), None, 0,
-                    float(guess_accept), int(restriction))
+                    float(guess_accept), int(restriction), int(bool(judge_skip)))
         nbytes = lib.isis_mg_workspace_size(C.byref(d))
         if nbytes == 0:
             raise ValueError("invalid solver description (N, box, nu_*, max_cycles, precision, "

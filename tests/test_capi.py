@@ -55,7 +55,8 @@ def test_workspace_size_validation():
                 dict(fp32_floor=-1e-6), dict(fp32_floor=2.0), dict(fp32_floor=1e-13),
                 dict(fp32_floor=float("nan")), dict(guess_accept=-0.1),
                 dict(guess_accept=1.5), dict(guess_accept=float("nan")),
-                dict(restriction=2), dict(restriction=-2)):
+                dict(restriction=2), dict(restriction=-2), dict(judge_skip=2),
+                dict(judge_skip=-1)):
         assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad
 
 

@@ -309,3 +309,28 @@ def test_mixed_from_a_near_converged_guess(orc, name):
     assert stm.status == 0 and stm.rel_res <= 1e-11
     assert stm.cycles_fp32 == 0 and stm.cycles <= st64.cycles
     assert float((phi - ref).abs().max()) <= 1e-9 * float(ref.abs().max()) + 1e-12
+
+
+@pytest.mark.parametrize("name,precision", [("fofr", "mixed"), ("fofr", "fp64"),
+                                            ("symmetron_a1", "mixed")])
+def test_judge_skip_keeps_the_stop_test(name, precision):
+    """Skipping the FP64 judge on cycles predicted to stay above tol: the
+    final residual is judged and <= tol, the solve takes at most one cycle
+    more, fewer judges run, unjudged cycles have NaN history, and the field
+    agrees with the every-cycle solve to what two solves stopped at the same
+    tolerance can differ by."""
+    _, sp, a = models(name)
+    w = _wl("fr_256", 128)
+    eta = dev(w["eta"])
+    phi0, st0 = _solver(128, w["box"], precision=precision).solve(eta, sp, a, 1e-8)
+    phi1, st1 = _solver(128, w["box"], precision=precision, judge_skip=True).solve(eta, sp, a,
+                                                                                   1e-8)
+    assert st0.status == 0 and st1.status == 0
+    assert st1.rel_res <= 1e-8 and np.isfinite(st1.rel_hist[-1])
+    assert st0.judged_cycles == st0.cycles
+    assert st1.cycles <= st0.cycles + 1
+    assert st1.judged_cycles == int(np.sum(np.isfinite(st1.rel_hist[1:])))
+    if name.startswith("fofr"):  # slow enough to skip some judges (the symmetron is not)
+        assert st1.judged_cycles < st1.cycles
+    diff = float((phi1 - phi0).norm() / phi0.norm())
+    assert diff <= 1e-5, diff
