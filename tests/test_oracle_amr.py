@@ -205,3 +205,24 @@ def test_refined_patch_approaches_the_fine_solution(orc):
     e_patch = np.abs(phi[core, core, core] - fine_core).max()
     e_interp = np.abs(u_int[core, core, core] - fine_core).max()
     assert e_patch < 0.1 * e_interp, (e_patch, e_interp)  # measured 0.04
+
+
+def test_chameleon_masked_steps_are_bounded(orc):
+    """Chameleon with n = -1/2 on a lognormal density with sigma_delta = 2,
+    patch cells started at zero, far from the local roots (which span about
+    -8 .. 11): the masked half-sweep moves no cell by more than 2 (reading
+    R15; unbounded Newton steps overflow here), and the patch solve reaches
+    its tolerance with a finite field."""
+    m = orc.Model(model=orc.CHAMELEON, cham_alpha=0.7, cham_mu=0.4, cham_n=-0.5)
+    n, box = 16, 32.0
+    eta = synth.lognormal(n, box, 2.0, 31)
+    mask = _patch_mask(n, 2, 14)
+    root = orc.cold_start(m, eta)
+    u = np.zeros_like(eta)
+    for c in (0, 1):
+        v = orc.masked_halfsweep(m, box / n, u, eta, mask, root, root, colour=c)
+        assert np.max(np.abs(v - u)) == 2.0
+        u = v
+    phi, sweeps, rms = orc.patch_solve(m, box / n, np.zeros_like(eta), eta, mask, root, block=4,
+                                       tol=1e-10)
+    assert rms <= 1e-10 and np.all(np.isfinite(phi))

@@ -18,7 +18,7 @@ MUTATIONS = {
                               "dflux += bc * (nb[f] - p) - bf;"),
     "face_average_half_dropped": ("double bf = 0.5 * (bc + exp(nb[f]));",
                                   "double bf = (bc + exp(nb[f]));"),
-    "flux_missing_inv_h2": ("return flux * ih2 - S;", "return flux - S;"),
+    "flux_missing_inv_h2": ("return flux * ih2 - S;", "return flux - S;", 0),
     "symmetron_cubic_sign": ("*S = K * (A * eta * chi - chi + chi * chi * chi);",
                              "*S = K * (A * eta * chi - chi - chi * chi * chi);"),
     "symmetron_K_missing_a2": ("double K = m->a * m->a / (2.0 * m->lambda0 * m->lambda0);",
@@ -32,7 +32,7 @@ MUTATIONS = {
     "prolongation_no_phihat": ("(coarse[q] - coarse_hat[q])", "(coarse[q])"),
     "fas_sigma_sign": ("c->sigma[q] -= c->work[q];", "c->sigma[q] += c->work[q];"),
     "laplacian_wrong_diagonal": ("double lap = (sum - 6.0 * p) * ih2;",
-                                 "double lap = (sum - 5.0 * p) * ih2;"),
+                                 "double lap = (sum - 5.0 * p) * ih2;", 0),
     "neighbour_index": ("nb[3] = phi[cidx(n, i, wrap(j + 1, n), k)];",
                         "nb[3] = phi[cidx(n, i, wrap(j - 1, n), k)];"),
     "force_difference_sign": ("return (f[cidx(n, ip, jp, kp)] - f[cidx(n, im, jm, km)]) / (2.0 * h);",
@@ -54,10 +54,10 @@ MUTATIONS = {
         "phi[c] = log(m->cham_mu / (m->cham_alpha * eta[c])) / (1.0 + m->cham_n);",
         "phi[c] = log(m->cham_mu / (m->cham_alpha * eta[c]));"),
     "chameleon_canonical_laplacian_of_psi": (
-        "if (m->model == ORC_FR_HS || m->model == ORC_CHAMELEON) {",
-        "if (m->model == ORC_FR_HS) {"),
+        "if (m->model == ORC_FR_HS || m->model == ORC_CHAMELEON) {\n        /* Sec. 3.4",
+        "if (m->model == ORC_FR_HS) {\n        /* Sec. 3.4"),
     "chameleon_step_unbounded": ("if (m->model == ORC_CHAMELEON) /* reading R15 */",
-                                 "if (0) /* reading R15 */"),
+                                 "if (0) /* reading R15 */", 0),
     "rms_missing_sqrt": ("return sqrt(sumsq(nn, r) / (double)(nn * nn * nn));",
                          "return sumsq(nn, r) / (double)(nn * nn * nn);"),
     "rms_cell_count": ("return sqrt(sumsq(nn, r) / (double)(nn * nn * nn));",
@@ -78,6 +78,12 @@ MUTATIONS = {
         "            *D = -6.0 * ih2 - fabs(dS); /* reading R10 */"),
     "amr_int_ignored": ("const double uint_f = mask[q] > -1.0 ? u_pre[q] : u_int[q]; /* eq. bpsi */",
                         "const double uint_f = u_pre[q]; /* eq. bpsi */"),
+    # the same mistakes in the masked operator and the masked half-sweep
+    "amr_flux_missing_inv_h2": ("return flux * ih2 - S;", "return flux - S;", 1),
+    "amr_laplacian_wrong_diagonal": ("double lap = (sum - 6.0 * p) * ih2;",
+                                     "double lap = (sum - 5.0 * p) * ih2;", 1),
+    "amr_chameleon_step_unbounded": ("if (m->model == ORC_CHAMELEON) /* reading R15 */",
+                                     "if (0) /* reading R15 */", 1),
     "amr_ghost_sign": ("v[f] = uint_f + r[f] * (p - u_pre[c]); /* eq. ueq */",
                        "v[f] = uint_f - r[f] * (p - u_pre[c]); /* eq. ueq */"),
     "paper_u_a4_factor": ("- om * a * a * a * a * H2 * g * c * e +",
@@ -107,11 +113,17 @@ def _pin_order(name):
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_planted_mistake_fails_a_pin(tmp_path, name):
     from oracle import oracle as O
-    old, new = MUTATIONS[name]
+    old, new, *which = MUTATIONS[name]
     src = open(SRC).read()
-    assert src.count(old) == 1, name
+    if which:  # a line that occurs in the uniform and the masked operator: one copy
+        assert src.count(old) == 2, name
+        at = src.index(old) if which[0] == 0 else src.index(old, src.index(old) + 1)
+        src = src[:at] + new + src[at + len(old):]
+    else:
+        assert src.count(old) == 1, name
+        src = src.replace(old, new)
     mut = tmp_path / "mutant.c"
-    mut.write_text(src.replace(old, new))
+    mut.write_text(src)
     so = str(tmp_path / "libmutant.so")
     O.build(force=True, src=str(mut), out=so)
     env = dict(os.environ, ORACLE_LIB=so, OMP_NUM_THREADS="4")
