@@ -120,7 +120,9 @@ def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: boo
     s-byte values: each smoothing pass reads phi, eta (and Sigma below the
     finest level) once and writes phi; the descent reads phi, eta (Sigma) and
     writes phi_c, phihat_c and the restricted defect (3/8 s per fine cell), full
-    weighting adding the fine defect's write and read; the coarse source reads
+    weighting in two passes (double precision, or sides the single-pass kernel
+    does not tile: below 64 or not a power of two) adding the fine defect's
+    write and read; the coarse source reads
     phi_c, eta_c, the restricted defect and writes Sigma_c; the correction
     reads the two coarse fields and reads and writes phi.  The coarsest level
     is smoothed in one workgroup and moves no more than its 64 cells."""
@@ -129,7 +131,7 @@ def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: boo
         return 4 * s * c
     b = passes * (3 + (1 if sig else 0)) * s * c          # smoothing
     b += (2 + (1 if sig else 0)) * s * c + 3 * s * c / 8  # defect + restriction
-    if fw:
+    if fw and not (s == 4 and nl >= 64 and nl & (nl - 1) == 0):
         b += 2 * s * c                                    # fine defect written, read
     b += 4 * s * c / 8                                    # coarse source
     b += 2 * s * c + 2 * s * c / 8                        # prolongation + correction

@@ -178,9 +178,10 @@ typedef struct {
                                      denominator -6/h^2 - |dS/dchi| replaced the
                                      Jacobian -6/h^2 - dS/dchi (Sec. 3.3); each
                                      cell update counts once; 0 for other models */
-    double ms_smooth;             /* profiling on: summed kernel time of every
-                                     smoothing step of every level, the coarsest
-                                     grid's sweeps included, milliseconds         */
+    double ms_smooth;             /* profiling on: summed kernel time of the
+                                     smoothing steps on the finest level and on
+                                     every level of side >= 256 (the smaller
+                                     levels are not timed), milliseconds          */
     int restriction;              /* the restriction of the defect the solve used
                                      (0 mean, 1 full weighting)                    */
     int judged_cycles;            /* V-cycles after which the judge ran          */

@@ -283,6 +283,42 @@ int launch_restrict_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* e
     return ISIS_OK;
 }
 
+// FAS descent with the full-weighting restriction in one pass (single
+// precision, tiled levels): XC = 16 coarse planes per workgroup at 512^3 and
+// above, 8 below (enough workgroups to fill the device at 256^3).
+template <class T, class M, bool SIG, int XC>
+int launch_defect_fw_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
+                           const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, hipStream_t s,
+                           char* err)
+{
+    using G = DefectFwTile<XC>;
+    auto kern = k_defect_restrict_fw_tiled<T, M, SIG, XC>;
+    constexpr int lds = defect_fw_lds_bytes<T, M, XC>();
+    static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
+    HIP_TRY(err, ensure_dynamic_lds((const void*)kern, lds, lds_done));
+    const int blocks = (nf / G::TZ) * (nf / G::TY) * ((nf / 2) / XC);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), lds, s, m, nf, ih2f, phi_f, eta_f,
+                       sigma_f, phi_c, phihat_c, rr_c);
+    LAUNCH_CHECK(err, "k_defect_restrict_fw_tiled");
+    return ISIS_OK;
+}
+
+template <class T, class M>
+int launch_defect_fw(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
+                     const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, hipStream_t s, char* err)
+{
+    if (nf >= 512)
+        return sigma_f ? launch_defect_fw_tiled<T, M, true, 16>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                                phi_c, phihat_c, rr_c, s, err)
+                       : launch_defect_fw_tiled<T, M, false, 16>(m, nf, ih2f, phi_f, eta_f,
+                                                                 sigma_f, phi_c, phihat_c, rr_c,
+                                                                 s, err);
+    return sigma_f ? launch_defect_fw_tiled<T, M, true, 8>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                           phi_c, phihat_c, rr_c, s, err)
+                   : launch_defect_fw_tiled<T, M, false, 8>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                            phi_c, phihat_c, rr_c, s, err);
+}
+
 // coarse = full-weighting restriction of an nf^3 fine field (nf even >= 4).
 template <class T>
 int launch_restrict_fw(int nf, const T* fine, T* coarse, hipStream_t s, char* err)
@@ -299,9 +335,10 @@ int launch_restrict_fw(int nf, const T* fine, T* coarse, hipStream_t s, char* er
     return ISIS_OK;
 }
 
-// The FAS descent.  dfine: NULL for the 8-child mean of the defect; else an
-// nf^3 scratch field that receives the fine defect, which is then restricted
-// by full weighting.
+// The FAS descent.  dfine: NULL for the 8-child mean of the defect; else full
+// weighting, in one pass on single-precision tiled levels, elsewhere through
+// dfine, an nf^3 scratch field that receives the fine defect, which is then
+// restricted.
 template <class T, class M>
 int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f,
                    const T* sigma_f, const T* eta_c, T* phi_c, T* phihat_c, T* sigma_c, T* rr_c,
@@ -313,7 +350,20 @@ int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f
     double hc = 2.0 * hf;
     T ih2c = (T)(1.0 / (hc * hc));
     using RG = RestrictTileF;
-    if ((nf & (nf - 1)) == 0 && nf % RG::TZ == 0 && nf % RG::TY == 0 && nc % RG::XC == 0) {
+    const bool tiled =
+        (nf & (nf - 1)) == 0 && nf % RG::TZ == 0 && nf % RG::TY == 0 && nc % RG::XC == 0;
+    if constexpr (sizeof(T) == 4) {
+        if (dfine && tiled) {  // single pass; dfine is not needed
+            int r = launch_defect_fw<T, M>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c,
+                                           rr_c, s, err);
+            if (r) return r;
+            hipLaunchKernelGGL((k_fas_sigma<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m, nc,
+                               ih2c, phi_c, eta_c, rr_c, sigma_c);
+            LAUNCH_CHECK(err, "k_fas_sigma");
+            return ISIS_OK;
+        }
+    }
+    if (tiled) {
         const int blocks = (nf / RG::TZ) * (nf / RG::TY) * (nc / RG::XC);
         constexpr int lds = restrict_tiled_lds_bytes<T, M>();
         int r;
@@ -596,14 +646,20 @@ int sub_mean(isis_mg* H, T* f, long n3)
     return ISIS_OK;
 }
 
-// Smoothing step of level l; with profiling on, the launches are bracketed by
-// HIP events on the solver stream (all levels; the finest level's are also
-// reported per precision).
+// Levels whose smoothing steps are timed with profiling on: an event pair
+// holds the stream for a few microseconds, about the length of a whole
+// smoothing step on the small levels, so those are left untimed.
+constexpr int kTimedMinN = 256;
+
+// Smoothing step of level l; with profiling on, the launches on levels of side
+// >= kTimedMinN are bracketed by HIP events on the solver stream (the finest
+// level's are also reported per precision).
 template <class T, class M>
 int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
 {
     const int tb = H->tb;
-    const bool timed = H->profile && count > 0 && H->ntimed < isis_mg::kMaxTimed;
+    const bool timed = H->profile && count > 0 && (f.n >= kTimedMinN || l == 0) &&
+                       H->ntimed < isis_mg::kMaxTimed;
     const int q = H->ntimed;
     if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
     int r = launch_sweeps<T, M>(m, f.n, f.h, &f.phi, &f.tmp, f.eta, f.sigma, count, tb, H->s,
@@ -634,21 +690,7 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
     int r;
     if (l == H->nlev - 1) {
         *updates += (double)d.nu_coarse * n3;
-        const bool timed = H->profile && H->ntimed < isis_mg::kMaxTimed;
-        const int q = H->ntimed;
-        if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
-        if ((r = launch_coarse<T, M>(m, f.h, f.phi, f.eta, f.sigma, d.nu_coarse, H->s, H->err)))
-            return r;
-        if (timed) {
-            HIP_TRY(H->err, hipEventRecord(H->ev1[q], H->s));
-            H->tlaunch[q] = 1;
-            H->tupd[q] = (double)d.nu_coarse * n3;
-            H->tbytes[q] = 0.0;
-            H->tprec[q] = sizeof(T) == 4 ? 1 : 0;
-            H->tlevel[q] = l;
-            H->ntimed = q + 1;
-        }
-        return ISIS_OK;
+        return launch_coarse<T, M>(m, f.h, f.phi, f.eta, f.sigma, d.nu_coarse, H->s, H->err);
     }
     LevP<T>& c = L[l + 1];
     if ((r = timed_sweeps<T, M>(H, m, f, l, d.nu_pre))) return r;

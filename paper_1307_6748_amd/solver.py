@@ -112,7 +112,7 @@ class Stats:
     temporal_block: int = 0  # the temporal block the solve used
     rho_hist: list = field(default_factory=list)  # per-cycle factors, [0] = 0
     safeguard_hits: int = 0  # symmetron: updates with the safeguarded denominator
-    ms_smooth: float = 0.0   # profiling on: all smoothing kernels, all levels
+    ms_smooth: float = 0.0   # profiling on: smoothing on the finest level and sides >= 256
     restriction: int = 0     # defect restriction used: 0 mean, 1 full weighting
     judged_cycles: int = 0   # cycles after which the FP64 judge ran
 

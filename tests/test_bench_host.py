@@ -110,3 +110,10 @@ def test_solve_bytes_counts_every_kernel_once():
     st.restriction = 1
     fw = want + 2 * 8 * (n3 + 512)
     assert abs(bench.solve_bytes(16, st, 0, (2, 2), False) - fw) <= 1e-9 * fw
+    # in single precision only below 64^3: a 128^3 FP32 cycle's levels 128 and
+    # 64 restrict by full weighting in one pass, levels 32, 16 and 8 in two
+    st32 = types.SimpleNamespace(cycles=1, cycles_fp32=1, restriction=0, judged_cycles=1)
+    mean = bench.solve_bytes(128, st32, 0, (2, 2), True)
+    st32.restriction = 1
+    got = bench.solve_bytes(128, st32, 0, (2, 2), True)
+    assert abs(got - mean - 2 * 4 * (32 ** 3 + 16 ** 3 + 8 ** 3)) <= 1e-9 * got

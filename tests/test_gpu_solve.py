@@ -240,6 +240,32 @@ def test_mixed_fp32_cycles_match(orc, name, n):
     assert abs(st.rel_res - r) <= 1e-9 * r, (st.rel_res, r)
 
 
+@pytest.mark.parametrize("name,n", [(nm, n) for nm in ("symmetron_a1", "fofr", "linear",
+                                                         "chameleon") for n in (64, 256)]
+                         + [("symmetron_a1", 512)])
+def test_mixed_fp32_cycles_other_restriction(orc, name, n):
+    """As above with the restriction of the defect switched from each model's
+    default: full weighting for the symmetron, the linear model and the
+    chameleon (on the tiled FP32 levels, 64^3 and up, the single-pass defect
+    + full-weighting kernel; its evaluation of the defect on the tile's
+    one-cell ring and the x filter across steps must match the oracle's full
+    weighting; 16 coarse planes per workgroup at 512^3, 8 below), the
+    8-child mean for f(R)."""
+    from paper_1307_6748_amd import synth
+    om, sp, a = models(name)
+    box = 4.0 * n
+    eta = synth.lognormal(n, box, 2.0, 300 + n)
+    fw = 0 if name == "fofr" else 1
+    k = 2
+    ro = orc.vcycles(om, eta, box, orc.cold_start(om, eta), k, cfg=orc.Cfg(restrict_fw=bool(fw)))
+    s = _solver(n, box, precision="mixed", max_cycles=k, restriction=fw)
+    phi, st = s.solve(dev(eta), sp, a, 1e-300, check=False)
+    assert st.status == -2 and st.cycles_fp32 == k and st.restriction == fw
+    got = cubic(phi, n)
+    err = np.max(np.abs(got - ro.phi)) / (np.abs(ro.phi).max() + 1.0)
+    assert err <= 1e-6, err
+
+
 def test_safeguard_hits_match_oracle(orc):
     """The count of symmetron updates made with the safeguarded denominator
     (reading 14) over a whole solve from a poor guess equals the oracle's
