@@ -98,16 +98,22 @@ def roofline(kern: dict, n: int):
     per launch / mean event-timed launch duration.  The dominant kernel (most
     time in the step) is the headline."""
     kernels = []
-    for (model, prec), v in kern.items():
+    for key, v in kern.items():
+        model, prec = key[:2]
+        prol = len(key) > 2
         t, mt = TYPES[prec], MODEL_TYPES[model]
         avg_ms = v["ms"] / v["launches"]
         bpl = v["bytes"] / v["launches"]
         ach = bpl / (avg_ms * 1e-3) / 1e9
         tb = v["tb"]
+        what = ("first post-smoothing pass, prolongation fused in" if prol
+                else "no FAS source")
         kernels.append(dict(
-            kernel=f"k_sweep_fused<{t}, {mt}<{t}>, {tb}, ...> ({n}^3, no FAS source)",
+            kernel=f"k_sweep_fused<{t}, {mt}<{t}>, {tb}, ...{', PROL' if prol else ''}> "
+                   f"({n}^3, {what})",
             model=model, precision=prec, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
-            unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(model, prec, n, tb),
+            unit="GB/s", frac=ach / HBM_PEAK_GBS,
+            traffic=None if prol else measured_traffic(model, prec, n, tb),
             launches=v["launches"], total_ms=v["ms"], avg_launch_ms=avg_ms,
             bytes_per_launch=bpl))
     kernels.sort(key=lambda k: -k["total_ms"])
@@ -115,17 +121,19 @@ def roofline(kern: dict, n: int):
     return head, kernels
 
 
-def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: bool) -> float:
+def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: bool,
+                fused: bool = False) -> float:
     """Compulsory HBM bytes of one V-cycle's visit to a level of nl^3 cells with
     s-byte values: each smoothing pass reads phi, eta (and Sigma below the
     finest level) once and writes phi; the descent reads phi, eta (Sigma) and
     writes phi_c, phihat_c and the restricted defect (3/8 s per fine cell), full
     weighting in two passes (double precision, or sides the single-pass kernel
     does not tile: below 64 or not a power of two) adding the fine defect's
-    write and read; the coarse source reads
-    phi_c, eta_c, the restricted defect and writes Sigma_c; the correction
-    reads the two coarse fields and reads and writes phi.  The coarsest level
-    is smoothed in one workgroup and moves no more than its 64 cells."""
+    write and read; the coarse source reads phi_c, eta_c, the restricted
+    defect and writes Sigma_c; the correction reads the two coarse fields and,
+    unless `fused` (fused sweep levels, where the first post-smoothing pass
+    applies it to the values it loads), reads and writes phi.  The coarsest
+    level is smoothed in one workgroup and moves no more than its 64 cells."""
     c = float(nl) ** 3
     if coarsest:
         return 4 * s * c
@@ -134,7 +142,9 @@ def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: boo
     if fw and not (s == 4 and nl >= 64 and nl & (nl - 1) == 0):
         b += 2 * s * c                                    # fine defect written, read
     b += 4 * s * c / 8                                    # coarse source
-    b += 2 * s * c + 2 * s * c / 8                        # prolongation + correction
+    b += 2 * s * c / 8                                    # correction: the coarse fields
+    if not fused:
+        b += 2 * s * c                                    # its own pass over phi
     return b
 
 
@@ -160,7 +170,10 @@ def solve_bytes(n: int, st, tb: int, nu: tuple, mixed: bool) -> float:
             fused = tb >= 1 and nl >= 256
             blk = max(1, tb) if fused else 1
             passes = -(-nu[0] // blk) + -(-nu[1] // blk)
-            per += level_bytes(nl, s, passes, l > 0, bool(st.restriction), l == nlev - 1)
+            # the correction rides in the first post-smoothing pass when that
+            # pass is a single sweep
+            per += level_bytes(nl, s, passes, l > 0, bool(st.restriction), l == nlev - 1,
+                               fused and nu[1] > 0 and (blk == 1 or nu[1] == 1))
         b += count * per
     # the FP64 judge after the judged cycles (every cycle unless judge_skip;
     # the few FP64 cycles at the end of a mixed solve are all judged): reads
@@ -305,8 +318,13 @@ def main() -> int:
             kern[(name, prec)] = dict(
                 ms=ms, launches=nl, updates=sum(st.fine_sweep_updates[k] for st in sts),
                 bytes=sum(st.fine_sweep_bytes[k] for st in sts), tb=sts[-1].temporal_block)
-    sweep_ms = sum(v["ms"] for v in kern.values())
-    sweep_upd = sum(v["updates"] for v in kern.values())
+            npl = sum(st.fine_prol_launches[k] for st in sts)
+            if npl:
+                kern[(name, prec, "prol")] = dict(
+                    ms=sum(st.fine_prol_ms[k] for st in sts), launches=npl,
+                    bytes=sum(st.fine_prol_bytes[k] for st in sts), tb=sts[-1].temporal_block)
+    sweep_ms = sum(v["ms"] for k, v in kern.items() if len(k) == 2)
+    sweep_upd = sum(v["updates"] for k, v in kern.items() if len(k) == 2)
     per_model = {}
     for name, sts in rec.items():
         st = sts[-1]

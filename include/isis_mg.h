@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define ISIS_MG_ABI_VERSION 2
+#define ISIS_MG_ABI_VERSION 3
 #define ISIS_MG_MAX_HIST 128
 
 typedef enum {
@@ -185,6 +185,15 @@ typedef struct {
     int restriction;              /* the restriction of the defect the solve used
                                      (0 mean, 1 full weighting)                    */
     int judged_cycles;            /* V-cycles after which the judge ran          */
+    /* Finest-level first post-smoothing pass with the prolongation
+     * phi += P(phi_c - phihat_c) fused in (fused sweep kernels with a
+     * single-sweep first pass, i.e. temporal block 1; profiling on): [0] FP64,
+     * [1] FP32.  These launches are not in fine_sweep_*. */
+    double fine_prol_ms[2];       /* summed kernel time                           */
+    int fine_prol_launches[2];    /* number of kernel launches                    */
+    double fine_prol_bytes[2];    /* compulsory HBM bytes: a pass's (as in
+                                     fine_sweep_bytes) plus the two coarse fields,
+                                     2 x (n/2)^3 values                           */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;
@@ -276,6 +285,20 @@ const char* isis_mg_last_error(const isis_mg_t* h);
  * db/du), symmetron safeguarded as -6/h^2 - |dS/dphi|.  sigma may be NULL. */
 int isis_op_halfsweep(const isis_model_params* p, double a, int n, double h, double* phi,
                       const double* eta, const double* sigma, int colour, void* stream);
+
+/* The coarse-grid correction phi += P(coarse - coarse_hat) (cell-centred
+ * trilinear prolongation, as isis_op_prolong_correct; coarse and coarse_hat of
+ * side n/2) followed by `count` sweeps as isis_op_sweeps, the way the solver
+ * makes its post-smoothing step: where the sweeps run on the fused kernels
+ * (temporal_block >= 1, n a power of two >= 64) and the first pass is a
+ * single sweep (temporal_block 1, or count 1) the correction is applied
+ * inside that pass to the values it loads, never written on its own; else by
+ * its own kernel first.  n even >= 4; tmp: device n^3 doubles of
+ * scratch; sigma may be NULL; the result is in phi. */
+int isis_op_prolong_sweeps(const isis_model_params* p, double a, int n, double h, double* phi,
+                           double* tmp, const double* eta, const double* sigma,
+                           const double* coarse, const double* coarse_hat, int count,
+                           int temporal_block, void* stream);
 
 /* `count` full red-black sweeps with the solver's production kernels
  * (temporal_block as in isis_mg_desc).  tmp: device n^3 doubles of scratch.

@@ -45,7 +45,9 @@ class StatsC(C.Structure):
                 ("fine_sweep_updates", C.c_double * 2), ("fine_sweep_bytes", C.c_double * 2),
                 ("temporal_block", C.c_int), ("rho_hist", C.c_double * MAX_HIST),
                 ("safeguard_hits", C.c_longlong), ("ms_smooth", C.c_double),
-                ("restriction", C.c_int), ("judged_cycles", C.c_int)]
+                ("restriction", C.c_int), ("judged_cycles", C.c_int),
+                ("fine_prol_ms", C.c_double * 2), ("fine_prol_launches", C.c_int * 2),
+                ("fine_prol_bytes", C.c_double * 2)]
 
 
 _lib = None
@@ -67,6 +69,8 @@ SIGNATURES = [
     ("isis_op_halfsweep", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _I, _P]),
     ("isis_force", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P, _P]),
     ("isis_op_sweeps", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _I, _I, _P]),
+    ("isis_op_prolong_sweeps", _I,
+     [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P, _P, _I, _I, _P]),
     ("isis_op_defect", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P]),
     ("isis_op_restrict", _I, [_I, _P, _P, _P]),
     ("isis_op_fas_descend", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _P, _P,

@@ -49,6 +49,10 @@ struct FusedGeom {
     static constexpr int PAIRS = EY * NP;       // pair loads per plane
     static constexpr int LPT = (PAIRS + NT - 1) / NT;  // pair loads per thread
     // cells of one colour updated by stage k (1-based) and per thread
+    // coarse planes for the prolongation fused into a pass (see PROL): the
+    // parents and their neighbours of the loaded fine rows and columns
+    static constexpr int CJ = EY / 2 + 2, CK = EZ / 2 + 2, CP = CJ * CK;
+    static constexpr int CLPT = (CP + NT - 1) / NT;
     static constexpr int items(int k) { return (EY - 2 * k) * ((EZ - 2 * k) / 2); }
     static constexpr int ipt(int k) { return (items(k) + NT - 1) / NT; }
     static constexpr int MAXI = (items(1) + NT - 1) / NT;
@@ -65,12 +69,12 @@ __device__ __forceinline__ void static_for(F&& f)
 }
 
 // Shared-memory footprint of one workgroup, in bytes.
-template <class T, class M, int TB, int TY, int TZ>
+template <class T, class M, int TB, int TY, int TZ, bool PROL = false>
 constexpr int fused_lds_bytes()
 {
     using G = FusedGeom<T, TB, TY, TZ, 256>;
     int planes = G::NR * (StageOp<T, M>::kStaged ? 2 : 1);
-    return planes * G::PLANE * (int)sizeof(T);
+    return (planes * G::PLANE + (PROL ? G::CP : 0)) * (int)sizeof(T);
 }
 
 // Element at byte offset `off` from `base` (32-bit offsets from a uniform
@@ -86,11 +90,21 @@ __device__ __forceinline__ T& at_bytes(T* base, unsigned off)
     return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
 }
 
-template <class T, class M, int TB, int TY, int TZ, int NT, bool SIG>
+// PROL: the pass first adds the coarse-grid correction P(cphi - cphat) to
+// every value of `in` it loads (cell-centred trilinear prolongation, Sec. 3.2;
+// cphi, cphat of side n/2), so `in` holds the field before the correction and
+// the corrected field is never written.  A fine plane x reads its parent
+// plane x/2 and the neighbour on its side; the two current coarse planes of
+// the tile's window live in registers (each thread the same elements), coarse
+// plane s/2 + 1 replacing s/2 - 1 at each even step s, fetched two steps
+// ahead.
+template <class T, class M, int TB, int TY, int TZ, int NT, bool SIG, bool PROL = false>
 __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
                                                     const T* __restrict__ in, T* __restrict__ out,
                                                     const T* __restrict__ eta,
-                                                    const T* __restrict__ sigma)
+                                                    const T* __restrict__ sigma,
+                                                    const T* __restrict__ cphi = nullptr,
+                                                    const T* __restrict__ cphat = nullptr)
 {
     using G = FusedGeom<T, TB, TY, TZ, NT>;
     using V = typename Vec2<T>::type;
@@ -202,6 +216,83 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
         wl[j] = lds(G::H + rr, G::H + 2 * cp);  // even column (H is even)
     }
 
+    // PROL: each thread owns elements e = tid + q*NT of the coarse window (the
+    // tile's parents plus a one-cell halo: rows from coarse row (y0 - H)/2 - 1,
+    // columns from (z0 - H)/2 - 1) and keeps them, for the two coarse planes
+    // the current fine plane reads, in registers (older, newer), with the next
+    // plane in flight (cA - cB).  Per fine plane x it writes the window
+    // interpolated along x (3/4 parent x/2, 1/4 its neighbour on x's side) to
+    // LDS, from which each fine pair interpolates along y and z.
+    const int nc = n >> 1, cmsk = nc - 1;
+    const size_t nc2 = (size_t)nc * nc;
+    unsigned cgoff[PROL ? G::CLPT : 1];
+    T cA[PROL ? G::CLPT : 1], cB[PROL ? G::CLPT : 1];
+    T cold_[PROL ? G::CLPT : 1] = {}, cnew[PROL ? G::CLPT : 1] = {};
+    T* xbuf = ring + G::NR * G::PLANE * (STAGED ? 2 : 1);  // the x-interpolated window (PROL)
+    if constexpr (PROL) {
+        const int jb = ((y0 - G::H) >> 1) - 1, kb = ((z0 - G::H) >> 1) - 1;
+#pragma unroll
+        for (int q = 0; q < G::CLPT; ++q) {
+            const int e = min(tid + q * NT, G::CP - 1);
+            const int cr = e / G::CK, cc = e - cr * G::CK;
+            cgoff[q] = (unsigned)((((jb + cr) & cmsk) * nc + ((kb + cc) & cmsk)) * SZ);
+        }
+    }
+    auto load_coarse = [&](int cpl) __attribute__((always_inline)) {  // into cA, cB
+        if constexpr (PROL) {
+            const T* a0 = cphi + (size_t)(cpl & cmsk) * nc2;
+            const T* b0 = cphat + (size_t)(cpl & cmsk) * nc2;
+#pragma unroll
+            for (int q = 0; q < G::CLPT; ++q) {
+                cA[q] = at_bytes(a0, cgoff[q]);
+                cB[q] = at_bytes(b0, cgoff[q]);
+            }
+        }
+    };
+    auto advance_coarse = [&]() __attribute__((always_inline)) {  // newer plane arrives
+        if constexpr (PROL) {
+#pragma unroll
+            for (int q = 0; q < G::CLPT; ++q) {
+                cold_[q] = cnew[q];
+                cnew[q] = cA[q] - cB[q];
+            }
+        }
+    };
+    // x-interpolated window for fine plane x: x odd reads parents (older,
+    // newer) = (x/2, x/2 + 1), x even (newer, older) = (x/2, x/2 - 1)
+    auto write_xbuf = [&](auto oddc) __attribute__((always_inline)) {
+        if constexpr (PROL) {
+            constexpr bool ODD = decltype(oddc)::value;
+#pragma unroll
+            for (int q = 0; q < G::CLPT; ++q)
+                if ((q + 1) * NT <= G::CP || tid + q * NT < G::CP)
+                    xbuf[tid + q * NT] = ODD ? T(0.75) * cold_[q] + T(0.25) * cnew[q]
+                                             : T(0.75) * cnew[q] + T(0.25) * cold_[q];
+        }
+    };
+    // the correction of the loaded pairs: per pair (fine row r, columns 2cp,
+    // 2cp+1 of the loaded plane), parent window row (r >> 1) + 1 (3/4) and its
+    // neighbour on r's side (1/4); columns cp, cp+1, cp+2 hold K'-1, K', K'+1
+    // of the pair's parent K' (cell 2K' takes 3/4 K' + 1/4 K'-1, cell 2K'+1
+    // 3/4 K' + 1/4 K'+1)
+    auto correct = [&](V (&regs)[G::LPT]) __attribute__((always_inline)) {
+        if constexpr (PROL) {
+            const T w0 = T(0.75), w1 = T(0.25);
+#pragma unroll
+            for (int q = 0; q < G::LPT; ++q) {
+                const int r = doff[q] / G::EZ, cp = doff[q] - r * G::EZ;
+                const int j0 = (r >> 1) + 1, j1 = j0 + ((r & 1) ? 1 : -1);
+                const T* a0 = xbuf + j0 * G::CK + cp;
+                const T* a1 = xbuf + j1 * G::CK + cp;
+                T t[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) t[d] = w0 * a0[d] + w1 * a1[d];
+                regs[q].x += w0 * t[1] + w1 * t[0];
+                regs[q].y += w0 * t[1] + w1 * t[2];
+            }
+        }
+    };
+
     unsigned hits = 0;  // safeguard activations on owned cells (kGuard models)
     V pA[G::LPT], pB[G::LPT];
     T eA[NK][G::MAXI], eB[NK][G::MAXI];
@@ -226,8 +317,9 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
         });
     };
 
-    auto deposit = [&](auto slc, const V (&regs)[G::LPT]) __attribute__((always_inline)) {
+    auto deposit = [&](auto slc, V (&regs)[G::LPT]) __attribute__((always_inline)) {
         constexpr int SL = decltype(slc)::value;
+        correct(regs);
         T* dst = ring + SL * G::PLANE;
         T* xd = xring + SL * G::PLANE;
 #pragma unroll
@@ -332,11 +424,22 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
     // (which held plane s) receives plane s+2.  ec/sc hold this step's cell
     // data, en/sn receive the next step's (with LATE2, the black stage's
     // entries of ec/sc are consumed here and refilled for step s+2).
-    auto step = [&](auto jc, int s, V (&spare)[G::LPT], const V (&ready)[G::LPT],
+    auto step = [&](auto jc, int s, V (&spare)[G::LPT], V (&ready)[G::LPT],
                     T (&ec)[NK][G::MAXI], T (&sc)[SIG ? NK : 1][SIG ? G::MAXI : 1],
                     T (&en)[NK][G::MAXI], T (&sn)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
         constexpr int J = decltype(jc)::value;
         constexpr int S2 = J & 1;
+        if constexpr (PROL) {
+            // even s: coarse plane s/2 + 1 arrives (s/2 becomes the older);
+            // then the window for plane s + 1, read by this step's deposit
+            // after the stage barriers (the previous deposit's reads ended at
+            // the previous step's closing barrier)
+            if constexpr (S2 == 0) {
+                advance_coarse();
+                load_coarse((s >> 1) + 2);
+            }
+            write_xbuf(std::integral_constant<bool, S2 == 0>{});
+        }
         // (past the chunk end these load wrapped, unused planes: branch-free)
         load_plane(s + 2, spare);
         // next step's stage k works on plane s + 1 - k
@@ -370,6 +473,15 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
         }
     load_plane(sbeg, pA);
     load_plane(sbeg + 1, pB);
+    if constexpr (PROL) {  // older sbeg/2 - 1, newer sbeg/2; sbeg/2 + 1 in flight
+        load_coarse((sbeg >> 1) - 1);
+        advance_coarse();
+        load_coarse(sbeg >> 1);
+        advance_coarse();
+        load_coarse((sbeg >> 1) + 1);
+        write_xbuf(std::integral_constant<bool, false>{});  // plane sbeg (even)
+        __syncthreads();
+    }
     deposit(std::integral_constant<int, 0>{}, pA);
     static_for<0, NK>([&](auto kc) {
         constexpr int k = decltype(kc)::value + 1;
@@ -439,14 +551,16 @@ inline int fused_chunks(int n, int tiles, int resident)
     return n / fused_chunk(n);
 }
 
-template <class T, class M, int TB, bool SIG>
+template <class T, class M, int TB, bool SIG, bool PROL = false>
 int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T* eta,
-                      const T* sigma, hipStream_t s, char* err)
+                      const T* sigma, hipStream_t s, char* err, const T* cphi = nullptr,
+                      const T* cphat = nullptr)
 {
     using Tile = FusedTile<T, M, TB>;
     constexpr int TY = Tile::TY, TZ = Tile::TZ, NT = Tile::NT;
-    constexpr int lds = fused_lds_bytes<T, M, TB, TY, TZ>();
-    auto kern = k_sweep_fused<T, M, TB, TY, TZ, NT, SIG>;
+    constexpr int lds = fused_lds_bytes<T, M, TB, TY, TZ, PROL>();
+    static_assert(lds <= Tile::kFull, "LDS overflow");
+    auto kern = k_sweep_fused<T, M, TB, TY, TZ, NT, SIG, PROL>;
     static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
     if (ensure_dynamic_lds((const void*)kern, lds, lds_done) != hipSuccess) {
         snprintf(err, 512, "hipFuncSetAttribute(shared %d B) failed", lds);
@@ -458,7 +572,8 @@ int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T*
     const int nxc = fused_chunks(n, tiles, res);
     const int blocks = tiles * nxc;
     T ih2 = (T)(1.0 / (h * h));
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, s, m, n, nxc, ih2, in, out, eta, sigma);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, s, m, n, nxc, ih2, in, out, eta, sigma,
+                       cphi, cphat);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         snprintf(err, 512, "k_sweep_fused: %s", hipGetErrorString(e));
@@ -467,23 +582,49 @@ int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T*
     return 0;
 }
 
+template <class T, class M, int TB, bool PROL>
+int launch_fused_pass_sig(const M& m, int n, double h, const T* in, T* out, const T* eta,
+                          const T* sigma, hipStream_t s, char* err, const T* cphi,
+                          const T* cphat)
+{
+    return sigma ? launch_fused_pass<T, M, TB, true, PROL>(m, n, h, in, out, eta, sigma, s, err,
+                                                           cphi, cphat)
+                 : launch_fused_pass<T, M, TB, false, PROL>(m, n, h, in, out, eta, sigma, s, err,
+                                                            cphi, cphat);
+}
+
+// Sweeps in the first fused pass of `count` sweeps with temporal block tb.
+inline int fused_first_pass(int count, int tb) { return (tb >= 2 && count >= 2) ? 2 : 1; }
+
 // `count` sweeps of phi through the fused kernels, ping-ponging between *phi
 // and *tmp.  On return *phi points at the buffer holding the result (the two
-// pointers are swapped when the number of passes is odd).
+// pointers are swapped when the number of passes is odd).  With cphi (and
+// cphat, side n/2), phi += P(cphi - cphat) first, inside the first pass,
+// which must then be a single sweep (fused_first_pass == 1): in a two-sweep
+// pass the extra registers cost a third of the workgroups per CU, more than
+// the separate prolongation pass saves.
 template <class T, class M>
 int launch_fused_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta,
-                        const T* sigma, int count, int tb, hipStream_t s, char* err)
+                        const T* sigma, int count, int tb, hipStream_t s, char* err,
+                        const T* cphi = nullptr, const T* cphat = nullptr)
 {
+    if (cphi && fused_first_pass(count, tb) != 1) {
+        snprintf(err, 512, "fused prolongation needs a single-sweep first pass");
+        return -4;
+    }
     int done = 0;
     while (done < count) {
         const int step = (tb >= 2 && count - done >= 2) ? 2 : 1;
+        const bool prol = cphi && done == 0;
         int r;
         if (step == 2)
-            r = sigma ? launch_fused_pass<T, M, 2, true>(m, n, h, *phi, *tmp, eta, sigma, s, err)
-                      : launch_fused_pass<T, M, 2, false>(m, n, h, *phi, *tmp, eta, sigma, s, err);
+            r = launch_fused_pass_sig<T, M, 2, false>(m, n, h, *phi, *tmp, eta, sigma, s, err,
+                                                      nullptr, nullptr);
         else
-            r = sigma ? launch_fused_pass<T, M, 1, true>(m, n, h, *phi, *tmp, eta, sigma, s, err)
-                      : launch_fused_pass<T, M, 1, false>(m, n, h, *phi, *tmp, eta, sigma, s, err);
+            r = prol ? launch_fused_pass_sig<T, M, 1, true>(m, n, h, *phi, *tmp, eta, sigma, s, err,
+                                                            cphi, cphat)
+                     : launch_fused_pass_sig<T, M, 1, false>(m, n, h, *phi, *tmp, eta, sigma, s,
+                                                             err, nullptr, nullptr);
         if (r) return r;
         T* t = *phi;
         *phi = *tmp;

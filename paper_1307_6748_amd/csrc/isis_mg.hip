@@ -21,6 +21,7 @@
 
 #include "../../include/isis_mg.h"
 #include "amr.hpp"
+#include "bottom.hpp"
 #include "force.hpp"
 #include "full_weighting.hpp"
 #include "fused_sweep.hpp"
@@ -63,6 +64,17 @@ int num_levels(int N)
         ++L;
     }
     return L;
+}
+
+// Level at which the V-cycle hands over to the one-workgroup bottom kernel:
+// the first level below the finest with side <= kBottomMaxN, if at least two
+// levels (it and the 4^3 grid) remain; else -1.
+int bottom_level(int N, int nlev)
+{
+    for (int l = 1; l < nlev; ++l)
+        if ((N >> l) <= kBottomMaxN)
+            return (nlev - l >= 2 && (N >> l) == (4 << (nlev - 1 - l))) ? l : -1;
+    return -1;
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -252,13 +264,44 @@ int launch_halfsweep(const M& m, int n, double h, T* phi, const T* eta, const T*
 // workgroups to hide its per-plane latency.
 constexpr int kFusedSolverMinN = 256;
 
+template <class T>
+int launch_prolong(int nf, T* fine, const T* coarse, const T* coarse_hat, hipStream_t s,
+                   char* err);
+
+template <class T, class M>
+bool fused_level(int n, int tb, int min_fused_n = kFusedSolverMinN)
+{
+    return tb >= 1 && n >= min_fused_n && fused_supported<T, M>(n);
+}
+
+// Whether a smoothing step of `count` sweeps takes the prolongation inside
+// its first fused pass (fused level, single-sweep first pass).
+template <class T, class M>
+bool prolong_fused(int n, int count, int tb, int min_fused_n = kFusedSolverMinN)
+{
+    return count > 0 && fused_level<T, M>(n, tb, min_fused_n) && fused_first_pass(count, tb) == 1;
+}
+
+// With cphi (and cphat, side n/2): phi += P(cphi - cphat) first, inside the
+// first fused pass where prolong_fused(), else by its own kernel.
 template <class T, class M>
 int launch_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta, const T* sigma,
-                  int count, int tb, hipStream_t s, char* err, int min_fused_n = kFusedSolverMinN)
+                  int count, int tb, hipStream_t s, char* err, int min_fused_n = kFusedSolverMinN,
+                  const T* cphi = nullptr, const T* cphat = nullptr)
 {
-    if (count <= 0) return ISIS_OK;
-    if (tb >= 1 && n >= min_fused_n && fused_supported<T, M>(n)) {
+    if (cphi && prolong_fused<T, M>(n, count, tb, min_fused_n))
+        return launch_fused_sweeps<T, M>(m, n, h, phi, tmp, eta, sigma, count, tb, s, err, cphi,
+                                         cphat);
+    if (count > 0 && fused_level<T, M>(n, tb, min_fused_n)) {
+        if (cphi) {
+            int r = launch_prolong<T>(n, *phi, cphi, cphat, s, err);
+            if (r) return r;
+        }
         return launch_fused_sweeps<T, M>(m, n, h, phi, tmp, eta, sigma, count, tb, s, err);
+    }
+    if (cphi) {
+        int r = launch_prolong<T>(n, *phi, cphi, cphat, s, err);
+        if (r) return r;
     }
     for (int q = 0; q < count; ++q) {
         int r = launch_halfsweep<T, M>(m, n, h, *phi, eta, sigma, 0, s, err);
@@ -462,6 +505,7 @@ struct LevP {
 struct isis_mg {
     isis_mg_desc d;
     int nlev;
+    int lb;  // bottom_level(), -1: none
     int device;
     hipStream_t s;
     LevP<double> L64[kMaxLevels];
@@ -481,6 +525,7 @@ struct isis_mg {
     int events_ready;
     hipEvent_t ev0[kMaxTimed], ev1[kMaxTimed];
     int tlaunch[kMaxTimed], tprec[kMaxTimed], tlevel[kMaxTimed];  // tprec: 0 FP64, 1 FP32
+    int tprol[kMaxTimed];  // 1: a pass with the prolongation fused in
     double tupd[kMaxTimed], tbytes[kMaxTimed];
     // use_guess = 2: relative residual after the first V-cycle of the last
     // cold-started solve of each model on this handle (0: none yet)
@@ -651,11 +696,12 @@ int sub_mean(isis_mg* H, T* f, long n3)
 // smoothing step on the small levels, so those are left untimed.
 constexpr int kTimedMinN = 256;
 
-// Smoothing step of level l; with profiling on, the launches on levels of side
-// >= kTimedMinN are bracketed by HIP events on the solver stream (the finest
-// level's are also reported per precision).
+// `count` sweeps of level l (cphi: with the prolongation fused into the first
+// pass); with profiling on, on levels of side >= kTimedMinN, bracketed by HIP
+// events on the solver stream.
 template <class T, class M>
-int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
+int timed_block(isis_mg* H, const M& m, LevP<T>& f, int l, int count, const T* cphi,
+                const T* cphat)
 {
     const int tb = H->tb;
     const bool timed = H->profile && count > 0 && (f.n >= kTimedMinN || l == 0) &&
@@ -663,21 +709,74 @@ int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count)
     const int q = H->ntimed;
     if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
     int r = launch_sweeps<T, M>(m, f.n, f.h, &f.phi, &f.tmp, f.eta, f.sigma, count, tb, H->s,
-                                H->err);
+                                H->err, kFusedSolverMinN, cphi, cphat);
     if (r) return r;
     if (timed) {
         HIP_TRY(H->err, hipEventRecord(H->ev1[q], H->s));
         const double n3 = (double)f.n * f.n * f.n;
         const int tblk = std::max(1, tb);
-        const bool fused = tb >= 1 && f.n >= kFusedSolverMinN && fused_supported<T, M>(f.n);
+        const bool fused = fused_level<T, M>(f.n, tb);
         const int passes = fused ? (count + tblk - 1) / tblk : count;
         H->tlaunch[q] = fused ? fused_launches(count, tb) : 2 * count;
         H->tupd[q] = n3 * count;
-        H->tbytes[q] = (double)passes * n3 * 3.0 * sizeof(T);
+        // compulsory bytes: per pass read phi, eta, write phi; the fused
+        // prolongation adds the two coarse fields
+        H->tbytes[q] = (double)passes * n3 * 3.0 * sizeof(T) + (cphi ? 2.0 * n3 / 8 * sizeof(T) : 0.0);
         H->tprec[q] = sizeof(T) == 4 ? 1 : 0;
         H->tlevel[q] = l;
+        H->tprol[q] = cphi ? 1 : 0;
         H->ntimed = q + 1;
     }
+    return ISIS_OK;
+}
+
+// Smoothing step of level l.  cphi, cphat (the coarse level's field and its
+// restriction, after the coarse-grid correction): phi += P(cphi - cphat)
+// first; where prolong_fused() inside the first pass, which is then timed on
+// its own, elsewhere by the prolongation kernel before the (timed) sweeps.
+template <class T, class M>
+int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count, const T* cphi = nullptr,
+                 const T* cphat = nullptr)
+{
+    if (cphi && prolong_fused<T, M>(f.n, count, H->tb)) {
+        int r = timed_block<T, M>(H, m, f, l, 1, cphi, cphat);  // the first, single-sweep pass
+        if (r) return r;
+        return timed_block<T, M>(H, m, f, l, count - 1, nullptr, nullptr);
+    }
+    if (cphi) {
+        int r = launch_prolong<T>(f.n, f.phi, cphi, cphat, H->s, H->err);
+        if (r) return r;
+    }
+    return timed_block<T, M>(H, m, f, l, count, nullptr, nullptr);
+}
+
+// Levels l .. nlev-1 of the V-cycle in one launch of k_bottom_cycle.
+template <class T, class M>
+int launch_bottom(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
+{
+    const isis_mg_desc& d = H->d;
+    BottomArgs<T> a{};
+    a.nlev = H->nlev - l;
+    a.nu_pre = d.nu_pre;
+    a.nu_post = d.nu_post;
+    a.nu_coarse = d.nu_coarse;
+    a.phi0 = L[l].phi;
+    a.sigma0 = L[l].sigma;
+    for (int q = 0; q < a.nlev; ++q) {
+        const LevP<T>& v = L[l + q];
+        a.eta[q] = v.eta;
+        a.ih2[q] = (T)(1.0 / (v.h * v.h));
+        const double n3 = (double)v.n * v.n * v.n;
+        *updates += (q + 1 < a.nlev ? d.nu_pre + d.nu_post : d.nu_coarse) * n3;
+    }
+    auto kern = H->fw ? k_bottom_cycle<T, M, true> : k_bottom_cycle<T, M, false>;
+    static std::atomic<unsigned> lds_done[2];  // per instantiation: devices set up
+    HIP_TRY(H->err, ensure_dynamic_lds((const void*)kern,
+                                       bottom_lds_elems(kBottomMaxLevels) * (int)sizeof(T),
+                                       lds_done[H->fw ? 1 : 0]));
+    hipLaunchKernelGGL(kern, dim3(1), dim3(bottom_threads<T>()),
+                       bottom_lds_elems(a.nlev) * (int)sizeof(T), H->s, m, a);
+    LAUNCH_CHECK(H->err, "k_bottom_cycle");
     return ISIS_OK;
 }
 
@@ -688,6 +787,7 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
     LevP<T>& f = L[l];
     const double n3 = (double)f.n * f.n * f.n;
     int r;
+    if (l == H->lb) return launch_bottom<T, M>(H, m, L, l, updates);
     if (l == H->nlev - 1) {
         *updates += (double)d.nu_coarse * n3;
         return launch_coarse<T, M>(m, f.h, f.phi, f.eta, f.sigma, d.nu_coarse, H->s, H->err);
@@ -701,8 +801,8 @@ int vcycle(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
                                   c.sigma, c.rr, H->s, H->err, H->fw ? f.tmp : nullptr)))
         return r;
     if ((r = vcycle<T, M>(H, m, L, l + 1, updates))) return r;
-    if ((r = launch_prolong<T>(f.n, f.phi, c.phi, c.phihat, H->s, H->err))) return r;
-    if ((r = timed_sweeps<T, M>(H, m, f, l, d.nu_post))) return r;
+    // the correction phi += P(phi_c - phihat_c), then post-smoothing
+    if ((r = timed_sweeps<T, M>(H, m, f, l, d.nu_post, c.phi, c.phihat))) return r;
     *updates += d.nu_post * n3;
     return ISIS_OK;
 }
@@ -959,6 +1059,12 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             st->ms_smooth += e;
             if (H->tlevel[q] != 0) continue;
             const int k = H->tprec[q];
+            if (H->tprol[q]) {
+                st->fine_prol_ms[k] += e;
+                st->fine_prol_launches[k] += H->tlaunch[q];
+                st->fine_prol_bytes[k] += H->tbytes[q];
+                continue;
+            }
             st->fine_sweep_ms[k] += e;
             st->fine_sweep_launches[k] += H->tlaunch[q];
             st->fine_sweep_updates[k] += H->tupd[q];
@@ -1095,6 +1201,7 @@ int isis_mg_create(const isis_mg_desc* desc, isis_mg_t** out)
     }
     H->d = *desc;
     H->nlev = num_levels(desc->N);
+    H->lb = bottom_level(desc->N, H->nlev);
     H->s = (hipStream_t)desc->stream;
     H->err[0] = 0;
     if (hipGetDevice(&H->device) != hipSuccess ||
@@ -1322,6 +1429,33 @@ int isis_op_sweeps(const isis_model_params* p, double a, int n, double h, double
         int r = launch_sweeps<double, decltype(m)>(m, n, h, &cur, &other, eta, sigma, count,
                                                    temporal_block, (hipStream_t)stream, g_err,
                                                    kFusedMinN);
+        if (r) return r;
+        if (cur != phi)
+            HIP_TRY(g_err, hipMemcpyAsync(phi, cur, sizeof(double) * (size_t)n * n * n,
+                                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
+        return (int)ISIS_OK;
+    });
+}
+
+int isis_op_prolong_sweeps(const isis_model_params* p, double a, int n, double h, double* phi,
+                           double* tmp, const double* eta, const double* sigma,
+                           const double* coarse, const double* coarse_hat, int count,
+                           int temporal_block, void* stream)
+{
+    if (!valid_params(p, a, g_err)) return ISIS_ERR_INVALID_ARG;
+    if (!op_grid_ok(n, 4) || !finite_pos(h) || !phi || !tmp || !eta || !coarse ||
+        !coarse_hat || count < 0 || temporal_block < 0 || temporal_block > 2) {
+        fmt_err(g_err, "prolong_sweeps: need even n >= 4, h > 0, phi/tmp/eta/coarse/coarse_hat "
+                       "non-NULL, count >= 0, temporal_block in 0..2");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!ptrs_aligned({phi, tmp, eta, sigma, coarse, coarse_hat})) return ISIS_ERR_INVALID_ARG;
+    return with_model<double>(*p, a, [&](auto m) {
+        double* cur = phi;
+        double* other = tmp;
+        int r = launch_sweeps<double, decltype(m)>(m, n, h, &cur, &other, eta, sigma, count,
+                                                   temporal_block, (hipStream_t)stream, g_err,
+                                                   kFusedMinN, coarse, coarse_hat);
         if (r) return r;
         if (cur != phi)
             HIP_TRY(g_err, hipMemcpyAsync(phi, cur, sizeof(double) * (size_t)n * n * n,

@@ -106,6 +106,12 @@ int main(void)
     EXPECT(isis_op_halfsweep(&bad, 1.0, 8, 1.0, ok, ok, NULL, 0, NULL) == ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_sweeps(&p, 1.0, 8, 1.0, ok, mis, ok, NULL, 1, 0, NULL) == ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_sweeps(&p, 1.0, 8, 1.0, ok, ok, ok, NULL, 1, 3, NULL) == ISIS_ERR_INVALID_ARG);
+    EXPECT(isis_op_prolong_sweeps(&p, 1.0, 8, 1.0, ok, ok, ok, NULL, ok, NULL, 1, 1, NULL) ==
+           ISIS_ERR_INVALID_ARG);
+    EXPECT(isis_op_prolong_sweeps(&p, 1.0, 2, 1.0, ok, ok, ok, NULL, ok, ok, 1, 1, NULL) ==
+           ISIS_ERR_INVALID_ARG);
+    EXPECT(isis_op_prolong_sweeps(&p, 1.0, 8, 1.0, ok, ok, ok, NULL, mis, ok, 1, 1, NULL) ==
+           ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_defect(&p, 0.0, 8, 1.0, ok, ok, NULL, ok, NULL) == ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_defect(&p, 1.0, 8, 1.0, ok, ok, NULL, NULL, NULL) == ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_restrict(9, ok, ok, NULL) == ISIS_ERR_INVALID_ARG);

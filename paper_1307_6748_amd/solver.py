@@ -115,6 +115,11 @@ class Stats:
     ms_smooth: float = 0.0   # profiling on: smoothing on the finest level and sides >= 256
     restriction: int = 0     # defect restriction used: 0 mean, 1 full weighting
     judged_cycles: int = 0   # cycles after which the FP64 judge ran
+    # finest-level first post-smoothing pass with the prolongation fused in
+    # (profiling on): [FP64, FP32]
+    fine_prol_ms: list = field(default_factory=lambda: [0.0, 0.0])
+    fine_prol_launches: list = field(default_factory=lambda: [0, 0])
+    fine_prol_bytes: list = field(default_factory=lambda: [0.0, 0.0])
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
@@ -123,7 +128,8 @@ class Stats:
                      bool(s.used_guess), list(s.fine_sweep_ms), list(s.fine_sweep_launches),
                      list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block,
                      list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth,
-                     s.restriction, s.judged_cycles)
+                     s.restriction, s.judged_cycles, list(s.fine_prol_ms),
+                     list(s.fine_prol_launches), list(s.fine_prol_bytes))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -278,6 +284,25 @@ def sweeps(params: ModelParams, a: float, h: float, phi, eta, sigma=None, count:
     _ok(A.lib().isis_op_sweeps(C.byref(pc), float(a), n, float(h), _ptr(phi), _ptr(tmp),
                                _ptr(eta), _ptr(sigma), int(count), int(temporal_block),
                                _stream()))
+
+
+def prolong_sweeps(params: ModelParams, a: float, h: float, phi, eta, coarse, coarse_hat,
+                   sigma=None, count: int = 1, temporal_block: int = 0, tmp=None):
+    """phi += P(coarse - coarse_hat), then `count` sweeps, as the solver's
+    post-smoothing step makes them (the correction inside the first fused
+    pass where the sweeps are fused)."""
+    n = _side(phi)
+    _check_field(phi, n, "phi")
+    _check_field(eta, n, "eta")
+    _check_field(coarse, n // 2, "coarse")
+    _check_field(coarse_hat, n // 2, "coarse_hat")
+    if sigma is not None:
+        _check_field(sigma, n, "sigma")
+    tmp = torch.empty_like(phi) if tmp is None else tmp
+    pc = params.c()
+    _ok(A.lib().isis_op_prolong_sweeps(C.byref(pc), float(a), n, float(h), _ptr(phi), _ptr(tmp),
+                                       _ptr(eta), _ptr(sigma), _ptr(coarse), _ptr(coarse_hat),
+                                       int(count), int(temporal_block), _stream()))
 
 
 def defect(params: ModelParams, a: float, h: float, phi, eta, sigma=None, out=None):

@@ -117,3 +117,14 @@ def test_solve_bytes_counts_every_kernel_once():
     st32.restriction = 1
     got = bench.solve_bytes(128, st32, 0, (2, 2), True)
     assert abs(got - mean - 2 * 4 * (32 ** 3 + 16 ** 3 + 8 ** 3)) <= 1e-9 * got
+    # the fused sweep levels (>= 256^3, temporal block >= 1) apply the
+    # correction inside the first post-smoothing pass: no pass of its own
+    st512 = types.SimpleNamespace(cycles=1, cycles_fp32=1, restriction=0, judged_cycles=1)
+    plain = bench.solve_bytes(512, st512, 0, (2, 2), True)
+    fused = bench.solve_bytes(512, st512, 1, (2, 2), True)
+    assert abs(plain - fused - 2 * 4 * (512 ** 3 + 256 ** 3)) <= 1e-9 * plain
+    # not with two sweeps per pass: there the correction keeps its own pass
+    # (and the two post-smoothing sweeps take one pass instead of two)
+    tb2 = bench.solve_bytes(512, st512, 2, (2, 2), True)
+    assert abs(fused - tb2 - 2 * 12 * (512 ** 3 + 256 ** 3) - 2 * 4 * (256 ** 3)
+               + 2 * 4 * (512 ** 3 + 256 ** 3)) <= 1e-9 * plain

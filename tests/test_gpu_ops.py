@@ -160,3 +160,30 @@ def test_sweeps_production_path(orc, name, n, tb):
         g = dev(phi)
         S.sweeps(sp, a, h, g, dev(eta), dev(sigma), count=count, temporal_block=tb)
         assert np.max(np.abs(cubic(g, n) - expect)) <= 1e-12 * (np.abs(expect).max() + 1)
+
+
+@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "linear", "chameleon", "fofr_paper_u"])
+@pytest.mark.parametrize("n", [8, 32, 64, 128])
+@pytest.mark.parametrize("tb", [0, 1, 2])
+def test_prolong_sweeps(orc, name, n, tb):
+    """The solver's post-smoothing step: phi += P(coarse - coarse_hat), then
+    `count` sweeps.  On the fused kernels (n >= 64, tb >= 1) the correction is
+    applied inside the first pass to every value it loads, halo included,
+    from a two-plane coarse ring; it must equal the oracle's prolongation
+    followed by its sweeps (count 0: the prolongation alone)."""
+    from paper_1307_6748_amd import solver as S
+    om, sp, a = models(name)
+    h = 0.5
+    rng = np.random.default_rng(60 + n)
+    phi = field_for(name, n, 61)
+    eta = density(n, 62)
+    sigma = sigma_for(name, n, 63, 0.1)
+    coarse = field_for(name, n // 2, 64)
+    coarse_hat = coarse + 0.05 * rng.standard_normal(coarse.shape)
+    for count in (0, 1, 2, 3):
+        expect = orc.sweep(om, h, orc.prolong_correct(phi, coarse, coarse_hat), eta, sigma,
+                           count=count) if count else orc.prolong_correct(phi, coarse, coarse_hat)
+        g = dev(phi)
+        S.prolong_sweeps(sp, a, h, g, dev(eta), dev(coarse), dev(coarse_hat), sigma=dev(sigma),
+                         count=count, temporal_block=tb)
+        assert np.max(np.abs(cubic(g, n) - expect)) <= 1e-12 * (np.abs(expect).max() + 1), count
