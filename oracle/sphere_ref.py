@@ -35,16 +35,23 @@ def grid_density(n: int, B: float, R: float, delta: float, sub: int = 4) -> np.n
     h = B / n
     off = (np.arange(sub) + 0.5) / sub * h
     x = np.arange(n) * h - B / 2.0  # cell low corners, centred box
-    frac = np.zeros((n, n, n))
+    # nearest and farthest squared distance of each cell from the centre: the
+    # cells wholly inside (all samples inside) get 1, those wholly outside 0,
+    # and only the cells the surface cuts are sampled
+    near = np.where(x > 0, x, np.where(x + h < 0, x + h, 0.0)) ** 2
+    far = np.maximum(x ** 2, (x + h) ** 2)
+    dmin = near[:, None, None] + near[None, :, None] + near[None, None, :]
+    dmax = far[:, None, None] + far[None, :, None] + far[None, None, :]
+    frac = (dmax < R * R).astype(np.float64)
+    cut = np.argwhere((dmin < R * R) & ~(dmax < R * R))
+    cnt = np.zeros(len(cut))
     for ox in off:
-        dx2 = (x + ox) ** 2
+        dx2 = (x[cut[:, 0]] + ox) ** 2
         for oy in off:
-            dy2 = (x + oy) ** 2
-            dxy = dx2[:, None] + dy2[None, :]
+            dxy = dx2 + (x[cut[:, 1]] + oy) ** 2
             for oz in off:
-                dz2 = (x + oz) ** 2
-                frac += (dxy[:, :, None] + dz2[None, None, :]) < R * R
-    frac /= sub ** 3
+                cnt += (dxy + (x[cut[:, 2]] + oz) ** 2) < R * R
+    frac[cut[:, 0], cut[:, 1], cut[:, 2]] = cnt / sub ** 3
     return eta_out + (eta_in - eta_out) * frac
 
 
