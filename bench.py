@@ -329,13 +329,15 @@ def main() -> int:
     for name, sts in rec.items():
         st = sts[-1]
         secs = float(np.mean([s.ms_total for s in sts]) / 1000.0)
-        sb = solve_bytes(n, st, st.temporal_block, (2, 2), args.precision == "mixed")
+        sb = solve_bytes(n, st, st.temporal_block, (st.nu_pre, st.nu_post),
+                         args.precision == "mixed")
         per_model[name] = dict(
             seconds=secs,
             cycles=st.cycles, cycles_fp32=st.cycles_fp32, rel_res=st.rel_res,
             temporal_block=st.temporal_block,
             judged_cycles=st.judged_cycles,
             restriction="full weighting" if st.restriction else "mean of 8",
+            cycle=f"V({st.nu_pre},{st.nu_post})",
             safeguard_hits=st.safeguard_hits,
             smoothing_s=float(np.mean([s.ms_smooth for s in sts]) / 1000.0),
             rho=[None if not np.isfinite(x) else x for x in st.rho_hist[1:]],
@@ -615,6 +617,7 @@ def main() -> int:
             "temporal_block": ({k: v["temporal_block"] for k, v in per_model.items()}
                                if tb < 0 else tb),
             "fp32_floor": args.fp32_floor or None,
+            "cycle": {k: v["cycle"] for k, v in per_model.items()},
             "judge_skip": judge_skip,
             "parallelism": "single GPU", "eta_sha256": eta_sha,
         },

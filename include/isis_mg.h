@@ -100,7 +100,10 @@ typedef struct {
     int N;             /* grid cells per side: power of two, >= 8                 */
     double box;        /* box side, comoving Mpc/h (> 0)                           */
     int nu_pre;        /* pre-smoothing sweeps per level (>= 0; default 2)          */
-    int nu_post;       /* post-smoothing sweeps per level (>= 0; default 2)         */
+    int nu_post;       /* post-smoothing sweeps per level (>= 0), or -1: per model,
+                          1 for ISIS_SYMMETRON and ISIS_CHAMELEON, 2 otherwise
+                          (the faster choice measured on lognormal + halo
+                          densities at 256^3 and 512^3)                         */
     int nu_coarse;     /* red-black sweeps on the 4^3 grid (>= 1; default 32)       */
     int max_cycles;    /* V-cycle limit (1 .. ISIS_MG_MAX_HIST-1; default 50)       */
     int precision;     /* isis_precision                                           */
@@ -194,6 +197,7 @@ typedef struct {
     double fine_prol_bytes[2];    /* compulsory HBM bytes: a pass's (as in
                                      fine_sweep_bytes) plus the two coarse fields,
                                      2 x (n/2)^3 values                           */
+    int nu_pre, nu_post;          /* the smoothing sweeps per level the solve used */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;

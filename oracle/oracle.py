@@ -91,7 +91,9 @@ class Model:
 @dataclass
 class Cfg:
     nu_pre: int = 2
-    nu_post: int = 2
+    # post-smoothing sweeps; None = per model, the GPU library's default: one
+    # for the symmetron and the chameleon, two for the others
+    nu_post: int | None = None
     nu_coarse: int = 32
     max_cycles: int = 50
     # restriction of the defect: False = mean of the 8 children, True = full
@@ -101,7 +103,8 @@ class Cfg:
 
     def _c(self, model: int = SYMMETRON) -> _Cfg:
         fw = (model == FR_HS) if self.restrict_fw is None else bool(self.restrict_fw)
-        return _Cfg(self.nu_pre, self.nu_post, self.nu_coarse, self.max_cycles, int(fw))
+        post = (1 if model in (SYMMETRON, CHAMELEON) else 2) if self.nu_post is None else self.nu_post
+        return _Cfg(self.nu_pre, post, self.nu_coarse, self.max_cycles, int(fw))
 
 
 @dataclass

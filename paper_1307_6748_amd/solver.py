@@ -120,6 +120,8 @@ class Stats:
     fine_prol_ms: list = field(default_factory=lambda: [0.0, 0.0])
     fine_prol_launches: list = field(default_factory=lambda: [0, 0])
     fine_prol_bytes: list = field(default_factory=lambda: [0.0, 0.0])
+    nu_pre: int = 2          # smoothing sweeps per level the solve used
+    nu_post: int = 2
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
@@ -129,7 +131,7 @@ class Stats:
                      list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block,
                      list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth,
                      s.restriction, s.judged_cycles, list(s.fine_prol_ms),
-                     list(s.fine_prol_launches), list(s.fine_prol_bytes))
+                     list(s.fine_prol_launches), list(s.fine_prol_bytes), s.nu_pre, s.nu_post)
 
 
 def _ptr(t: torch.Tensor | None):
@@ -160,9 +162,10 @@ class Solver:
     default) restricts the defect by full weighting for f(R) and by the
     8-child mean otherwise; 0 / 1 force the mean / full weighting.
     judge_skip: skip the FP64 judge on cycles predicted to stay above tol
-    (see isis_mg_desc.judge_skip)."""
+    (see isis_mg_desc.judge_skip).  nu_post = -1 (the default): one
+    post-smoothing sweep for the symmetron and the chameleon, two otherwise."""
 
-    def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = 2,
+    def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = -1,
                  nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
                  temporal_block: int = -1, fp32_floor: float = 0.0, guess_accept: float = 0.0,
                  restriction: int = -1, judge_skip: bool = False):

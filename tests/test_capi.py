@@ -56,8 +56,10 @@ def test_workspace_size_validation():
                 dict(fp32_floor=float("nan")), dict(guess_accept=-0.1),
                 dict(guess_accept=1.5), dict(guess_accept=float("nan")),
                 dict(restriction=2), dict(restriction=-2), dict(judge_skip=2),
-                dict(judge_skip=-1)):
+                dict(judge_skip=-1), dict(nu_post=-2), dict(nu_pre=-1)):
         assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad
+    # nu_post = -1 picks the sweeps per model; with nu_pre = 0 that is still >= 1
+    assert lib.isis_mg_workspace_size(C.byref(_desc(nu_pre=0, nu_post=-1))) > 0
 
 
 def test_create_rejects_bad_workspace_without_gpu():
