@@ -151,15 +151,21 @@ def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: boo
 def solve_bytes(n: int, st, tb: int, nu: tuple, mixed: bool) -> float:
     """Compulsory HBM bytes of a whole solve (the algorithmic traffic of its
     kernels with perfect on-chip reuse): density hierarchy, cold start and
-    r_ref, the V-cycles (FP32 cycles in mixed precision, FP64 otherwise; the
+    r_ref (one pass on sides that are multiples of 64), the V-cycles (FP32 cycles in mixed precision, FP64 otherwise; the
     fused kernels' temporal block on levels >= 256^3) and the FP64 judge of
     each cycle (reads the iterate and the FP64 density)."""
     nlev = 1
     while (n >> (nlev - 1)) > 4:
         nlev += 1
     n3 = float(n) ** 3
-    b = 8 * n3 * (1 + 1 / 7) + (4 * n3 * (1 + 1 / 7) if mixed else 0)  # eta hierarchy (+FP32 copy)
-    b += 8 * n3 + 8 * n3 + (4 * n3 if mixed else 0) + 16 * n3            # cold start, r_ref
+    if n >= 64 and n % 64 == 0 and n & (n - 1) == 0:
+        # one setup pass: read eta, write the cold start (+ FP32 copy), eta's
+        # FP32 copy and the next level; then the rest of the hierarchy
+        b = (8 + 8 + 1 + (8 if mixed else 0)) * n3
+        b += (8 + 1 + (4 if mixed else 0)) * n3 / 8 * (1 + 1 / 7)
+    else:
+        b = 8 * n3 * (1 + 1 / 7) + (4 * n3 * (1 + 1 / 7) if mixed else 0)  # eta hierarchy (+FP32)
+        b += 8 * n3 + 8 * n3 + (4 * n3 if mixed else 0) + 16 * n3            # cold start, r_ref
     cyc64 = st.cycles - st.cycles_fp32
     for count, s in ((st.cycles_fp32, 4), (cyc64, 8)):
         if count == 0:

@@ -165,6 +165,8 @@ FofR<T> make_fofr(const isis_model_params& p, double a)
     m.inv_np1 = 1.0 / (p.n + 1.0);
     m.a3 = a3;
     m.cL = cL;
+    m.inv_a3 = 1.0 / a3;
+    m.inv_1pcl = 1.0 / (1.0 + cL);
     m.np1 = p.n + 1.0;
     m.ushift = 0.0;
     m.stiff_e = kFofRStiff;
@@ -200,6 +202,8 @@ FofR<T, true> make_chameleon(const isis_model_params& p)
     m.inv_np1 = 1.0 + p.cham_n;
     m.a3 = m.c1;
     m.cL = 0.0;
+    m.inv_a3 = 1.0 / m.a3;
+    m.inv_1pcl = 1.0;
     m.np1 = 1.0 / m.inv_np1;
     m.ushift = 0.0;
     m.stiff_e = (float)(100.0 / m.c1);
@@ -521,7 +525,7 @@ struct isis_mg {
     hipStream_t s;
     LevP<double> L64[kMaxLevels];
     LevP<float> L32[kMaxLevels];
-    double* partial;  // kReduceBlocks
+    double* partial;  // 2 * kReduceBlocks
     double* scal;     // 16: [0] reduction result, [8] safeguard counter (64-bit)
     double* host;     // pinned, 16
     double* tmp0;     // finest-level scratch field (workspace)
@@ -590,7 +594,7 @@ size_t carve(const isis_mg_desc& d, char* base, isis_mg* h)
             if (l == 0) h->tmp0 = a.tmp;
         }
     }
-    double* partial = (double*)take(sizeof(double) * kReduceBlocks);
+    double* partial = (double*)take(sizeof(double) * 2 * kReduceBlocks);  // two sums at once
     double* scal = (double*)take(sizeof(double) * 16);
     if (h) {
         h->partial = partial;
@@ -857,20 +861,46 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     H->L64[0].tmp = H->tmp0;
     H->L64[0].eta = const_cast<double*>(density);
     H->L64[0].sigma = nullptr;
-    // Density hierarchy; in mixed precision each restriction also writes the
-    // FP32 copy of its fine level (the coarsest is converted below).
-    for (int l = 1; l < H->nlev; ++l)
-        if ((r = launch_restrict<double>(H->L64[l - 1].n, H->L64[l - 1].eta, H->L64[l].eta, H->s,
-                                         H->err, mixed ? H->L32[l - 1].eta : nullptr)))
-            return r;
-
     // r_ref from the cold start, whatever the initial guess.  Without a
     // guess the cold start is built in the field itself (in mixed precision
-    // together with the FP32 copy the first cycle starts from), and the same
-    // pass sums its squares for the exact-root test below.
+    // together with the FP32 copy the first cycle starts from); its sum of
+    // squares serves the exact-root test below.  The density hierarchy: in
+    // mixed precision each restriction also writes the FP32 copy of its fine
+    // level (the coarsest is converted below).
     double* cold = use_guess ? H->L64[0].tmp : field;
     const bool cold32 = mixed && !use_guess && !singular;
-    {
+    const double h0 = H->L64[0].h;
+    double cold_rms, r_ref;
+    using NG = NormTileF;
+    if ((N & (N - 1)) == 0 && N % NG::TZ == 0 && N % NG::TY == 0 && N % NG::XC == 0) {
+        // one pass over the FP64 density: cold start, its copies, the
+        // density's FP32 copy and first restriction, and both sums
+        const long tiles = (long)(N / NG::TZ) * (N / NG::TY) * (N / NG::XC);
+        const int g = (int)std::min<long>(kReduceBlocks, tiles);
+        hipLaunchKernelGGL((k_setup_tiled<M64>), dim3(g), dim3(kBlock), 0, H->s, m64, N,
+                           1.0 / (h0 * h0), density, cold, cold32 ? H->L32[0].phi : nullptr,
+                           M32::kVar, -shift32 * M32::kVar, mixed ? H->L32[0].eta : nullptr,
+                           H->L64[1].eta, H->partial, H->partial + kReduceBlocks);
+        LAUNCH_CHECK(H->err, "k_setup_tiled");
+        for (int l = 2; l < H->nlev; ++l)
+            if ((r = launch_restrict<double>(H->L64[l - 1].n, H->L64[l - 1].eta, H->L64[l].eta,
+                                             H->s, H->err, mixed ? H->L32[l - 1].eta : nullptr)))
+                return r;
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
+        LAUNCH_CHECK(H->err, "k_reduce");
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial + kReduceBlocks, g,
+                           H->scal + 1);
+        LAUNCH_CHECK(H->err, "k_reduce");
+        HIP_TRY(H->err, hipMemcpyAsync(H->host, H->scal, 2 * sizeof(double),
+                                       hipMemcpyDeviceToHost, H->s));
+        HIP_TRY(H->err, hipStreamSynchronize(H->s));
+        r_ref = std::sqrt(H->host[0] / (double)n3);
+        cold_rms = std::sqrt(H->host[1] / (double)n3);
+    } else {
+        for (int l = 1; l < H->nlev; ++l)
+            if ((r = launch_restrict<double>(H->L64[l - 1].n, H->L64[l - 1].eta, H->L64[l].eta,
+                                             H->s, H->err, mixed ? H->L32[l - 1].eta : nullptr)))
+                return r;
         const int g = std::min(kReduceBlocks, grid_for(n3));
         hipLaunchKernelGGL((k_cold_start_sumsq<M64>), dim3(g), dim3(kBlock), 0, H->s, m64, n3,
                            density, cold, cold32 ? H->L32[0].phi : nullptr, M32::kVar,
@@ -881,18 +911,16 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         HIP_TRY(H->err,
                 hipMemcpyAsync(H->host, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->s));
         HIP_TRY(H->err, hipStreamSynchronize(H->s));
+        cold_rms = std::sqrt(H->host[0] / (double)n3);
+        if ((r = fine_rms<double, M64>(H, m64, cold, density, nullptr, &r_ref))) return r;
     }
     // A cold-start residual at the rounding level of its Laplacian means the
     // cold start is an exact root (uniform density): absolute tolerance.
-    const double cold_rms = std::sqrt(H->host[0] / (double)n3);
-    double r_ref;
-    if ((r = fine_rms<double, M64>(H, m64, cold, density, nullptr, &r_ref))) return r;
     if (!std::isfinite(r_ref)) {
         fmt_err(H->err, "density gives a non-finite cold-start residual (NaN/Inf or invalid "
                         "values in eta)");
         return ISIS_ERR_INVALID_ARG;
     }
-    const double h0 = H->L64[0].h;
     const double cold_scale = 1e-14 * 6.0 / (h0 * h0) * cold_rms;
     if (singular && (r = sub_mean<double>(H, field, n3))) return r;
     const double rnorm = r_ref > cold_scale ? r_ref : 1.0;

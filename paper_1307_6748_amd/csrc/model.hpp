@@ -164,6 +164,7 @@ struct FofR {
     __device__ __forceinline__ unsigned guarded(T, T) const { return 0u; }
     double Q, cLa3, c1, inv_np1;
     double a3, cL, np1;  // for the cold start
+    double inv_a3, inv_1pcl;  // 1/a^3 and 1/(1 + cL): the cold start without divisions
     double ushift;       // added to the cold start (variable offset)
     double qc1n;         // Q c1 / (n+1): dS/du = qc1n e^{-u/(n+1)}
     float stiff_e;       // e^{-u/(n+1)} above which the FP32 source is evaluated in FP64
@@ -259,7 +260,7 @@ struct FofR {
     __device__ __forceinline__ T cold(T eta) const
     {
         // u = -(n+1) ln[(eta/a^3 + cL)/(1 + cL)]
-        return (T)((-np1 * log(((double)eta / a3 + cL) / (1.0 + cL)) + ushift) * kVar);
+        return (T)((-np1 * log(fma((double)eta, inv_a3, cL) * inv_1pcl) + ushift) * kVar);
     }
 };
 

@@ -705,4 +705,181 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// Solve setup in one pass over the FP64 density (tiles, ring and summation
+// order of k_defect_norm_tiled): the cold start phi_c = cold(eta), computed
+// for every loaded value and staged in the ring, gives the defect whose
+// squares sum to r_ref^2 (partial); the same pass writes phi_c to `cold`, its
+// FP32 copy (cold - shift) * kVar to cold32 (if not NULL), the FP32 copy of
+// eta to eta32 (if not NULL) and the 8-child mean of eta to eta_c (the next
+// level, children summed in the order of k_restrict: x, then y, then z), and
+// sums cold^2 into partial2.  n a power of two, a multiple of the tile.
+template <class M>
+__global__ __launch_bounds__(kBlock) void k_setup_tiled(M m, int n, double ih2,
+                                                        const double* __restrict__ eta,
+                                                        double* __restrict__ cold,
+                                                        float* __restrict__ cold32, double scale32,
+                                                        double offset32, float* __restrict__ eta32,
+                                                        double* __restrict__ eta_c,
+                                                        double* __restrict__ partial,
+                                                        double* __restrict__ partial2)
+{
+    using G = NormTileF;
+    using SO = StageOp<double, M>;
+    using VD = typename Vec2<double>::type;
+    using VF = typename Vec2<float>::type;
+    constexpr bool STAGED = SO::kStaged;
+    static_assert(G::XC % 2 == 0 && G::TY % 2 == 0, "tiles cover whole coarse cells");
+    __shared__ __align__(16) double ring[3][G::PLANE];
+    __shared__ __align__(16) double xring[STAGED ? 3 : 1][STAGED ? G::PLANE : 2];
+    __shared__ double exptab[SO::kTable ? kExpTable : 1];
+    if constexpr (SO::kTable) {
+        exp_table_fill(exptab);
+        __syncthreads();
+    }
+    const int tid = threadIdx.x;
+    const int msk = n - 1;
+    const int nc = n >> 1;
+    const int ntz = n / G::TZ, nty = n / G::TY, ntx = n / G::XC;
+    const int ntiles = ntz * nty * ntx;
+    const int nb = gridDim.x;
+    const bool remap = (nb & 7) == 0 && (ntiles & 7) == 0;
+    const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, per = ntiles >> 3;
+    // this thread's pair: row rr, columns 2cp, 2cp+1 of the tile; rows rr and
+    // rr ^ 1 sit in the two halves of one wave (32 pairs per row)
+    const int rr = tid / (G::TZ / 2), cp = tid - rr * (G::TZ / 2);
+    double acc = 0.0, acc2 = 0.0;
+    for (int it = 0;; ++it) {
+        int t;
+        if (remap) {
+            const int loc = lb + it * (nb >> 3);
+            if (loc >= per) break;
+            t = xcd * per + loc;
+        } else {
+            t = blockIdx.x + it * nb;
+            if (t >= ntiles) break;
+        }
+        const int zt = t % ntz, yt = (t / ntz) % nty, xt = t / (ntz * nty);
+        const int x0 = xt * G::XC, y0 = yt * G::TY, z0 = zt * G::TZ;
+        const size_t n2 = (size_t)n * n;
+        unsigned poff[G::LPT];
+#pragma unroll
+        for (int q = 0; q < G::LPT; ++q) {
+            const int k = min(tid + q * G::NT, G::PAIRS - 1);
+            const int r = k / G::NP, c2 = k - r * G::NP;
+            poff[q] = (unsigned)(((y0 - 1 + r) & msk) * n + ((z0 - 2 + 2 * c2) & msk));
+        }
+        const unsigned eoff = (unsigned)((y0 + rr) * n + z0 + 2 * cp);
+        VD regs[G::LPT];
+        auto load = [&](int x) __attribute__((always_inline)) {
+            const double* pl = eta + (size_t)(x & msk) * n2;
+#pragma unroll
+            for (int q = 0; q < G::LPT; ++q) regs[q] = *reinterpret_cast<const VD*>(pl + poff[q]);
+        };
+        auto deposit = [&](int x) __attribute__((always_inline)) {
+            double* d = ring[(x - x0 + 3) % 3];
+#pragma unroll
+            for (int q = 0; q < G::LPT; ++q) {
+                const int k = tid + q * G::NT;
+                if ((q + 1) * G::NT <= G::PAIRS || k < G::PAIRS) {
+                    const double a = (double)m.cold(regs[q].x), b = (double)m.cold(regs[q].y);
+                    *reinterpret_cast<VD*>(d + 2 * k) = VD{a, b};
+                    if constexpr (STAGED) {
+                        double* e = xring[(x - x0 + 3) % 3];
+                        *reinterpret_cast<VD*>(e + 2 * k) = VD{SO::stage(a, exptab), SO::stage(b, exptab)};
+                    }
+                }
+            }
+        };
+        auto eta_at = [&](int x) __attribute__((always_inline)) {
+            return (size_t)(x & msk) * n2 + eoff;
+        };
+        load(x0 - 1);
+        deposit(x0 - 1);
+        load(x0);
+        deposit(x0);
+        VD enext = *reinterpret_cast<const VD*>(eta + eta_at(x0));
+        load(x0 + 1);
+        __syncthreads();
+        double csum = 0.0;  // the coarse cell's children so far (even rows)
+        for (int x = x0; x < x0 + G::XC; ++x) {
+            deposit(x + 1);
+            const VD e2 = enext;
+            const size_t g = eta_at(x);
+            enext = *reinterpret_cast<const VD*>(eta + eta_at(min(x + 1, x0 + G::XC - 1)));
+            load(min(x + 2, x0 + G::XC));
+            __syncthreads();
+            const double* pv = ring[(x - 1 - x0 + 3) % 3];
+            const double* cu = ring[(x - x0 + 3) % 3];
+            const double* nx = ring[(x + 1 - x0 + 3) % 3];
+            const int o = (rr + 1) * G::EZ + 2 + 2 * cp;
+            const VD c = *reinterpret_cast<const VD*>(cu + o);
+            const VD xm = *reinterpret_cast<const VD*>(pv + o);
+            const VD xp = *reinterpret_cast<const VD*>(nx + o);
+            const VD ym = *reinterpret_cast<const VD*>(cu + o - G::EZ);
+            const VD yp = *reinterpret_cast<const VD*>(cu + o + G::EZ);
+            const double zm = cu[o - 1], zp = cu[o + 2];
+            VD ec, exm, exp_, eym, eyp;
+            double ezm = 0.0, ezp = 0.0;
+            if constexpr (STAGED) {
+                const double* epv = xring[(x - 1 - x0 + 3) % 3];
+                const double* ecu = xring[(x - x0 + 3) % 3];
+                const double* enx = xring[(x + 1 - x0 + 3) % 3];
+                ec = *reinterpret_cast<const VD*>(ecu + o);
+                exm = *reinterpret_cast<const VD*>(epv + o);
+                exp_ = *reinterpret_cast<const VD*>(enx + o);
+                eym = *reinterpret_cast<const VD*>(ecu + o - G::EZ);
+                eyp = *reinterpret_cast<const VD*>(ecu + o + G::EZ);
+                ezm = ecu[o - 1];
+                ezp = ecu[o + 2];
+            }
+#pragma unroll
+            for (int dk = 0; dk < 2; ++dk) {
+                double nbv[6];
+                nbv[0] = xm[dk];
+                nbv[1] = xp[dk];
+                nbv[2] = ym[dk];
+                nbv[3] = yp[dk];
+                nbv[4] = dk ? c[0] : zm;
+                nbv[5] = dk ? zp : c[1];
+                double L, D;
+                if constexpr (STAGED) {
+                    double enb[6];
+                    enb[0] = exm[dk];
+                    enb[1] = exp_[dk];
+                    enb[2] = eym[dk];
+                    enb[3] = eyp[dk];
+                    enb[4] = dk ? ec[0] : ezm;
+                    enb[5] = dk ? ezp : ec[1];
+                    SO::eval(m, c[dk], nbv, ec[dk], enb, e2[dk], ih2, L, D);
+                } else {
+                    m.op(c[dk], nbv, e2[dk], ih2, L, D);
+                }
+                acc += L * L;
+                acc2 += c[dk] * c[dk];
+            }
+            *reinterpret_cast<VD*>(cold + g) = c;
+            if (cold32)
+                *reinterpret_cast<VF*>(cold32 + g) =
+                    VF{(float)(c[0] * scale32 + offset32), (float)(c[1] * scale32 + offset32)};
+            if (eta32) *reinterpret_cast<VF*>(eta32 + g) = VF{(float)e2[0], (float)e2[1]};
+            // the next level's density: children (x, row, z) in the order x, y, z
+            const double p0 = __shfl_xor(e2[0], 32, 64), p1 = __shfl_xor(e2[1], 32, 64);
+            if ((x & 1) == 0) csum = 0.0;
+            csum += e2[0];
+            csum += e2[1];
+            csum += p0;
+            csum += p1;
+            if ((x & 1) && (rr & 1) == 0)
+                eta_c[((size_t)(x >> 1) * nc + ((y0 + rr) >> 1)) * nc + (z0 >> 1) + cp] = csum / 8.0;
+            __syncthreads();  // plane x-1's slot is refilled next
+        }
+    }
+    double s = block_sum(acc);
+    double s2 = block_sum(acc2);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = s;
+        partial2[blockIdx.x] = s2;
+    }
+}
+
 }  // namespace isis
