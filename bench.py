@@ -105,7 +105,7 @@ def roofline(kern: dict, n: int):
         avg_ms = v["ms"] / v["launches"]
         bpl = v["bytes"] / v["launches"]
         ach = bpl / (avg_ms * 1e-3) / 1e9
-        tb = v["tb"]
+        tb = 1 if prol else v["tb"]  # the fused prolongation rides in single-sweep passes
         what = ("first post-smoothing pass, prolongation fused in" if prol
                 else "no FAS source")
         kernels.append(dict(
