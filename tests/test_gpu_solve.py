@@ -360,3 +360,21 @@ def test_judge_skip_keeps_the_stop_test(name, precision):
         assert st1.judged_cycles < st1.cycles
     diff = float((phi1 - phi0).norm() / phi0.norm())
     assert diff <= 1e-5, diff
+
+
+@pytest.mark.parametrize("name,post", [("symmetron_a1", 1), ("chameleon", 1), ("fofr", 2),
+                                       ("linear", 2)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_default_post_smoothing_per_model(name, post, precision):
+    """nu_post = -1 (the default) runs one post-smoothing sweep for the
+    symmetron and the chameleon and two for the others, reports it in the
+    stats, and gives the same field, bit for bit, as asking for that count."""
+    from paper_1307_6748_amd import synth
+    _, sp, a = models(name)
+    n, box = 64, 64.0
+    eta = dev(synth.lognormal(n, box, 1.0, 71))
+    phi0, st0 = _solver(n, box, precision=precision).solve(eta, sp, a, 1e-9)
+    phi1, st1 = _solver(n, box, precision=precision, nu_post=post).solve(eta, sp, a, 1e-9)
+    assert st0.status == 0 and st0.nu_post == post and st0.nu_pre == 2
+    assert st1.nu_post == post and st0.cycles == st1.cycles
+    assert bool((phi0 == phi1).all())
