@@ -130,18 +130,25 @@ def level_bytes(nl: int, s: int, passes: int, sig: bool, fw: bool, coarsest: boo
     weighting in two passes (double precision, or sides the single-pass kernel
     does not tile: below 64 or not a power of two) adding the fine defect's
     write and read; the coarse source reads phi_c, eta_c, the restricted
-    defect and writes Sigma_c; the correction reads the two coarse fields and,
-    unless `fused` (fused sweep levels, where the first post-smoothing pass
-    applies it to the values it loads), reads and writes phi.  The coarsest
-    level is smoothed in one workgroup and moves no more than its 64 cells."""
+    defect and writes Sigma_c, except on the tiled descents (sides >= 64, powers
+    of two; full weighting there only in single precision), which write Sigma_c
+    in place of the restricted defect and read only eta_c for it; the
+    correction reads the two coarse fields and, unless `fused` (fused sweep
+    levels, where the first post-smoothing pass applies it to the values it
+    loads), reads and writes phi.  The coarsest level is smoothed in one
+    workgroup and moves no more than its 64 cells."""
     c = float(nl) ** 3
     if coarsest:
         return 4 * s * c
+    tiled = nl >= 64 and nl & (nl - 1) == 0
     b = passes * (3 + (1 if sig else 0)) * s * c          # smoothing
     b += (2 + (1 if sig else 0)) * s * c + 3 * s * c / 8  # defect + restriction
-    if fw and not (s == 4 and nl >= 64 and nl & (nl - 1) == 0):
+    if fw and not (s == 4 and tiled):
         b += 2 * s * c                                    # fine defect written, read
-    b += 4 * s * c / 8                                    # coarse source
+    if tiled and (s == 4 or not fw):
+        b += s * c / 8                                    # coarse source in the descent
+    else:
+        b += 4 * s * c / 8                                # coarse source
     b += 2 * s * c / 8                                    # correction: the coarse fields
     if not fused:
         b += 2 * s * c                                    # its own pass over phi

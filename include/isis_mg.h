@@ -326,7 +326,10 @@ int isis_op_restrict(int n_fine, const double* fine, double* coarse, void* strea
  * R the mean of the 8 children; R' = R, or full weighting (see
  * isis_op_restrict_fw) when fine_scratch (device n_fine^3 doubles, receives
  * the fine defect) is not NULL.  sigma_f may be NULL (finest level).  rr_c:
- * coarse scratch (receives R' of the fine defect). */
+ * coarse scratch; on the paths that restrict the defect before forming
+ * sigma_c it receives R' of the fine defect, while the LDS-tiled descent
+ * (n_fine a power of two >= 64, with R' = R) forms sigma_c in the same pass
+ * and leaves rr_c untouched. */
 int isis_op_fas_descend(const isis_model_params* p, double a, int n_fine, double h_fine,
                         const double* phi_f, const double* eta_f, const double* sigma_f,
                         const double* eta_c, double* phi_c, double* phihat_c, double* sigma_c,

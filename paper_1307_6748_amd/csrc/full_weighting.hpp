@@ -160,7 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict_fw_tiled(int nf, const T* _
 // k_restrict_fw_tiled).  phi_c = phihat_c = the mean of the 8 children, as in
 // k_defect_restrict_tiled.  The phi ring holds fine planes 2I .. 2I+3 with a
 // two-cell halo (rows y0-2 .. y0+17, columns z0-2 .. z0+65), with e^phi beside
-// them for staged models.
+// them for staged models.  The coarse FAS source sigma_c = L_c(phi_c) - R'(d)
+// is completed in the same step, as k_fas_sigma computes it: the ring also
+// holds the children of the coarse cell's four y-z neighbours and of its
+// successor in x, whose means are summed again there (the predecessor's is
+// kept from the previous step); the restricted defect is not stored.
 template <int XC_>
 struct DefectFwTile {
     static constexpr int TY = 16, TZ = 64, XC = XC_, NT = kBlock;
@@ -185,11 +189,14 @@ constexpr int defect_fw_lds_bytes()
     return (4 * G::PLANE * (StageOp<T, M>::kStaged ? 2 : 1) + 2 * G::DPLANE) * (int)sizeof(T);
 }
 
+// At least three waves per SIMD (at most 168 VGPRs), as many workgroups as
+// the LDS allows: the f(R) form then keeps two values in scratch, only in the
+// double-precision branch of the stiff source.
 template <class T, class M, bool SIG, int XC>
-__global__ __launch_bounds__(kBlock) void k_defect_restrict_fw_tiled(
+__global__ __launch_bounds__(kBlock, 3) void k_defect_restrict_fw_tiled(
     M m, int nf, T ih2, const T* __restrict__ phi, const T* __restrict__ eta,
-    const T* __restrict__ sigma, T* __restrict__ phi_c, T* __restrict__ phihat_c,
-    T* __restrict__ rr_c)
+    const T* __restrict__ sigma, T* __restrict__ phi_c, T* __restrict__ phihat_c, T ih2c,
+    const T* __restrict__ eta_c, T* __restrict__ sigma_c)
 {
     using G = DefectFwTile<XC>;
     using V = typename Vec2<T>::type;
@@ -381,6 +388,23 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_fw_tiled(
             }
         }
     };
+    // the mean of the 8 children of the coarse cell whose child (0, 0) sits at
+    // ring offset o, coarse plane X (fine planes 2X, 2X+1 in the ring), in the
+    // order of k_defect_restrict_tiled
+    auto ring_mean = [&](int X, int o) __attribute__((always_inline)) {
+        T sp = T(0);
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+            const T* cu = ring + ((2 * X + di) & 3) * G::PLANE;
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const V c = *reinterpret_cast<const V*>(cu + o + dj * G::EZ);
+                sp += c[0];
+                sp += c[1];
+            }
+        }
+        return sp / T(8);
+    };
     const T w[4] = {T(0.125), T(0.375), T(0.375), T(0.125)};
     // y and z filter of buffered plane s at this thread's coarse cell: region
     // rows 2jj .. 2jj+3 and columns 2kk .. 2kk+3 (fine rows 2jj-1 .. 2jj+2 and
@@ -398,7 +422,8 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_fw_tiled(
         }
         return sy;
     };
-    // prologue: phi planes 2I0-2 .. 2I0+1 in LDS, defect and Q of 2I0-1, 2I0
+    // prologue: phi planes 2I0-2 .. 2I0+1 in LDS, defect and Q of 2I0-1, 2I0,
+    // and the means of coarse planes I0-1 and I0
     load2(2 * I0 - 2);
     deposit1(2 * I0 - 2, ra);
     deposit1(2 * I0 - 1, rb);
@@ -409,6 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_fw_tiled(
     load2(2 * I0 + 2);
     __syncthreads();
     defects(2 * I0 - 1);
+    T pm = ring_mean(I0 - 1, o00), pc = ring_mean(I0, o00);
     __syncthreads();
     T qa = filt(0), qb = filt(1);
     for (int I = I0; I < I0 + G::XC; ++I) {
@@ -416,31 +442,35 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_fw_tiled(
         deposit1(2 * I + 2, ra);
         deposit1(2 * I + 3, rb);
         load_cells(2 * I + 1);
+        const size_t q = ((size_t)I * nc + (y0 / 2 + jj)) * nc + z0 / 2 + kk;
+        const T ec = eta_c[q];
         load2(min(2 * I + 4, 2 * (I0 + G::XC)));  // clamped: branch-free
         __syncthreads();
         defects(2 * I + 1);
-        // the mean of the 8 children (fine planes 2I, 2I+1), in the order of
-        // k_defect_restrict_tiled
-        T sp = T(0);
-#pragma unroll
-        for (int di = 0; di < 2; ++di) {
-            const T* cu = ring + ((2 * I + di) & 3) * G::PLANE;
-#pragma unroll
-            for (int dj = 0; dj < 2; ++dj) {
-                const V c = *reinterpret_cast<const V*>(cu + o00 + dj * G::EZ);
-                sp += c[0];
-                sp += c[1];
-            }
-        }
         __syncthreads();
         const T qc = filt(0), qd = filt(1);
-        const size_t q = ((size_t)I * nc + (y0 / 2 + jj)) * nc + z0 / 2 + kk;
-        const T pc = sp / T(8);
+        // the coarse plane I's neighbours of this thread's cell (fine planes
+        // 2I, 2I+1: means of the neighbouring cells' children; 2I+2, 2I+3:
+        // the mean of plane I+1), all in the ring until the next step
+        T nbv[6];
+        nbv[0] = pm;
+        nbv[1] = ring_mean(I + 1, o00);
+        nbv[2] = ring_mean(I, o00 - 2 * G::EZ);
+        nbv[3] = ring_mean(I, o00 + 2 * G::EZ);
+        nbv[4] = ring_mean(I, o00 - 2);
+        nbv[5] = ring_mean(I, o00 + 2);
         phi_c[q] = pc;
         phihat_c[q] = pc;
-        rr_c[q] = w[0] * qa + w[1] * qb + w[2] * qc + w[3] * qd;
+        // sigma_c = L_c(phi_c) - R'(defect), as k_fas_sigma computes it
+        // (carrying e^phi_c of the x-neighbours from step to step instead of
+        // recomputing them measured slower: the extra registers spill)
+        T L, D;
+        m.op(pc, nbv, ec, ih2c, L, D);
+        sigma_c[q] = L - (w[0] * qa + w[1] * qb + w[2] * qc + w[3] * qd);
         qa = qc;
         qb = qd;
+        pm = pc;
+        pc = nbv[1];
     }
 }
 

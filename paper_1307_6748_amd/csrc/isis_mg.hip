@@ -326,27 +326,55 @@ int launch_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta, c
     return ISIS_OK;
 }
 
-template <class T, class M, bool SIG, bool FW>
-int launch_restrict_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
-                          const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, T* dfine, int blocks,
-                          int lds, hipStream_t s, char* err)
+// FW: the fine defect to dfine (restricted afterwards); else the 8-child
+// mean of the defect, and with it the coarse source sigma_c in the same pass.
+// XC coarse planes per workgroup: 8, and 4 or 2 on the small levels (more
+// workgroups; see launch_defect_fw).
+template <class T, class M, bool SIG, bool FW, int XC>
+int launch_restrict_tiled_xc(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
+                             const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, T* dfine, T ih2c,
+                             const T* eta_c, T* sigma_c, hipStream_t s, char* err)
 {
-    auto kern = k_defect_restrict_tiled<T, M, SIG, FW>;
+    constexpr bool SIGC = !FW;
+    using G = RestrictTile<XC, SIGC>;
+    auto kern = k_defect_restrict_tiled<T, M, SIG, FW, SIGC, XC>;
+    constexpr int lds = restrict_tiled_lds_bytes<T, M, SIGC>();
     static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
     HIP_TRY(err, ensure_dynamic_lds((const void*)kern, lds, lds_done));
+    const int blocks = (nf / G::TZ) * (nf / G::TY) * ((nf / 2) / G::XC);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), lds, s, m, nf, ih2f, phi_f, eta_f,
-                       sigma_f, phi_c, phihat_c, rr_c, dfine);
+                       sigma_f, phi_c, phihat_c, rr_c, dfine, ih2c, eta_c, sigma_c);
     LAUNCH_CHECK(err, "k_defect_restrict_tiled");
     return ISIS_OK;
 }
 
+template <class T, class M, bool SIG, bool FW>
+int launch_restrict_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
+                          const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, T* dfine, T ih2c,
+                          const T* eta_c, T* sigma_c, hipStream_t s, char* err)
+{
+    if (nf >= 256)
+        return launch_restrict_tiled_xc<T, M, SIG, FW, 8>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c,
+                                                          phihat_c, rr_c, dfine, ih2c, eta_c,
+                                                          sigma_c, s, err);
+    if (nf == 128)
+        return launch_restrict_tiled_xc<T, M, SIG, FW, 4>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c,
+                                                          phihat_c, rr_c, dfine, ih2c, eta_c,
+                                                          sigma_c, s, err);
+    return launch_restrict_tiled_xc<T, M, SIG, FW, 2>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c,
+                                                      phihat_c, rr_c, dfine, ih2c, eta_c, sigma_c,
+                                                      s, err);
+}
+
 // FAS descent with the full-weighting restriction in one pass (single
-// precision, tiled levels): XC = 16 coarse planes per workgroup at 512^3 and
-// above, 8 below (enough workgroups to fill the device at 256^3).
+// precision, tiled levels).  XC coarse planes per workgroup: 16 at 512^3 and
+// above, 8 at 256^3 (enough workgroups to fill the device), and 4 or 2 below,
+// where the few tiles of a level would otherwise leave most of the device
+// idle while each workgroup steps through its planes.
 template <class T, class M, bool SIG, int XC>
 int launch_defect_fw_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
-                           const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, hipStream_t s,
-                           char* err)
+                           const T* sigma_f, T* phi_c, T* phihat_c, T ih2c, const T* eta_c,
+                           T* sigma_c, hipStream_t s, char* err)
 {
     using G = DefectFwTile<XC>;
     auto kern = k_defect_restrict_fw_tiled<T, M, SIG, XC>;
@@ -355,25 +383,41 @@ int launch_defect_fw_tiled(const M& m, int nf, T ih2f, const T* phi_f, const T* 
     HIP_TRY(err, ensure_dynamic_lds((const void*)kern, lds, lds_done));
     const int blocks = (nf / G::TZ) * (nf / G::TY) * ((nf / 2) / XC);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), lds, s, m, nf, ih2f, phi_f, eta_f,
-                       sigma_f, phi_c, phihat_c, rr_c);
+                       sigma_f, phi_c, phihat_c, ih2c, eta_c, sigma_c);
     LAUNCH_CHECK(err, "k_defect_restrict_fw_tiled");
     return ISIS_OK;
 }
 
+template <class T, class M, int XC>
+int launch_defect_fw_xc(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
+                        const T* sigma_f, T* phi_c, T* phihat_c, T ih2c, const T* eta_c,
+                        T* sigma_c, hipStream_t s, char* err)
+{
+    return sigma_f ? launch_defect_fw_tiled<T, M, true, XC>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                            phi_c, phihat_c, ih2c, eta_c, sigma_c,
+                                                            s, err)
+                   : launch_defect_fw_tiled<T, M, false, XC>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                             phi_c, phihat_c, ih2c, eta_c,
+                                                             sigma_c, s, err);
+}
+
+// nf: a power of two >= 64
 template <class T, class M>
 int launch_defect_fw(const M& m, int nf, T ih2f, const T* phi_f, const T* eta_f,
-                     const T* sigma_f, T* phi_c, T* phihat_c, T* rr_c, hipStream_t s, char* err)
+                     const T* sigma_f, T* phi_c, T* phihat_c, T ih2c, const T* eta_c, T* sigma_c,
+                     hipStream_t s, char* err)
 {
     if (nf >= 512)
-        return sigma_f ? launch_defect_fw_tiled<T, M, true, 16>(m, nf, ih2f, phi_f, eta_f, sigma_f,
-                                                                phi_c, phihat_c, rr_c, s, err)
-                       : launch_defect_fw_tiled<T, M, false, 16>(m, nf, ih2f, phi_f, eta_f,
-                                                                 sigma_f, phi_c, phihat_c, rr_c,
-                                                                 s, err);
-    return sigma_f ? launch_defect_fw_tiled<T, M, true, 8>(m, nf, ih2f, phi_f, eta_f, sigma_f,
-                                                           phi_c, phihat_c, rr_c, s, err)
-                   : launch_defect_fw_tiled<T, M, false, 8>(m, nf, ih2f, phi_f, eta_f, sigma_f,
-                                                            phi_c, phihat_c, rr_c, s, err);
+        return launch_defect_fw_xc<T, M, 16>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c,
+                                             ih2c, eta_c, sigma_c, s, err);
+    if (nf == 256)
+        return launch_defect_fw_xc<T, M, 8>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c,
+                                            ih2c, eta_c, sigma_c, s, err);
+    if (nf == 128)
+        return launch_defect_fw_xc<T, M, 4>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c,
+                                            ih2c, eta_c, sigma_c, s, err);
+    return launch_defect_fw_xc<T, M, 2>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c, ih2c,
+                                        eta_c, sigma_c, s, err);
 }
 
 // coarse = full-weighting restriction of an nf^3 fine field (nf even >= 4).
@@ -395,7 +439,9 @@ int launch_restrict_fw(int nf, const T* fine, T* coarse, hipStream_t s, char* er
 // The FAS descent.  dfine: NULL for the 8-child mean of the defect; else full
 // weighting, in one pass on single-precision tiled levels, elsewhere through
 // dfine, an nf^3 scratch field that receives the fine defect, which is then
-// restricted.
+// restricted.  On tiled levels with the mean, and with full weighting in one
+// pass, the descent kernel also computes the coarse source sigma_c; the other
+// paths restrict the defect to rr_c and finish with k_fas_sigma.
 template <class T, class M>
 int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f,
                    const T* sigma_f, const T* eta_c, T* phi_c, T* phihat_c, T* sigma_c, T* rr_c,
@@ -406,38 +452,31 @@ int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f
     T ih2f = (T)(1.0 / (hf * hf));
     double hc = 2.0 * hf;
     T ih2c = (T)(1.0 / (hc * hc));
-    using RG = RestrictTileF;
+    using RG = RestrictTile<8, false>;  // the tile (every chunk length divides nc here)
     const bool tiled =
         (nf & (nf - 1)) == 0 && nf % RG::TZ == 0 && nf % RG::TY == 0 && nc % RG::XC == 0;
     if constexpr (sizeof(T) == 4) {
-        if (dfine && tiled) {  // single pass; dfine is not needed
-            int r = launch_defect_fw<T, M>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c,
-                                           rr_c, s, err);
-            if (r) return r;
-            hipLaunchKernelGGL((k_fas_sigma<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s, m, nc,
-                               ih2c, phi_c, eta_c, rr_c, sigma_c);
-            LAUNCH_CHECK(err, "k_fas_sigma");
-            return ISIS_OK;
-        }
+        if (dfine && tiled)  // single pass; dfine is not needed
+            return launch_defect_fw<T, M>(m, nf, ih2f, phi_f, eta_f, sigma_f, phi_c, phihat_c,
+                                          ih2c, eta_c, sigma_c, s, err);
     }
+    if (tiled && !dfine)
+        return sigma_f ? launch_restrict_tiled<T, M, true, false>(m, nf, ih2f, phi_f, eta_f,
+                                                                  sigma_f, phi_c, phihat_c, rr_c,
+                                                                  nullptr, ih2c, eta_c, sigma_c,
+                                                                  s, err)
+                       : launch_restrict_tiled<T, M, false, false>(m, nf, ih2f, phi_f, eta_f,
+                                                                   sigma_f, phi_c, phihat_c, rr_c,
+                                                                   nullptr, ih2c, eta_c, sigma_c,
+                                                                   s, err);
     if (tiled) {
-        const int blocks = (nf / RG::TZ) * (nf / RG::TY) * (nc / RG::XC);
-        constexpr int lds = restrict_tiled_lds_bytes<T, M>();
-        int r;
-        if (dfine)
-            r = sigma_f ? launch_restrict_tiled<T, M, true, true>(m, nf, ih2f, phi_f, eta_f, sigma_f,
-                                                                  phi_c, phihat_c, rr_c, dfine,
-                                                                  blocks, lds, s, err)
-                        : launch_restrict_tiled<T, M, false, true>(m, nf, ih2f, phi_f, eta_f,
-                                                                   sigma_f, phi_c, phihat_c, rr_c,
-                                                                   dfine, blocks, lds, s, err);
-        else
-            r = sigma_f ? launch_restrict_tiled<T, M, true, false>(m, nf, ih2f, phi_f, eta_f,
-                                                                   sigma_f, phi_c, phihat_c, rr_c,
-                                                                   nullptr, blocks, lds, s, err)
-                        : launch_restrict_tiled<T, M, false, false>(m, nf, ih2f, phi_f, eta_f,
-                                                                    sigma_f, phi_c, phihat_c, rr_c,
-                                                                    nullptr, blocks, lds, s, err);
+        const int r =
+            sigma_f ? launch_restrict_tiled<T, M, true, true>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                              phi_c, phihat_c, rr_c, dfine, ih2c,
+                                                              eta_c, sigma_c, s, err)
+                    : launch_restrict_tiled<T, M, false, true>(m, nf, ih2f, phi_f, eta_f, sigma_f,
+                                                               phi_c, phihat_c, rr_c, dfine, ih2c,
+                                                               eta_c, sigma_c, s, err);
         if (r) return r;
     } else if (nf >= 4) {
         hipLaunchKernelGGL((k_defect_restrict_pairs<T, M>), dim3(grid_for(c3)), dim3(kBlock), 0, s,

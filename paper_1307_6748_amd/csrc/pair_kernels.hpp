@@ -5,6 +5,7 @@
 // per-cell kernels in kernels.hpp compute, in the same summation order, with
 // about a third of the load instructions.  Fine sides must be even and >= 4.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -185,47 +186,72 @@ __global__ __launch_bounds__(kBlock) void k_prolong_pairs(int nf, T* __restrict_
     }
 }
 
-// FAS descent, first half (see k_defect_restrict), LDS-staged: each workgroup
-// owns a 16 x 64 tile of fine (y, z) cells -- 8 x 32 coarse cells, one per
-// thread -- and streams along x over XC coarse planes.  Fine planes pass
-// through a ring of four (2I-1 .. 2I+2 for coarse plane I; two new ones per
-// step), with e^phi beside them for staged models, so each fine value is read
-// from HBM about 1.2 times and each exponential computed about 1.2 times per
-// fine cell.  The 8 children are summed in the order of k_defect_restrict.
-template <int XC_>
+// FAS descent (see k_defect_restrict), LDS-staged: each workgroup owns a
+// 16 x 64 tile of fine (y, z) cells -- 8 x 32 coarse cells, one per thread --
+// and streams along x over XC coarse planes.  Fine planes pass through a ring
+// of four (2I-1 .. 2I+2 for coarse plane I; two new ones per step), with e^phi
+// beside them for staged models, so each fine value is read from HBM about 1.2
+// times and each exponential computed about 1.2 times per fine cell.  The 8
+// children are summed in the order of k_defect_restrict.
+//
+// SIGC: the coarse FAS source sigma_c = L_c(phi_c) - rr_c is computed here
+// too, one coarse plane behind, instead of by k_fas_sigma (same operator call
+// on the same values, so the same result), and rr_c is not stored.  The mean
+// of plane I is kept in LDS on the tile and a one-cell ring around it (two
+// slots, planes I-1 and I), which needs fine rows y0-2 .. y0+17 in the ring;
+// the x-neighbours come from registers.  The mean of plane I0-1 (first plane's
+// x-neighbour) and of plane I0+XC (last plane's) are summed from HBM.
+template <int XC_, bool SIGC_ = false>
 struct RestrictTile {
     static constexpr int TY = 16, TZ = 64, XC = XC_, NT = kBlock;  // fine tile; XC coarse planes
-    static constexpr int EY = TY + 2;          // fine rows y0-1 .. y0+16
+    static constexpr int YH = SIGC_ ? 2 : 1;   // fine halo rows
+    static constexpr int EY = TY + 2 * YH;     // fine rows y0-YH .. y0+15+YH
     static constexpr int EZ = TZ + 4;          // fine columns z0-2 .. z0+65 (pairs aligned)
     static constexpr int NP = EZ / 2;
     static constexpr int PAIRS = EY * NP;
     static constexpr int LPT = (PAIRS + NT - 1) / NT;
     static constexpr int PLANE = EY * EZ;
+    // coarse plane (SIGC): rows -1 .. 8, columns -1 .. 32 of the coarse tile
+    static constexpr int CY = TY / 2 + 2, CZ = TZ / 2 + 2, CPL = CY * CZ;
+    static constexpr int CRING = 2 * CZ + 2 * (CY - 2);
     static_assert((TY / 2) * (TZ / 2) == NT, "one coarse cell per thread");
+    static_assert(CRING <= NT, "one coarse ring cell per thread");
 };
-using RestrictTileF = RestrictTile<8>;
-
-template <class T, class M>
+template <class T, class M, bool SIGC>
 constexpr int restrict_tiled_lds_bytes()
 {
-    return 4 * RestrictTileF::PLANE * (int)sizeof(T) * (StageOp<T, M>::kStaged ? 2 : 1);
+    using G = RestrictTile<8, SIGC>;  // the same for every XC
+    return (4 * G::PLANE * (StageOp<T, M>::kStaged ? 2 : 1) + (SIGC ? 2 * G::CPL : 0)) *
+           (int)sizeof(T);
 }
 
 // FW: the fine defect L - sigma goes to dfine (full-weighting restriction of
 // the defect follows in k_restrict_fw_tiled) instead of its mean to rr_c.
-template <class T, class M, bool SIG, bool FW = false>
-__global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
+// SIGC (not with FW): sigma_c (coarse density eta_c, 1/h_c^2 = ih2c) instead
+// of rr_c.  XC: coarse planes per workgroup.  Single-precision f(R) forms:
+// at least three waves per SIMD (at most 168 VGPRs), as many workgroups as
+// their LDS allows.
+template <class T, class M>
+constexpr int restrict_tiled_min_waves()
+{
+    return sizeof(T) == 4 && StageOp<T, M>::kStaged ? 3 : 1;
+}
+template <class T, class M, bool SIG, bool FW = false, bool SIGC = false, int XC = 8>
+__global__ __launch_bounds__(kBlock, (restrict_tiled_min_waves<T, M>())) void k_defect_restrict_tiled(
     M m, int nf, T ih2, const T* __restrict__ phi, const T* __restrict__ eta,
     const T* __restrict__ sigma, T* __restrict__ phi_c, T* __restrict__ phihat_c,
-    T* __restrict__ rr_c, T* __restrict__ dfine = nullptr)
+    T* __restrict__ rr_c, T* __restrict__ dfine = nullptr, T ih2c = T(0),
+    const T* __restrict__ eta_c = nullptr, T* __restrict__ sigma_c = nullptr)
 {
-    using G = RestrictTileF;
+    static_assert(!(FW && SIGC), "the full-weighting path restricts the defect afterwards");
+    using G = RestrictTile<XC, SIGC>;
     using V = typename Vec2<T>::type;
     using SO = StageOp<T, M>;
     constexpr bool STAGED = SO::kStaged;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* ring = reinterpret_cast<T*>(smem_raw);  // 4 fine planes of phi
     T* xring = ring + 4 * G::PLANE;            // 4 planes of e^phi (staged models)
+    T* cbuf = ring + 4 * G::PLANE * (STAGED ? 2 : 1);  // 2 coarse planes (SIGC)
     __shared__ double exptab[SO::kTable ? kExpTable : 1];
     if constexpr (SO::kTable) {
         exp_table_fill(exptab);
@@ -249,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
     for (int q = 0; q < G::LPT; ++q) {
         const int e = min(tid + q * G::NT, G::PAIRS - 1);
         const int r = e / G::NP, c2 = e - r * G::NP;
-        poff[q] = (unsigned)(((y0 - 1 + r) & msk) * nf + ((z0 - 2 + 2 * c2) & msk));
+        poff[q] = (unsigned)(((y0 - G::YH + r) & msk) * nf + ((z0 - 2 + 2 * c2) & msk));
         doff[q] = r * G::EZ + 2 * c2;
     }
     // this thread's 8 children: fine rows 2jj, 2jj+1 of the tile, columns 2kk, 2kk+1
@@ -278,13 +304,70 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
             }
         }
     };
+    // SIGC: the mean of this thread's children of coarse plane X, from HBM
+    auto hbm_mean = [&](int X) __attribute__((always_inline)) {
+        T sp = T(0);
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+            const T* pl = phi + (size_t)((2 * X + di) & msk) * nf2;
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const V c = *reinterpret_cast<const V*>(pl + (dj ? coff1 : coff0));
+                sp += c[0];
+                sp += c[1];
+            }
+        }
+        return sp / T(8);
+    };
+    // SIGC: this thread's coarse ring cell (row cr, column cq of the coarse
+    // tile, -1 .. 8 and -1 .. 32) if tid < CRING; the others take the last
+    // ring cell and store the same value there (a store under a branch let
+    // the compiler sink the defect arithmetic below it: more registers)
+    int cr, cq;
+    {
+        const int e = min(tid, G::CRING - 1);
+        if (e < G::CZ) {
+            cr = -1;
+            cq = e - 1;
+        } else if (e < 2 * G::CZ) {
+            cr = G::CY - 2;
+            cq = e - G::CZ - 1;
+        } else {
+            const int e2 = e - 2 * G::CZ;
+            cr = e2 >> 1;
+            cq = (e2 & 1) ? G::CZ - 2 : -1;
+        }
+    }
+    const int cro = (2 * cr + G::YH) * G::EZ + 2 + 2 * cq;  // fine ring offset of its child (0,0)
+    const int crb = (cr + 1) * G::CZ + cq + 1;              // coarse plane offset
+    const int cob = (jj + 1) * G::CZ + kk + 1;              // this thread's cell there
+    T pm2 = T(0), pm1 = T(0), rm1 = T(0), em1 = T(0);       // planes I-2, I-1
+    if constexpr (SIGC) pm1 = hbm_mean(I0 - 1);
     // prologue: fine planes 2I0-1, 2I0 in LDS, 2I0+1, 2I0+2 in registers
     load2(2 * I0 - 1);
     deposit1(2 * I0 - 1, ra);
     deposit1(2 * I0, rb);
     load2(2 * I0 + 1);
-    const int o00 = (2 * jj + 1) * G::EZ + 2 + 2 * kk;  // LDS offset of child (row 2jj, col 2kk)
-    for (int I = I0; I < I0 + G::XC; ++I) {
+    const int o00 = (2 * jj + G::YH) * G::EZ + 2 + 2 * kk;  // LDS offset of child (row 2jj, col 2kk)
+    // sigma_c of coarse plane X from the buffered plane X and its x-neighbours
+    auto coarse_source = [&](int X, T pxm, T pc, T pxp, T ec, T rr)
+        __attribute__((always_inline)) {
+        const T* cb = cbuf + (X & 1) * G::CPL;
+        T nbv[6];
+        nbv[0] = pxm;
+        nbv[1] = pxp;
+        nbv[2] = cb[cob - G::CZ];
+        nbv[3] = cb[cob + G::CZ];
+        nbv[4] = cb[cob - 1];
+        nbv[5] = cb[cob + 1];
+        T L, D;
+        m.op(pc, nbv, ec, ih2c, L, D);
+        sigma_c[((size_t)(X & (nc - 1)) * nc + (y0 / 2 + jj)) * nc + z0 / 2 + kk] = L - rr;
+    };
+    // one coarse plane; SRC: also the source of plane I-1 (a compile-time
+    // flag rather than a branch, for the same reason)
+    auto step = [&](int I, auto src) __attribute__((always_inline)) {
+        constexpr bool SRC = decltype(src)::value;
         deposit1(2 * I + 1, ra);
         deposit1(2 * I + 2, rb);
         // this step's densities (and sources), then the next two planes
@@ -301,8 +384,26 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
                 s2[di][0] = s2[di][1] = V{T(0), T(0)};
             }
         }
+        T ec = T(0);
+        if constexpr (SIGC) ec = eta_c[((size_t)I * nc + (y0 / 2 + jj)) * nc + z0 / 2 + kk];
         load2(min(2 * I + 3, 2 * (I0 + G::XC) - 1));  // clamped: branch-free
         __syncthreads();
+        if constexpr (SIGC && SRC) {
+            // plane I-1's source first: its operator's branches then cannot
+            // draw the defects' arithmetic below them (more live registers)
+            T pn = T(0);
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+                const T* cu = ring + ((2 * I + di) & 3) * G::PLANE;
+#pragma unroll
+                for (int dj = 0; dj < 2; ++dj) {
+                    const V c = *reinterpret_cast<const V*>(cu + o00 + dj * G::EZ);
+                    pn += c[0];
+                    pn += c[1];
+                }
+            }
+            coarse_source(I - 1, pm2, pm1, pn / T(8), em1, rm1);
+        }
         T sr = T(0), sp = T(0);
 #pragma unroll
         for (int di = 0; di < 2; ++di) {
@@ -323,10 +424,10 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
                 const V ym = *reinterpret_cast<const V*>(cu + o - G::EZ);
                 const V yp = *reinterpret_cast<const V*>(cu + o + G::EZ);
                 const T zm = cu[o - 1], zp = cu[o + 2];
-                V ec, exm, exq, eym, eyp;
+                V ec2, exm, exq, eym, eyp;
                 T ezm = T(0), ezp = T(0);
                 if constexpr (STAGED) {
-                    ec = *reinterpret_cast<const V*>(ecu + o);
+                    ec2 = *reinterpret_cast<const V*>(ecu + o);
                     exm = *reinterpret_cast<const V*>(epv + o);
                     exq = *reinterpret_cast<const V*>(enx + o);
                     eym = *reinterpret_cast<const V*>(ecu + o - G::EZ);
@@ -350,9 +451,9 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
                         enb[1] = exq[dk];
                         enb[2] = eym[dk];
                         enb[3] = eyp[dk];
-                        enb[4] = dk ? ec[0] : ezm;
-                        enb[5] = dk ? ezp : ec[1];
-                        SO::eval(m, c[dk], nbv, ec[dk], enb, e2[di][dj][dk], ih2, L, D);
+                        enb[4] = dk ? ec2[0] : ezm;
+                        enb[5] = dk ? ezp : ec2[1];
+                        SO::eval(m, c[dk], nbv, ec2[dk], enb, e2[di][dj][dk], ih2, L, D);
                     } else {
                         m.op(c[dk], nbv, e2[di][dj][dk], ih2, L, D);
                     }
@@ -369,9 +470,34 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_tiled(
         const T pc = sp / T(8);
         phi_c[q] = pc;
         phihat_c[q] = pc;
-        if constexpr (!FW) rr_c[q] = sr / T(8);
+        if constexpr (!FW && !SIGC) rr_c[q] = sr / T(8);
+        if constexpr (SIGC) {
+            // plane I into its slot (free: plane I-2's source was computed
+            // before the previous step's closing barrier), then plane I-1's source
+            T* cb = cbuf + (I & 1) * G::CPL;
+            cb[cob] = pc;
+            T hp = T(0);
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+                const T* cu = ring + ((2 * I + di) & 3) * G::PLANE;
+#pragma unroll
+                for (int dj = 0; dj < 2; ++dj) {
+                    const V c = *reinterpret_cast<const V*>(cu + cro + dj * G::EZ);
+                    hp += c[0];
+                    hp += c[1];
+                }
+            }
+            cb[crb] = hp / T(8);
+            pm2 = pm1;
+            pm1 = pc;
+            rm1 = sr / T(8);
+            em1 = ec;
+        }
         __syncthreads();  // the slots of planes 2I-1, 2I are refilled next
-    }
+    };
+    step(I0, std::false_type{});
+    for (int I = I0 + 1; I < I0 + G::XC; ++I) step(I, std::true_type{});
+    if constexpr (SIGC) coarse_source(I0 + G::XC - 1, pm2, pm1, hbm_mean(I0 + G::XC), em1, rm1);
 }
 
 // fine += P(coarse - coarse_hat), LDS-staged: each workgroup owns a TJ x TK

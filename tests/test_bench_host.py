@@ -117,6 +117,14 @@ def test_solve_bytes_counts_every_kernel_once():
     st32.restriction = 1
     got = bench.solve_bytes(128, st32, 0, (2, 2), True)
     assert abs(got - mean - 2 * 4 * (32 ** 3 + 16 ** 3 + 8 ** 3)) <= 1e-9 * got
+    # tiled descents (sides >= 64) write Sigma_c themselves: only eta_c is
+    # read for it, instead of the coarse source's 4 values per coarse cell
+    c64 = 64 ** 3
+    lvl = c64 * 8 * (4 * 4 + (3 + 3 / 8) + 1 / 8 + 2 / 8 + 2)
+    assert abs(bench.level_bytes(64, 8, 4, True, False, False) - lvl) <= 1e-9 * lvl
+    assert abs(bench.level_bytes(64, 8, 4, True, True, False)
+               - (lvl + c64 * 8 * (2 + 3 / 8))) <= 1e-9 * lvl    # FP64 full weighting: two passes
+    assert abs(bench.level_bytes(64, 4, 4, True, True, False) - lvl / 2) <= 1e-9 * lvl
     # the fused sweep levels (>= 256^3, temporal block >= 1) apply the
     # correction inside the first post-smoothing pass: no pass of its own
     st512 = types.SimpleNamespace(cycles=1, cycles_fp32=1, restriction=0, judged_cycles=1)

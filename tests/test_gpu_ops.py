@@ -79,12 +79,15 @@ def test_prolong_correct(orc, n):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("n", [4, 12, 32, 64])
+@pytest.mark.parametrize("n", [4, 12, 32, 64, 128])
 @pytest.mark.parametrize("with_sigma", [False, True])
 @pytest.mark.parametrize("fw", [False, True])
 def test_fas_descend(orc, name, n, with_sigma, fw):
     """phi_c = phihat_c = R phi_f; sigma_c = L_c(R phi_f) - R'(L_f(phi_f) - sigma_f),
-    R' the 8-child mean or full weighting."""
+    R' the 8-child mean or full weighting.  At 64 and 128 the mean takes the
+    LDS-tiled descent (2 and 4 coarse planes per workgroup), which forms
+    sigma_c itself, one coarse plane behind, with the x-neighbours' means of
+    the first and last plane of each workgroup summed from HBM."""
     from paper_1307_6748_amd import solver as S
     om, sp, a = models(name)
     h = 0.9

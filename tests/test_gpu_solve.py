@@ -249,8 +249,10 @@ def test_mixed_fp32_cycles_other_restriction(orc, name, n):
     chameleon (on the tiled FP32 levels, 64^3 and up, the single-pass defect
     + full-weighting kernel; its evaluation of the defect on the tile's
     one-cell ring and the x filter across steps must match the oracle's full
-    weighting; 16 coarse planes per workgroup at 512^3, 8 below), the
-    8-child mean for f(R)."""
+    weighting, and the coarse source it forms in the same step the oracle's
+    Sigma; 16 coarse planes per workgroup at 512^3, 8 at 256^3, 4 at 128^3, 2
+    at 64^3), the 8-child mean for f(R) (its tiled descent forms Sigma one
+    coarse plane behind, from the means it keeps in LDS)."""
     from paper_1307_6748_amd import synth
     om, sp, a = models(name)
     box = 4.0 * n
