@@ -58,6 +58,32 @@ struct FusedGeom {
     static constexpr int MAXI = (items(1) + NT - 1) / NT;
 };
 
+// Work item `it` of a region of R rows of L items each (cells of one colour,
+// or column pairs).  SPLIT: the first R * M items, M = L rounded down to a
+// multiple of 32, take rows whole, M per row, so every 32-lane half of a wave
+// covers 32 consecutive items of one row; the L - M items left over at the
+// end of each row follow, row by row.  With the colour-split rows in LDS a
+// half-wave then reads 32 consecutive words, which LDS serves without bank
+// conflicts; in plain row-major order half-waves straddle two rows whose
+// words share banks (33 or 34 items per row: about 1.5 conflict cycles per
+// LDS access, 0.16 split).  The split order pays for f(R), whose stages read
+// two LDS rings (its sweep 2 % faster, 4 % with the prolongation fused in);
+// the symmetron's HBM-bound passes measured 1 % slower with it (the leftover
+// items' density loads scatter over many rows), so they keep row-major order.
+template <bool SPLIT>
+__device__ __forceinline__ void row_split(int it, int R, int L, int& r, int& c)
+{
+    const int M = SPLIT ? L & ~31 : 0, E = L - M;
+    if (SPLIT && it < R * M) {
+        r = it / M;
+        c = it - r * M;
+    } else {
+        const int j = it - R * M;
+        r = j / E;
+        c = M + (j - r * E);
+    }
+}
+
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F&& f)
@@ -151,8 +177,8 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
     auto stage_valid = [&](int p, int k) __attribute__((always_inline)) { return p >= sbeg + k && p <= send - k; };
     // Plane row r, column c of a plane in LDS.  Rows are stored colour-split
     // (even columns, then odd columns): the cells one stage updates have one
-    // column parity per row, so consecutive lanes touch consecutive words and
-    // the LDS accesses are free of bank conflicts.
+    // column parity per row, so consecutive lanes of a row touch consecutive
+    // words (and for f(R) row_split keeps each half-wave within one row).
     auto lds = [&](int r, int c) __attribute__((always_inline)) {
         return r * G::EZ + (c & 1) * G::HZ + (c >> 1);
     };
@@ -165,7 +191,8 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
 #pragma unroll
     for (int q = 0; q < G::LPT; ++q) {
         const int it = min(tid + q * NT, G::PAIRS - 1);
-        const int r = it / G::NP, cp = it - r * G::NP;
+        int r, cp;
+        row_split<STAGED>(it, G::EY, G::NP, r, cp);
         poff[q] = (unsigned)((((y0 - G::H + r) & msk) * n + ((z0 - G::H + 2 * cp) & msk)) * SZ);
         doff[q] = r * G::EZ + cp;
     }
@@ -187,7 +214,8 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
         static_for<0, G::ipt(k)>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const int it = min(tid + q * NT, G::items(k) - 1);
-            const int rr = it / pairs, cp = it - rr * pairs;
+            int rr, cp;
+            row_split<STAGED>(it, G::EY - 2 * k, pairs, rr, cp);
             const int r = k + rr;
 #pragma unroll
             for (int pb = 0; pb < 2; ++pb) {
