@@ -161,8 +161,8 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const bf16_t* __restrict__ x
 // taps at a time: lane g = lane / 16 takes channel half g & 1 of tap 2p + (g
 // >> 1), so the 16 lanes of one (half, tap) group read 256 contiguous bytes
 // (a voxel-major layout put lanes m, m+4, m+8, m+12 on one bank).  The 27th
-// tap runs on the 16x16x16 MFMA, reading 4-channel (8-byte) quarters of the
-// same arrays.  Tiles are dealt to the 8 XCDs in contiguous ranges with x
+// tap is a 14th pair whose second half is zero, so every product runs on the
+// 16x16x32 MFMA.  Tiles are dealt to the 8 XCDs in contiguous ranges with x
 // fastest, so neighbouring planes share an L2.
 constexpr int kLY = 4, kLZ = 64;                   // output tile (y, z)
 constexpr int kLPY = kLY + 2, kLPZ = kLZ + 2;      // with the halo
