@@ -33,6 +33,9 @@
  *       Option (orc_cfg.restrict_fw): the defect is restricted by full
  *       weighting, the adjoint of P over 8 (weights 1, 3, 3, 1 over 8 per
  *       axis on the 4 fine cells 2I-1 .. 2I+2); phi and rho keep the mean.
+ *       Option (orc_cfg.prolong_w, flux-form models): P weighted by the
+ *       coefficient b = e^u of the restricted field, see
+ *       orc_prolong_correct_w.
  *   R3  The non-canonical operator carries the 1/h^2 that its Jacobian has.
  *   R4  The db/du term of the Jacobian carries the factor 1/2 that follows
  *       from differentiating the arithmetic face average.
@@ -111,6 +114,8 @@ typedef struct {
 typedef struct {
     int nu_pre, nu_post, nu_coarse, max_cycles;
     int restrict_fw; /* 1: full-weighting restriction of the defect (reading R2) */
+    int prolong_w;   /* 1: coefficient-weighted prolongation (reading R2; f(R),
+                        chameleon: b = e^u of coarse_hat)                          */
 } orc_cfg;
 
 typedef struct {
@@ -410,6 +415,54 @@ void orc_prolong_correct(int n_fine, double* fine, const double* coarse, const d
             }
 }
 
+/* fine += P_b(coarse - coarse_hat): the same stencil with weights taken from
+ * the flux coefficient b = e^{coarse_hat} of the flux-form operators (Sec.
+ * 3.4), an option of reading R2.  Along each axis the correction is taken to
+ * vary linearly in the "resistance" integral of 1/b, with b constant over
+ * each coarse cell: the fine centre lies a quarter coarse spacing from its
+ * parent P (coefficient b_P) and, towards the other coarse centre N, a further
+ * quarter in P and a half in N (coefficient b_N), so its weight on N is
+ * (1/(4 b_P)) / (1/(2 b_P) + 1/(2 b_N)) = b_N / (2 (b_P + b_N)), and 1 minus
+ * that on P; this keeps the flux b de/dx continuous across the face between
+ * P and N.  The three axes' weights come from P and its neighbour along each
+ * axis and multiply as in the trilinear stencil.  With b uniform the weights
+ * are 3/4 and 1/4: the trilinear prolongation.  The weight is evaluated as
+ * 1 / (2 (1 + e^{u_P - u_N})), which needs only the difference of the two
+ * values and tends to 0 or 1/2 instead of overflowing. */
+void orc_prolong_correct_w(int n_fine, double* fine, const double* coarse, const double* coarse_hat)
+{
+    long nf = n_fine, nc = n_fine / 2;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nf; ++i)
+        for (long j = 0; j < nf; ++j)
+            for (long k = 0; k < nf; ++k) {
+                long I[2], J[2], K[2];
+                I[0] = i / 2;
+                I[1] = wrap(I[0] + ((i & 1) ? 1 : -1), nc);
+                J[0] = j / 2;
+                J[1] = wrap(J[0] + ((j & 1) ? 1 : -1), nc);
+                K[0] = k / 2;
+                K[1] = wrap(K[0] + ((k & 1) ? 1 : -1), nc);
+                const double up = coarse_hat[cidx(nc, I[0], J[0], K[0])];
+                const double un[3] = {coarse_hat[cidx(nc, I[1], J[0], K[0])],
+                                      coarse_hat[cidx(nc, I[0], J[1], K[0])],
+                                      coarse_hat[cidx(nc, I[0], J[0], K[1])]};
+                double w[3][2];
+                for (int ax = 0; ax < 3; ++ax) {
+                    w[ax][1] = 1.0 / (2.0 * (1.0 + exp(up - un[ax])));
+                    w[ax][0] = 1.0 - w[ax][1];
+                }
+                double s = 0.0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        for (int c = 0; c < 2; ++c) {
+                            long q = cidx(nc, I[a], J[b], K[c]);
+                            s += w[0][a] * w[1][b] * w[2][c] * (coarse[q] - coarse_hat[q]);
+                        }
+                fine[cidx(nf, i, j, k)] += s;
+            }
+}
+
 /* ------------------------------------------------------------------ */
 /* Cold start and norms.                                               */
 /* ------------------------------------------------------------------ */
@@ -521,7 +574,10 @@ static void vcycle(const orc_model* m, const orc_cfg* cfg, orc_level* lv, int l,
     vcycle(m, cfg, lv, l + 1, nlev);
 
     /* phi_l += P(phi_{l+1} - phihat_{l+1}) */
-    orc_prolong_correct(f->n, f->phi, c->phi, c->phihat);
+    if (cfg->prolong_w && (m->model == ORC_FR_HS || m->model == ORC_CHAMELEON))
+        orc_prolong_correct_w(f->n, f->phi, c->phi, c->phihat);
+    else
+        orc_prolong_correct(f->n, f->phi, c->phi, c->phihat);
     for (int s = 0; s < cfg->nu_post; ++s) orc_sweep(m, f->n, f->h, f->phi, f->eta, f->sigma);
 }
 

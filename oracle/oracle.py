@@ -54,7 +54,7 @@ class _Model(C.Structure):
 
 class _Cfg(C.Structure):
     _fields_ = [("nu_pre", C.c_int), ("nu_post", C.c_int), ("nu_coarse", C.c_int),
-                ("max_cycles", C.c_int), ("restrict_fw", C.c_int)]
+                ("max_cycles", C.c_int), ("restrict_fw", C.c_int), ("prolong_w", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -98,13 +98,20 @@ class Cfg:
     max_cycles: int = 50
     # restriction of the defect: False = mean of the 8 children, True = full
     # weighting; None = per model, the choice the GPU library makes by
-    # default (full weighting for f(R), where it takes fewer V-cycles)
+    # default (full weighting only for f(R) with the trilinear prolongation)
     restrict_fw: bool | None = None
+    # prolongation: False = trilinear, True = weighted by b = e^u (flux-form
+    # models; see orc_prolong_correct_w); None = per model, the GPU
+    # library's default (weighted for f(R), where it takes fewer V-cycles)
+    prolong_w: bool | None = None
 
     def _c(self, model: int = SYMMETRON) -> _Cfg:
-        fw = (model == FR_HS) if self.restrict_fw is None else bool(self.restrict_fw)
+        pw = (model == FR_HS) if self.prolong_w is None else bool(self.prolong_w)
+        if model not in (FR_HS, CHAMELEON):
+            pw = False
+        fw = (model == FR_HS and not pw) if self.restrict_fw is None else bool(self.restrict_fw)
         post = (1 if model in (SYMMETRON, CHAMELEON) else 2) if self.nu_post is None else self.nu_post
-        return _Cfg(self.nu_pre, post, self.nu_coarse, self.max_cycles, int(fw))
+        return _Cfg(self.nu_pre, post, self.nu_coarse, self.max_cycles, int(fw), int(pw))
 
 
 @dataclass
@@ -140,6 +147,7 @@ def lib():
         L.orc_restrict.argtypes = [C.c_int, dp, dp]
         L.orc_restrict_fw.argtypes = [C.c_int, dp, dp]
         L.orc_prolong_correct.argtypes = [C.c_int, dp, dp, dp]
+        L.orc_prolong_correct_w.argtypes = [C.c_int, dp, dp, dp]
         L.orc_cold_start.argtypes = [C.POINTER(_Model), C.c_long, dp, dp]
         L.orc_rms.argtypes = [C.c_int, dp]
         L.orc_rms.restype = C.c_double
@@ -264,6 +272,13 @@ def prolong_correct(fine, coarse, coarse_hat) -> np.ndarray:
     return out
 
 
+def prolong_correct_w(fine, coarse, coarse_hat) -> np.ndarray:
+    """fine + P_b(coarse - coarse_hat), weights from b = e^coarse_hat."""
+    out = _f64(fine).copy()
+    lib().orc_prolong_correct_w(out.shape[0], out, _f64(coarse), _f64(coarse_hat))
+    return out
+
+
 def cold_start(m: Model, eta) -> np.ndarray:
     eta = _f64(eta)
     out = np.empty_like(eta)
@@ -354,5 +369,5 @@ def solve(m: Model, eta, box: float, tol: float = 1e-10, phi0=None, cfg: Cfg | N
 def vcycles(m: Model, eta, box: float, phi0, k: int, cfg: Cfg | None = None) -> Result:
     """Exactly k V-cycles from phi0 (no stop test)."""
     cfg = cfg or Cfg()
-    c2 = Cfg(cfg.nu_pre, cfg.nu_post, cfg.nu_coarse, k, cfg.restrict_fw)
+    c2 = Cfg(cfg.nu_pre, cfg.nu_post, cfg.nu_coarse, k, cfg.restrict_fw, cfg.prolong_w)
     return solve(m, eta, box, tol=0.0, phi0=phi0, cfg=c2)

@@ -19,7 +19,7 @@ typedef struct {
     int paper_u;
 } orc_model;
 typedef struct {
-    int nu_pre, nu_post, nu_coarse, max_cycles, restrict_fw;
+    int nu_pre, nu_post, nu_coarse, max_cycles, restrict_fw, prolong_w;
 } orc_cfg;
 typedef struct {
     int cycles;
@@ -36,6 +36,7 @@ void orc_halfsweep(const orc_model*, int, double, double*, const double*, const 
 void orc_restrict(int, const double*, double*);
 void orc_restrict_fw(int, const double*, double*);
 void orc_prolong_correct(int, double*, const double*, const double*);
+void orc_prolong_correct_w(int, double*, const double*, const double*);
 void orc_cold_start(const orc_model*, long, const double*, double*);
 double orc_rms(int, const double*);
 void orc_force(const orc_model*, int, double, const double*, const double*, double*, double*,
@@ -89,12 +90,13 @@ int main(void)
     double* coarse = (double*)malloc(sizeof(double) * (size_t)(n3 / 8));
     double* coarse2 = (double*)malloc(sizeof(double) * (size_t)(n3 / 8));
     for (int mi = 0; mi < 4; ++mi) {
-        for (int fw = 0; fw < 2; ++fw) {
-            orc_cfg cfg = {2, 2, 32, 40, fw};
+        for (int opt = 0; opt < 4; ++opt) {
+            const int fw = opt & 1, pw = opt >> 1;  /* pw: only the flux-form models use it */
+            orc_cfg cfg = {2, 2, 32, 40, fw, pw};
             orc_stats st;
             int rc = orc_solve(&models[mi], &cfg, n, box, eta, phi, 0, 1e-9, &st);
             if (rc != 0) {
-                printf("FAIL solve model %d fw %d: status %d\n", mi, fw, rc);
+                printf("FAIL solve model %d fw %d pw %d: status %d\n", mi, fw, pw, rc);
                 ++fails;
             }
             check_finite("solve", phi, n3);
@@ -115,6 +117,7 @@ int main(void)
     orc_restrict(n, eta, coarse);
     orc_restrict_fw(n, eta, coarse2);
     orc_prolong_correct(n, phi, coarse, coarse2);
+    orc_prolong_correct_w(n, phi, coarse, coarse2);
     check_finite("transfers", phi, n3);
     if (!(orc_rms(n, phi) > 0.0)) ++fails;
     /* masked patch operators: inside 4..11, fractional masks outside */

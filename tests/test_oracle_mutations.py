@@ -29,7 +29,15 @@ MUTATIONS = {
                            "coarse[cidx(nc, I, J, K)] = s / 7.0;"),
     "prolongation_weights_swapped": ("const double w[2] = {0.75, 0.25};",
                                      "const double w[2] = {0.25, 0.75};"),
-    "prolongation_no_phihat": ("(coarse[q] - coarse_hat[q])", "(coarse[q])"),
+    "prolongation_no_phihat": ("(coarse[q] - coarse_hat[q])", "(coarse[q])", 0),
+    # the coefficient-weighted prolongation
+    "prolongation_w_no_phihat": ("(coarse[q] - coarse_hat[q])", "(coarse[q])", 1),
+    "prolongation_w_sign": ("w[ax][1] = 1.0 / (2.0 * (1.0 + exp(up - un[ax])));",
+                            "w[ax][1] = 1.0 / (2.0 * (1.0 + exp(un[ax] - up)));"),
+    "prolongation_w_half_dropped": ("w[ax][1] = 1.0 / (2.0 * (1.0 + exp(up - un[ax])));",
+                                    "w[ax][1] = 1.0 / (1.0 + exp(up - un[ax]));"),
+    "prolongation_w_axis": ("coarse_hat[cidx(nc, I[0], J[1], K[0])],",
+                            "coarse_hat[cidx(nc, I[0], J[0], K[1])],"),
     "fas_sigma_sign": ("c->sigma[q] -= c->work[q];", "c->sigma[q] += c->work[q];"),
     "laplacian_wrong_diagonal": ("double lap = (sum - 6.0 * p) * ih2;",
                                  "double lap = (sum - 5.0 * p) * ih2;", 0),
@@ -94,7 +102,7 @@ MUTATIONS = {
                              "const double eup = m->paper_u ? m->a * m->fR0_abs * exp(field[c])"),
 }
 PIN_FILES = ["test_oracle_pins.py", "test_oracle_force.py", "test_oracle_models.py",
-             "test_oracle_newton.py", "test_oracle_amr.py"]
+             "test_oracle_newton.py", "test_oracle_amr.py", "test_oracle_prolong_w.py"]
 # The pin file that catches a mutation runs first (the suite stops at its first
 # failure); the other files follow, so every pin still gets its chance.
 FIRST_FILE = {
@@ -102,6 +110,7 @@ FIRST_FILE = {
     "chameleon_": "test_oracle_models.py",
     "paper_u_": "test_oracle_models.py",
     "amr_": "test_oracle_amr.py",
+    "prolongation_w_": "test_oracle_prolong_w.py",
 }
 
 
