@@ -20,7 +20,8 @@ solve (Newtonian potential on the same grid, force kernel) as another, and the
 model variants (chameleon, f(R) in the paper's variable) on the same density as
 a third.  Per model the whole solve is also set against the HBM roofline: the
 compulsory bytes of all its kernels (solve_bytes) over its wall time; and each
-model is solved once more with the other restriction of the defect.
+model is solved once more with the other restriction of the defect (f(R) also
+with the trilinear prolongation).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -185,8 +186,10 @@ def solve_bytes(n: int, st, tb: int, nu: tuple, mixed: bool) -> float:
             passes = -(-nu[0] // blk) + -(-nu[1] // blk)
             # the correction rides in the first post-smoothing pass when that
             # pass is a single sweep
+            # (not with the coefficient-weighted prolongation: its own kernel)
             per += level_bytes(nl, s, passes, l > 0, bool(st.restriction), l == nlev - 1,
-                               fused and nu[1] > 0 and (blk == 1 or nu[1] == 1))
+                               fused and nu[1] > 0 and (blk == 1 or nu[1] == 1)
+                               and not getattr(st, "prolongation", 0))
         b += count * per
     # the FP64 judge after the judged cycles (every cycle unless judge_skip;
     # the few FP64 cycles at the end of a mixed solve are all judged): reads
@@ -350,6 +353,7 @@ def main() -> int:
             temporal_block=st.temporal_block,
             judged_cycles=st.judged_cycles,
             restriction="full weighting" if st.restriction else "mean of 8",
+            prolongation="coefficient-weighted" if st.prolongation else "trilinear",
             cycle=f"V({st.nu_pre},{st.nu_post})",
             safeguard_hits=st.safeguard_hits,
             smoothing_s=float(np.mean([s.ms_smooth for s in sts]) / 1000.0),
@@ -384,34 +388,42 @@ def main() -> int:
             solver64.close()
             del solver64
 
-    # The restriction of the defect: the library's per-model choice (full
-    # weighting for f(R)) against the other one, same solver otherwise.
+    # The transfer operators: the library's per-model choice (the 8-child mean
+    # of the defect; the prolongation weighted by e^u for f(R), trilinear for
+    # the symmetron) against the other restriction, and for f(R) also the
+    # trilinear prolongation with full weighting (its previous choice), same
+    # solver otherwise.
     restriction_leg = None
     if not args.no_restriction_compare:
         restriction_leg = {}
+        rlab = {0: "mean of 8", 1: "full weighting"}
+        plab = {0: "trilinear", 1: "coefficient-weighted"}
         for name, (p, a) in mods.items():
-            other = 0 if rec[name][-1].restriction else 1
-            so = S.Solver(n, box, precision=args.precision, temporal_block=tb, max_cycles=100,
-                          fp32_floor=args.fp32_floor, restriction=other, judge_skip=judge_skip)
-            ph = torch.empty_like(eta)
-            so.solve(eta, p, a, TOL, phi=ph)  # warm
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, sto = so.solve(eta, p, a, TOL, phi=ph)
-            torch.cuda.synchronize()
-            t_o = time.perf_counter() - t1
-            lab = {0: "mean of 8", 1: "full weighting"}
-            restriction_leg[name] = {
-                lab[rec[name][-1].restriction]: dict(seconds=per_model[name]["seconds"],
-                                                     cycles=per_model[name]["cycles"]),
-                lab[other]: dict(seconds=t_o, cycles=sto.cycles, cycles_fp32=sto.cycles_fp32,
-                                 rho=[None if not np.isfinite(x) else x
-                                      for x in sto.rho_hist[1:]])}
-            log(f"{name} with the {lab[other]} restriction: {t_o:.4f}s, {sto.cycles} cycles "
-                f"(default {lab[rec[name][-1].restriction]}: {per_model[name]['seconds']:.4f}s, "
-                f"{per_model[name]['cycles']} cycles)")
-            so.close()
-            del so, ph
+            r0, p0 = rec[name][-1].restriction, rec[name][-1].prolongation
+            leg = {f"{rlab[r0]}, {plab[p0]}": dict(seconds=per_model[name]["seconds"],
+                                                   cycles=per_model[name]["cycles"])}
+            others = [(1 - r0, p0)] + ([(1, 0)] if p0 == 1 and r0 != 1 else [])
+            for ro_, po_ in others:
+                so = S.Solver(n, box, precision=args.precision, temporal_block=tb,
+                              max_cycles=100, fp32_floor=args.fp32_floor, restriction=ro_,
+                              prolongation=po_, judge_skip=judge_skip)
+                ph = torch.empty_like(eta)
+                so.solve(eta, p, a, TOL, phi=ph)  # warm
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, sto = so.solve(eta, p, a, TOL, phi=ph)
+                torch.cuda.synchronize()
+                t_o = time.perf_counter() - t1
+                key = f"{rlab[ro_]}, {plab[po_]}"
+                leg[key] = dict(seconds=t_o, cycles=sto.cycles, cycles_fp32=sto.cycles_fp32,
+                                rho=[None if not np.isfinite(x) else x
+                                     for x in sto.rho_hist[1:]])
+                log(f"{name} with {key}: {t_o:.4f}s, {sto.cycles} cycles (default "
+                    f"{rlab[r0]}, {plab[p0]}: {per_model[name]['seconds']:.4f}s, "
+                    f"{per_model[name]['cycles']} cycles)")
+                so.close()
+                del so, ph
+            restriction_leg[name] = leg
 
     # The step after the solve: the Newtonian potential on the same grid (the
     # Poisson equation of Sec. 3.1 as the linear model) and the total force

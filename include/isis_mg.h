@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define ISIS_MG_ABI_VERSION 3
+#define ISIS_MG_ABI_VERSION 4
 #define ISIS_MG_MAX_HIST 128
 
 typedef enum {
@@ -131,9 +131,9 @@ typedef struct {
                           weighting, the adjoint of the trilinear prolongation
                           over 8 (weights 1, 3, 3, 1 over 8 per axis; phi and
                           eta keep the mean); -1 = per model at each solve: full
-                          weighting for f(R), the mean for the others.  The
-                          converged field does not depend on it, the V-cycles'
-                          convergence factors do                              */
+                          weighting for f(R) with the trilinear prolongation,
+                          else the mean.  The converged field does not depend
+                          on it, the V-cycles' convergence factors do          */
     int judge_skip;    /* 0: the FP64 fine defect (the judge of the stop test) is
                           evaluated after every V-cycle; 1: after a judged cycle,
                           the cycles that the mean factor per cycle since the
@@ -142,6 +142,15 @@ typedef struct {
                           in a row) run without it.  The stop test is unchanged
                           (the last cycle is always judged); unjudged cycles
                           have rel_hist = NaN                                   */
+    int prolongation;  /* prolongation of the coarse-grid correction (Sec. 3.1
+                          leaves P open): 0 = cell-centred trilinear; 1 =
+                          weighted by the flux coefficient b = e^u of the
+                          flux-form operators (Sec. 3.4; f(R) and the
+                          chameleon only, else the solve returns
+                          ISIS_ERR_UNSUPPORTED; see
+                          isis_op_prolong_correct_w); -1 = per model at each
+                          solve: weighted for f(R), trilinear for the others.
+                          The converged field does not depend on it          */
 } isis_mg_desc;
 
 typedef struct {
@@ -198,6 +207,8 @@ typedef struct {
                                      fine_sweep_bytes) plus the two coarse fields,
                                      2 x (n/2)^3 values                           */
     int nu_pre, nu_post;          /* the smoothing sweeps per level the solve used */
+    int prolongation;             /* the prolongation the solve used (0 trilinear,
+                                     1 coefficient-weighted)                       */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;
@@ -345,6 +356,18 @@ int isis_op_restrict_fw(int n_fine, const double* fine, double* coarse, void* st
  * weights 27, 9, 3, 1 over 64 and periodic wrap (n_fine even >= 4). */
 int isis_op_prolong_correct(int n_fine, double* fine, const double* coarse,
                             const double* coarse_hat, void* stream);
+
+/* fine += P_b(coarse - coarse_hat): the same stencil with the weights taken
+ * from the flux coefficient b = e^{coarse_hat} of the flux-form operators
+ * (Sec. 3.4; coarse_hat in u, or in any variable that differs from u by a
+ * constant, as the paper's f(R) variable does).  Along each axis the weight
+ * of the other coarse cell N of a fine cell whose parent is P is
+ * 1 / (2 (1 + b_P / b_N)), 1/4 when b_P = b_N, and the parent takes 1 minus
+ * it: with b constant over each coarse cell and the correction linear in
+ * between, the flux b de/dx stays continuous across the face between P and N.
+ * n_fine even >= 4. */
+int isis_op_prolong_correct_w(int n_fine, double* fine, const double* coarse,
+                              const double* coarse_hat, void* stream);
 
 /* nu_c red-black sweeps on the coarsest (n = 4) grid in one workgroup. */
 int isis_op_coarse_solve(const isis_model_params* p, double a, double h, double* phi,

@@ -33,7 +33,7 @@ class DescC(C.Structure):
                 ("fp32_floor", C.c_double), ("temporal_block", C.c_int), ("stream", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("guess_accept", C.c_double), ("restriction", C.c_int),
-                ("judge_skip", C.c_int)]
+                ("judge_skip", C.c_int), ("prolongation", C.c_int)]
 
 
 class StatsC(C.Structure):
@@ -47,7 +47,8 @@ class StatsC(C.Structure):
                 ("safeguard_hits", C.c_longlong), ("ms_smooth", C.c_double),
                 ("restriction", C.c_int), ("judged_cycles", C.c_int),
                 ("fine_prol_ms", C.c_double * 2), ("fine_prol_launches", C.c_int * 2),
-                ("fine_prol_bytes", C.c_double * 2), ("nu_pre", C.c_int), ("nu_post", C.c_int)]
+                ("fine_prol_bytes", C.c_double * 2), ("nu_pre", C.c_int), ("nu_post", C.c_int),
+                ("prolongation", C.c_int)]
 
 
 _lib = None
@@ -84,6 +85,7 @@ SIGNATURES = [
     ("isis_patch_solve", _I, [C.POINTER(ModelParamsC), _D, _I, _D, _P, _P, _P, _P, _I, _I, _D,
                               _P, C.c_size_t, C.POINTER(_I), C.POINTER(_D), _P]),
     ("isis_op_prolong_correct", _I, [_I, _P, _P, _P, _P]),
+    ("isis_op_prolong_correct_w", _I, [_I, _P, _P, _P, _P]),
     ("isis_op_coarse_solve", _I, [C.POINTER(ModelParamsC), _D, _D, _P, _P, _P, _I, _P]),
     ("isis_op_cold_start", _I, [C.POINTER(ModelParamsC), _D, C.c_long, _P, _P, _P]),
     ("isis_unet_param_count", C.c_size_t, []),

@@ -6,9 +6,9 @@
 // Each phase computes per cell what the per-level kernels compute, with the
 // same terms in the same order: k_halfsweep, k_defect_restrict (or the fine
 // defect then k_restrict_fw for full weighting), k_fas_sigma,
-// k_prolong_correct and the coarsest grid's sweeps of k_coarse_solve.  Only
-// the first level's field is written back; the coarser levels' fields are
-// rebuilt by every descent.
+// k_prolong_correct (with its weights PW) and the coarsest grid's sweeps of
+// k_coarse_solve.  Only the first level's field is written back; the coarser
+// levels' fields are rebuilt by every descent.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -48,7 +48,8 @@ __host__ __device__ constexpr int bottom_lds_elems(int nlev)
     return e;
 }
 
-template <class T, class M, bool FW>
+// PW: the prolongation's weights (k_prolong_correct).
+template <class T, class M, bool FW, int PW = 0>
 __global__ __launch_bounds__(bottom_threads<T>()) void k_bottom_cycle(M m, BottomArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -226,6 +227,16 @@ __global__ __launch_bounds__(bottom_threads<T>()) void k_bottom_cycle(M m, Botto
             J[1] = (j & 1) ? wrap_inc(J[0], nc) : wrap_dec(J[0], nc);
             K[0] = k >> 1;
             K[1] = (k & 1) ? wrap_inc(K[0], nc) : wrap_dec(K[0], nc);
+            T wx[2] = {w[0], w[1]}, wy[2] = {w[0], w[1]}, wz[2] = {w[0], w[1]};
+            if constexpr (PW != 0) {
+                const T hp = ch[cell(nc, I[0], J[0], K[0])];
+                wx[1] = prolong_weight<PW>(hp, ch[cell(nc, I[1], J[0], K[0])]);
+                wy[1] = prolong_weight<PW>(hp, ch[cell(nc, I[0], J[1], K[0])]);
+                wz[1] = prolong_weight<PW>(hp, ch[cell(nc, I[0], J[0], K[1])]);
+                wx[0] = T(1) - wx[1];
+                wy[0] = T(1) - wy[1];
+                wz[0] = T(1) - wz[1];
+            }
             T s = T(0);
 #pragma unroll
             for (int aa = 0; aa < 2; ++aa)
@@ -234,7 +245,7 @@ __global__ __launch_bounds__(bottom_threads<T>()) void k_bottom_cycle(M m, Botto
 #pragma unroll
                     for (int dd = 0; dd < 2; ++dd) {
                         const long qq = cell(nc, I[aa], J[bb], K[dd]);
-                        s += w[aa] * w[bb] * w[dd] * (co[qq] - ch[qq]);
+                        s += wx[aa] * wy[bb] * wz[dd] * (co[qq] - ch[qq]);
                     }
             phi[q][c] += s;
         }

@@ -278,9 +278,22 @@ int launch_halfsweep(const M& m, int n, double h, T* phi, const T* eta, const T*
 // workgroups to hide its per-plane latency.
 constexpr int kFusedSolverMinN = 256;
 
-template <class T>
+template <class T, int PW = 0>
 int launch_prolong(int nf, T* fine, const T* coarse, const T* coarse_hat, hipStream_t s,
                    char* err);
+
+// The prolongation weights (k_prolong_correct) of the coefficient-weighted
+// option for model M in precision T: 2 for the single-precision flux-form
+// models (their field carried as w = u / ln 2), 1 for the double-precision
+// ones, 0 (trilinear) for the canonical models, which have no coefficient.
+template <class T, class M>
+constexpr int weighted_code()
+{
+    if constexpr (StageOp<T, M>::kStaged)
+        return M::kW ? 2 : 1;
+    else
+        return 0;
+}
 
 template <class T, class M>
 bool fused_level(int n, int tb, int min_fused_n = kFusedSolverMinN)
@@ -297,12 +310,19 @@ bool prolong_fused(int n, int count, int tb, int min_fused_n = kFusedSolverMinN)
 }
 
 // With cphi (and cphat, side n/2): phi += P(cphi - cphat) first, inside the
-// first fused pass where prolong_fused(), else by its own kernel.
+// first fused pass where prolong_fused(), else by its own kernel; pw: with
+// the coefficient-weighted prolongation (always its own kernel).
 template <class T, class M>
 int launch_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta, const T* sigma,
                   int count, int tb, hipStream_t s, char* err, int min_fused_n = kFusedSolverMinN,
-                  const T* cphi = nullptr, const T* cphat = nullptr)
+                  const T* cphi = nullptr, const T* cphat = nullptr, bool pw = false)
 {
+    constexpr int PWc = weighted_code<T, M>();
+    if (cphi && pw && PWc != 0) {
+        int r = launch_prolong<T, PWc>(n, *phi, cphi, cphat, s, err);
+        if (r) return r;
+        cphi = cphat = nullptr;
+    }
     if (cphi && prolong_fused<T, M>(n, count, tb, min_fused_n))
         return launch_fused_sweeps<T, M>(m, n, h, phi, tmp, eta, sigma, count, tb, s, err, cphi,
                                          cphat);
@@ -500,7 +520,7 @@ int launch_descend(const M& m, int nf, double hf, const T* phi_f, const T* eta_f
     return ISIS_OK;
 }
 
-template <class T>
+template <class T, int PW>
 int launch_prolong(int nf, T* fine, const T* coarse, const T* coarse_hat, hipStream_t s,
                    char* err)
 {
@@ -508,13 +528,14 @@ int launch_prolong(int nf, T* fine, const T* coarse, const T* coarse_hat, hipStr
     using PG = ProlongTileF;
     const int nc = nf / 2;
     if ((nc & (nc - 1)) == 0 && nc % PG::TK == 0 && nc % PG::TJ == 0 && nc % PG::XC == 0)
-        hipLaunchKernelGGL((k_prolong_tiled<T>), dim3((nc / PG::TK) * (nc / PG::TJ) * (nc / PG::XC)),
-                           dim3(kBlock), 0, s, nf, fine, coarse, coarse_hat);
+        hipLaunchKernelGGL((k_prolong_tiled<T, PW>),
+                           dim3((nc / PG::TK) * (nc / PG::TJ) * (nc / PG::XC)), dim3(kBlock), 0, s,
+                           nf, fine, coarse, coarse_hat);
     else if (nf >= 4)
-        hipLaunchKernelGGL((k_prolong_pairs<T>), dim3(grid_for(f3 / 8)), dim3(kBlock), 0, s, nf,
-                           fine, coarse, coarse_hat);
+        hipLaunchKernelGGL((k_prolong_pairs<T, PW>), dim3(grid_for(f3 / 8)), dim3(kBlock), 0, s,
+                           nf, fine, coarse, coarse_hat);
     else
-        hipLaunchKernelGGL((k_prolong_correct<T>), dim3(grid_for(f3)), dim3(kBlock), 0, s, nf,
+        hipLaunchKernelGGL((k_prolong_correct<T, PW>), dim3(grid_for(f3)), dim3(kBlock), 0, s, nf,
                            fine, coarse, coarse_hat);
     LAUNCH_CHECK(err, "k_prolong_correct");
     return ISIS_OK;
@@ -574,6 +595,7 @@ struct isis_mg {
     static constexpr int kMaxTimed = 2048;
     int tb;  // temporal block of the current solve (desc.temporal_block resolved)
     int fw;  // full-weighting restriction of the defect (desc.restriction resolved)
+    int pw;  // coefficient-weighted prolongation (desc.prolongation resolved)
     int profile;
     int ntimed;
     int events_ready;
@@ -686,6 +708,10 @@ bool valid_desc(const isis_mg_desc* d, char* err)
         fmt_err(err, "restriction must be -1 (per model), 0 (mean) or 1 (full weighting)");
         return false;
     }
+    if (d->prolongation < -1 || d->prolongation > 1) {
+        fmt_err(err, "prolongation must be -1 (per model), 0 (trilinear) or 1 (coefficient-weighted)");
+        return false;
+    }
     return true;
 }
 
@@ -792,6 +818,12 @@ template <class T, class M>
 int timed_sweeps(isis_mg* H, const M& m, LevP<T>& f, int l, int count, const T* cphi = nullptr,
                  const T* cphat = nullptr)
 {
+    constexpr int PWc = weighted_code<T, M>();
+    if (cphi && H->pw && PWc != 0) {
+        int r = launch_prolong<T, PWc>(f.n, f.phi, cphi, cphat, H->s, H->err);
+        if (r) return r;
+        return timed_block<T, M>(H, m, f, l, count, nullptr, nullptr);
+    }
     if (cphi && prolong_fused<T, M>(f.n, count, H->tb)) {
         int r = timed_block<T, M>(H, m, f, l, 1, cphi, cphat);  // the first, single-sweep pass
         if (r) return r;
@@ -823,11 +855,14 @@ int launch_bottom(isis_mg* H, const M& m, LevP<T>* L, int l, double* updates)
         const double n3 = (double)v.n * v.n * v.n;
         *updates += (q + 1 < a.nlev ? d.nu_pre + H->nu_post : d.nu_coarse) * n3;
     }
-    auto kern = H->fw ? k_bottom_cycle<T, M, true> : k_bottom_cycle<T, M, false>;
-    static std::atomic<unsigned> lds_done[2];  // per instantiation: devices set up
+    constexpr int PWc = weighted_code<T, M>();
+    const bool pw = H->pw && PWc != 0;
+    auto kern = H->fw ? (pw ? k_bottom_cycle<T, M, true, PWc> : k_bottom_cycle<T, M, true, 0>)
+                      : (pw ? k_bottom_cycle<T, M, false, PWc> : k_bottom_cycle<T, M, false, 0>);
+    static std::atomic<unsigned> lds_done[4];  // per instantiation: devices set up
     HIP_TRY(H->err, ensure_dynamic_lds((const void*)kern,
                                        bottom_lds_elems(kBottomMaxLevels) * (int)sizeof(T),
-                                       lds_done[H->fw ? 1 : 0]));
+                                       lds_done[(H->fw ? 1 : 0) + (pw ? 2 : 0)]));
     hipLaunchKernelGGL(kern, dim3(1), dim3(bottom_threads<T>()),
                        bottom_lds_elems(a.nlev) * (int)sizeof(T), H->s, m, a);
     LAUNCH_CHECK(H->err, "k_bottom_cycle");
@@ -1356,15 +1391,28 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
     H->tb = H->d.temporal_block >= 0 ? H->d.temporal_block
             : (params->model == ISIS_FR_HS || params->model == ISIS_CHAMELEON) ? 1 : 2;
     if (stats) stats->temporal_block = H->tb;
+    // Per-model prolongation (desc.prolongation = -1): weighted by the flux
+    // coefficient e^u for f(R), whose V-cycles it speeds up most (measured on
+    // the 512^3 halo workload with the oracle: 11 -> 7 cycles to 1e-8, with
+    // the 8-child mean); trilinear for the others (the chameleon: no change).
     // Per-model restriction of the defect (desc.restriction = -1): full
-    // weighting for f(R), whose V-cycles it speeds up (measured on the 512^3
-    // halo workload with the oracle: 14 -> 11 cycles to 1e-8); the 8-child
-    // mean for the canonical models and the chameleon, where full weighting
-    // measured one to two cycles more.
-    H->fw = H->d.restriction >= 0 ? H->d.restriction : (params->model == ISIS_FR_HS ? 1 : 0);
+    // weighting for f(R) with the trilinear prolongation (14 -> 11 cycles
+    // there), else the 8-child mean (with the weighted prolongation full
+    // weighting took one cycle more; for the canonical models and the
+    // chameleon one to two more).
+    const bool flux_form = params->model == ISIS_FR_HS || params->model == ISIS_CHAMELEON;
+    H->pw = H->d.prolongation >= 0 ? H->d.prolongation : (params->model == ISIS_FR_HS ? 1 : 0);
+    if (H->pw && !flux_form) {
+        fmt_err(H->err, "the coefficient-weighted prolongation needs a flux-form model "
+                        "(f(R) or the chameleon)");
+        return ISIS_ERR_UNSUPPORTED;
+    }
+    H->fw = H->d.restriction >= 0 ? H->d.restriction
+            : (params->model == ISIS_FR_HS && !H->pw ? 1 : 0);
     H->nu_post = H->d.nu_post >= 0 ? H->d.nu_post : default_nu_post(params->model);
     if (stats) {
         stats->restriction = H->fw;
+        stats->prolongation = H->pw;
         stats->nu_pre = H->d.nu_pre;
         stats->nu_post = H->nu_post;
     }
@@ -1741,6 +1789,18 @@ int isis_op_prolong_correct(int n_fine, double* fine, const double* coarse,
     }
     if (!ptrs_aligned({fine, coarse, coarse_hat})) return ISIS_ERR_INVALID_ARG;
     return launch_prolong<double>(n_fine, fine, coarse, coarse_hat, (hipStream_t)stream, g_err);
+}
+
+int isis_op_prolong_correct_w(int n_fine, double* fine, const double* coarse,
+                              const double* coarse_hat, void* stream)
+{
+    if (!op_grid_ok(n_fine, 4) || !fine || !coarse || !coarse_hat) {
+        fmt_err(g_err, "prolong_correct_w: need even n_fine >= 4 and non-NULL arrays");
+        return ISIS_ERR_INVALID_ARG;
+    }
+    if (!ptrs_aligned({fine, coarse, coarse_hat})) return ISIS_ERR_INVALID_ARG;
+    return launch_prolong<double, 1>(n_fine, fine, coarse, coarse_hat, (hipStream_t)stream,
+                                     g_err);
 }
 
 int isis_op_coarse_solve(const isis_model_params* p, double a, double h, double* phi,

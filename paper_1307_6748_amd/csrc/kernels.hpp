@@ -346,10 +346,35 @@ __global__ __launch_bounds__(kBlock) void k_fas_sigma(M m, int nc, T ih2,
     }
 }
 
-// fine += P(coarse - coarse_hat), cell-centred trilinear: along each axis the
-// parent I = i/2 gets weight 3/4 and its neighbour I + s (s = +1 for odd i,
-// -1 for even i) weight 1/4.
-template <class T>
+// Prolongation weight of the other coarse cell N along one axis (the
+// parent P takes 1 minus it).  PW = 0: trilinear, 1/4.  PW = 1, 2: weighted by
+// the flux coefficient b of the flux-form operators (Sec. 3.4), read from the
+// restricted field coarse_hat: 1 / (2 (1 + b_P / b_N)), which keeps the flux
+// b de/dx continuous across the face between P and N when b is constant over
+// each coarse cell and the correction linear between the centres; b = e^x for
+// PW = 1 (fields in u), 2^x for PW = 2 (single-precision f(R), carried as
+// w = u / ln 2).  Only the difference of the two values enters, so extreme
+// contrasts give 0 or 1/2, never an overflow.
+template <int PW, class T>
+__device__ __forceinline__ T prolong_weight(T xp, T xn)
+{
+    if constexpr (PW == 0) {
+        return T(0.25);
+    } else {
+        const T d = xp - xn;
+        T e;
+        if constexpr (PW == 2)
+            e = exp2(d);
+        else
+            e = exp(d);
+        return T(1) / (T(2) * (T(1) + e));
+    }
+}
+
+// fine += P(coarse - coarse_hat), cell-centred: along each axis the parent
+// I = i/2 and its neighbour I + s (s = +1 for odd i, -1 for even i); weights
+// 3/4 and 1/4 (trilinear, PW = 0) or from prolong_weight (PW = 1, 2).
+template <class T, int PW = 0>
 __global__ __launch_bounds__(kBlock) void k_prolong_correct(int nf, T* __restrict__ fine,
                                                             const T* __restrict__ coarse,
                                                             const T* __restrict__ coarse_hat)
@@ -370,6 +395,16 @@ __global__ __launch_bounds__(kBlock) void k_prolong_correct(int nf, T* __restric
         J[1] = (j & 1) ? wrap_inc(J[0], nc) : wrap_dec(J[0], nc);
         K[0] = k >> 1;
         K[1] = (k & 1) ? wrap_inc(K[0], nc) : wrap_dec(K[0], nc);
+        T wx[2] = {w[0], w[1]}, wy[2] = {w[0], w[1]}, wz[2] = {w[0], w[1]};
+        if constexpr (PW != 0) {
+            const T hp = coarse_hat[cell(nc, I[0], J[0], K[0])];
+            wx[1] = prolong_weight<PW>(hp, coarse_hat[cell(nc, I[1], J[0], K[0])]);
+            wy[1] = prolong_weight<PW>(hp, coarse_hat[cell(nc, I[0], J[1], K[0])]);
+            wz[1] = prolong_weight<PW>(hp, coarse_hat[cell(nc, I[0], J[0], K[1])]);
+            wx[0] = T(1) - wx[1];
+            wy[0] = T(1) - wy[1];
+            wz[0] = T(1) - wz[1];
+        }
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -378,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_correct(int nf, T* __restric
 #pragma unroll
                 for (int d = 0; d < 2; ++d) {
                     long q = cell(nc, I[a], J[b], K[d]);
-                    s += w[a] * w[b] * w[d] * (coarse[q] - coarse_hat[q]);
+                    s += wx[a] * wy[b] * wz[d] * (coarse[q] - coarse_hat[q]);
                 }
         fine[c] += s;
     }

@@ -129,9 +129,10 @@ __global__ __launch_bounds__(kBlock) void k_defect_restrict_pairs(
     }
 }
 
-// fine += P(coarse - coarse_hat) (see k_prolong_correct): one thread per
-// coarse cell updates its 8 children, in the same order of terms per child.
-template <class T>
+// fine += P(coarse - coarse_hat) (see k_prolong_correct; PW its weights):
+// one thread per coarse cell updates its 8 children, in the same order of
+// terms per child.
+template <class T, int PW = 0>
 __global__ __launch_bounds__(kBlock) void k_prolong_pairs(int nf, T* __restrict__ fine,
                                                           const T* __restrict__ coarse,
                                                           const T* __restrict__ coarse_hat)
@@ -159,6 +160,17 @@ __global__ __launch_bounds__(kBlock) void k_prolong_pairs(int nf, T* __restrict_
                     const long cq = ((long)Ix[a] * nc + Jy[b]) * nc + Kz[c];
                     d[a][b][c] = coarse[cq] - coarse_hat[cq];
                 }
+        // weight of the other cell per axis and side (index 0: -1, 1: +1)
+        T wo[3][2] = {{w[1], w[1]}, {w[1], w[1]}, {w[1], w[1]}};
+        if constexpr (PW != 0) {
+            const T hp = coarse_hat[((long)I * nc + J) * nc + K];
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd) {
+                wo[0][sd] = prolong_weight<PW>(hp, coarse_hat[((long)Ix[2 * sd] * nc + J) * nc + K]);
+                wo[1][sd] = prolong_weight<PW>(hp, coarse_hat[((long)I * nc + Jy[2 * sd]) * nc + K]);
+                wo[2][sd] = prolong_weight<PW>(hp, coarse_hat[((long)I * nc + J) * nc + Kz[2 * sd]]);
+            }
+        }
 #pragma unroll
         for (int di = 0; di < 2; ++di)
 #pragma unroll
@@ -171,6 +183,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_pairs(int nf, T* __restrict_
                     const int ai[2] = {1, di ? 2 : 0};
                     const int bj[2] = {1, dj ? 2 : 0};
                     const int ck[2] = {1, dk ? 2 : 0};
+                    const T wx[2] = {PW ? T(1) - wo[0][di] : w[0], PW ? wo[0][di] : w[1]};
+                    const T wy[2] = {PW ? T(1) - wo[1][dj] : w[0], PW ? wo[1][dj] : w[1]};
+                    const T wz[2] = {PW ? T(1) - wo[2][dk] : w[0], PW ? wo[2][dk] : w[1]};
                     T s = T(0);
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_pairs(int nf, T* __restrict_
                         for (int b = 0; b < 2; ++b)
 #pragma unroll
                             for (int c = 0; c < 2; ++c)
-                                s += w[a] * w[b] * w[c] * d[ai[a]][bj[b]][ck[c]];
+                                s += wx[a] * wy[b] * wz[c] * d[ai[a]][bj[b]][ck[c]];
                     f[dk] += s;
                 }
                 *reinterpret_cast<V*>(fine + o) = f;
@@ -516,7 +531,9 @@ struct ProlongTile {
 };
 using ProlongTileF = ProlongTile<4, 64, 8>;
 
-template <class T>
+// PW: the weights of k_prolong_correct; for PW != 0 each thread reads the
+// restricted field of its coarse cell and of the cell's six neighbours.
+template <class T, int PW = 0>
 __global__ __launch_bounds__(kBlock) void k_prolong_tiled(int nf, T* __restrict__ fine,
                                                           const T* __restrict__ coarse,
                                                           const T* __restrict__ coarse_hat)
@@ -563,6 +580,21 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tiled(int nf, T* __restrict_
     for (int I = I0; I < I0 + G::XC; ++I) {
         deposit(I + 1);
         load(min(I + 2, I0 + G::XC));  // clamped: branch-free
+        // weight of the other cell per axis and side (index 0: -1, 1: +1)
+        T wo[3][2] = {{w[1], w[1]}, {w[1], w[1]}, {w[1], w[1]}};
+        if constexpr (PW != 0) {
+            const int J = J0 + jj, K = K0 + kk;
+            auto hat = [&](int a, int b, int c) __attribute__((always_inline)) {
+                return coarse_hat[((long)(a & cm) * nc + (b & cm)) * nc + (c & cm)];
+            };
+            const T hp = hat(I, J, K);
+            wo[0][0] = prolong_weight<PW>(hp, hat(I - 1, J, K));
+            wo[0][1] = prolong_weight<PW>(hp, hat(I + 1, J, K));
+            wo[1][0] = prolong_weight<PW>(hp, hat(I, J - 1, K));
+            wo[1][1] = prolong_weight<PW>(hp, hat(I, J + 1, K));
+            wo[2][0] = prolong_weight<PW>(hp, hat(I, J, K - 1));
+            wo[2][1] = prolong_weight<PW>(hp, hat(I, J, K + 1));
+        }
         // this coarse cell's 8 children: 4 z-pairs
         V f[2][2];
 #pragma unroll
@@ -586,6 +618,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tiled(int nf, T* __restrict_
                     const int ai[2] = {1, di ? 2 : 0};
                     const int bj[2] = {1, dj ? 2 : 0};
                     const int ck[2] = {1, dk ? 2 : 0};
+                    const T wx[2] = {PW ? T(1) - wo[0][di] : w[0], PW ? wo[0][di] : w[1]};
+                    const T wy[2] = {PW ? T(1) - wo[1][dj] : w[0], PW ? wo[1][dj] : w[1]};
+                    const T wz[2] = {PW ? T(1) - wo[2][dk] : w[0], PW ? wo[2][dk] : w[1]};
                     T s = T(0);
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
@@ -593,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_tiled(int nf, T* __restrict_
                         for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
                             for (int c = 0; c < 2; ++c)
-                                s += w[a] * w[bb] * w[c] *
+                                s += wx[a] * wy[bb] * wz[c] *
                                      pl[ai[a]][(jj + bj[bb]) * G::EK + kk + ck[c]];
                     f[di][dj][dk] += s;
                 }

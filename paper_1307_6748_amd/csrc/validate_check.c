@@ -52,6 +52,7 @@ int main(void)
     d.nu_coarse = 32;
     d.max_cycles = 50;
     d.restriction = -1;
+    d.prolongation = -1;
     size_t w64 = isis_mg_workspace_size(&d);
     EXPECT(w64 > 0);
     d.precision = ISIS_MIXED;
@@ -71,6 +72,9 @@ int main(void)
     EXPECT(isis_mg_workspace_size(&e) == 0);
     e = d;
     e.guess_accept = 2.0;
+    EXPECT(isis_mg_workspace_size(&e) == 0);
+    e = d;
+    e.prolongation = 2;
     EXPECT(isis_mg_workspace_size(&e) == 0);
 
     isis_mg_t* h = (isis_mg_t*)1;
@@ -121,6 +125,8 @@ int main(void)
     EXPECT(isis_op_fas_descend(&p, 1.0, 2, 1.0, ok, ok, NULL, ok, ok, ok, ok, ok, NULL, NULL) ==
            ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_prolong_correct(8, ok, NULL, ok, NULL) == ISIS_ERR_INVALID_ARG);
+    EXPECT(isis_op_prolong_correct_w(8, ok, ok, NULL, NULL) == ISIS_ERR_INVALID_ARG);
+    EXPECT(isis_op_prolong_correct_w(8, ok, ok, mis, NULL) == ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_coarse_solve(&p, 1.0, -1.0, ok, ok, NULL, 4, NULL) == ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_cold_start(&p, 1.0, -1, ok, ok, NULL) == ISIS_ERR_INVALID_ARG);
     EXPECT(isis_op_cold_start(&p, 1.0, 0, NULL, NULL, NULL) == ISIS_OK);

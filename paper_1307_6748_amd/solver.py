@@ -122,6 +122,7 @@ class Stats:
     fine_prol_bytes: list = field(default_factory=lambda: [0.0, 0.0])
     nu_pre: int = 2          # smoothing sweeps per level the solve used
     nu_post: int = 2
+    prolongation: int = 0    # prolongation used: 0 trilinear, 1 coefficient-weighted
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
@@ -131,7 +132,8 @@ class Stats:
                      list(s.fine_sweep_updates), list(s.fine_sweep_bytes), s.temporal_block,
                      list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth,
                      s.restriction, s.judged_cycles, list(s.fine_prol_ms),
-                     list(s.fine_prol_launches), list(s.fine_prol_bytes), s.nu_pre, s.nu_post)
+                     list(s.fine_prol_launches), list(s.fine_prol_bytes), s.nu_pre, s.nu_post,
+                     s.prolongation)
 
 
 def _ptr(t: torch.Tensor | None):
@@ -158,9 +160,13 @@ class Solver:
     The workspace is a torch uint8 tensor on the current device; kernels run
     on the torch stream current at construction.  temporal_block = -1 (the
     default) lets the library pick the sweeps per HBM pass for each model;
-    0, 1, 2 force one choice (see isis_mg_desc).  restriction = -1 (the
-    default) restricts the defect by full weighting for f(R) and by the
-    8-child mean otherwise; 0 / 1 force the mean / full weighting.
+    0, 1, 2 force one choice (see isis_mg_desc).  prolongation = -1 (the
+    default) weights the prolongation by the flux coefficient e^u for f(R)
+    and uses the trilinear one otherwise; 0 / 1 force trilinear / weighted
+    (weighted: f(R) and the chameleon only).  restriction = -1 (the default)
+    restricts the defect by full weighting for f(R) with the trilinear
+    prolongation and by the 8-child mean otherwise; 0 / 1 force the mean /
+    full weighting.
     judge_skip: skip the FP64 judge on cycles predicted to stay above tol
     (see isis_mg_desc.judge_skip).  nu_post = -1 (the default): one
     post-smoothing sweep for the symmetron and the chameleon, two otherwise."""
@@ -168,13 +174,14 @@ class Solver:
     def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = -1,
                  nu_coarse: int = 32, max_cycles: int = 50, precision: str = "fp64",
                  temporal_block: int = -1, fp32_floor: float = 0.0, guess_accept: float = 0.0,
-                 restriction: int = -1, judge_skip: bool = False):
+                 restriction: int = -1, judge_skip: bool = False, prolongation: int = -1):
         self.N, self.box = int(N), float(box)
         self._h = None
         lib = A.lib()
         d = A.DescC(self.N, self.box, nu_pre, nu_post, nu_coarse, max_cycles,
                     PRECISIONS[precision], float(fp32_floor), temporal_block, _stream(), None, 0,
-                    float(guess_accept), int(restriction), int(bool(judge_skip)))
+                    float(guess_accept), int(restriction), int(bool(judge_skip)),
+                    int(prolongation))
         nbytes = lib.isis_mg_workspace_size(C.byref(d))
         if nbytes == 0:
             raise ValueError("invalid solver description (N, box, nu_*, max_cycles, precision, "
@@ -351,6 +358,17 @@ def restrict_fw(fine, out=None):
     out = torch.empty(fine.numel() // 8, dtype=fine.dtype, device=fine.device) if out is None else out
     _ok(A.lib().isis_op_restrict_fw(n, _ptr(fine), _ptr(out), _stream()))
     return out
+
+
+def prolong_correct_w(fine, coarse, coarse_hat):
+    """fine += P_b(coarse - coarse_hat), the coefficient-weighted prolongation
+    (weights from b = e^coarse_hat; isis_op_prolong_correct_w), in place."""
+    n = _side(fine)
+    _check_field(fine, n, "fine")
+    _check_field(coarse, n // 2, "coarse")
+    _check_field(coarse_hat, n // 2, "coarse_hat")
+    _ok(A.lib().isis_op_prolong_correct_w(n, _ptr(fine), _ptr(coarse), _ptr(coarse_hat),
+                                          _stream()))
 
 
 def prolong_correct(fine, coarse, coarse_hat):

@@ -56,7 +56,8 @@ def test_workspace_size_validation():
                 dict(fp32_floor=float("nan")), dict(guess_accept=-0.1),
                 dict(guess_accept=1.5), dict(guess_accept=float("nan")),
                 dict(restriction=2), dict(restriction=-2), dict(judge_skip=2),
-                dict(judge_skip=-1), dict(nu_post=-2), dict(nu_pre=-1)):
+                dict(judge_skip=-1), dict(nu_post=-2), dict(nu_pre=-1),
+                dict(prolongation=2), dict(prolongation=-2)):
         assert lib.isis_mg_workspace_size(C.byref(_desc(**bad))) == 0, bad
     # nu_post = -1 picks the sweeps per model; with nu_pre = 0 that is still >= 1
     assert lib.isis_mg_workspace_size(C.byref(_desc(nu_pre=0, nu_post=-1))) > 0
@@ -102,6 +103,8 @@ def test_ops_validate_sizes_on_host():
     assert lib.isis_op_halfsweep(C.byref(p), 1.0, 8, 1.0, fake, fake, None, 2, None) == -1
     assert lib.isis_op_restrict(5, fake, fake, None) == -1
     assert lib.isis_op_prolong_correct(2, fake, fake, fake, None) == -1
+    assert lib.isis_op_prolong_correct_w(2, fake, fake, fake, None) == -1
+    assert lib.isis_op_prolong_correct_w(6, fake, None, fake, None) == -1
     assert lib.isis_op_sweeps(C.byref(p), 1.0, 8, 1.0, fake, fake, fake, None, 1, 5, None) == -1
     assert lib.isis_op_cold_start(C.byref(p), 1.0, 0, None, None, None) == 0
 
@@ -116,6 +119,7 @@ def test_ops_reject_misaligned_pointers_on_host():
     assert b"aligned" in lib.isis_mg_last_error(None)
     assert lib.isis_op_restrict(8, bad, ok, None) == -1
     assert lib.isis_op_prolong_correct(8, ok, ok, bad, None) == -1
+    assert lib.isis_op_prolong_correct_w(8, ok, ok, bad, None) == -1
     assert lib.isis_op_halfsweep(C.byref(p), 1.0, 8, 1.0, ok, ok, bad, 0, None) == -1
     assert lib.isis_op_sweeps(C.byref(p), 1.0, 8, 1.0, ok, bad, ok, None, 1, 0, None) == -1
     assert lib.isis_op_fas_descend(C.byref(p), 1.0, 8, 1.0, ok, ok, None, ok, ok, ok, ok, bad,

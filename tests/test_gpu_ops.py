@@ -78,6 +78,25 @@ def test_prolong_correct(orc, n):
     assert np.max(np.abs(cubic(g, n) - expect)) <= 1e-14 * np.abs(expect).max()
 
 
+# the weighted variants of the same three kernels (tiled at 128, 256; pairs
+# elsewhere); coarse_hat spread over a wide range so that the weights span
+# (0, 1/2), with a few cells far beyond the exponential's range
+@pytest.mark.parametrize("n", [4, 8, 12, 36, 128, 256, 384])
+def test_prolong_correct_w(orc, n):
+    from paper_1307_6748_amd import solver as S
+    rng = np.random.default_rng(100 + n)
+    fine = rng.standard_normal((n, n, n))
+    ch = 3.0 * rng.standard_normal((n // 2,) * 3)
+    ch.flat[:: max(1, ch.size // 5)] += 800.0 * rng.choice([-1.0, 1.0], size=ch.flat[:: max(1, ch.size // 5)].size)
+    c = ch + rng.standard_normal((n // 2,) * 3)
+    expect = orc.prolong_correct_w(fine, c, ch)
+    g = dev(fine)
+    S.prolong_correct_w(g, dev(c), dev(ch))
+    got = cubic(g, n)
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - expect)) <= 1e-14 * (np.abs(expect).max() + 1.0)
+
+
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("n", [4, 12, 32, 64, 128])
 @pytest.mark.parametrize("with_sigma", [False, True])

@@ -240,32 +240,55 @@ def test_mixed_fp32_cycles_match(orc, name, n):
     assert abs(st.rel_res - r) <= 1e-9 * r, (st.rel_res, r)
 
 
-@pytest.mark.parametrize("name,n", [(nm, n) for nm in ("symmetron_a1", "fofr", "linear",
-                                                         "chameleon") for n in (64, 256)]
-                         + [("symmetron_a1", 512)])
-def test_mixed_fp32_cycles_other_restriction(orc, name, n):
-    """As above with the restriction of the defect switched from each model's
-    default: full weighting for the symmetron, the linear model and the
-    chameleon (on the tiled FP32 levels, 64^3 and up, the single-pass defect
-    + full-weighting kernel; its evaluation of the defect on the tile's
+_OTHER = ([(nm, n, 1, 0) for nm in ("symmetron_a1", "linear", "chameleon") for n in (64, 256)]
+          + [("symmetron_a1", 512, 1, 0)]
+          + [("fofr", n, r, p) for n in (64, 256) for r, p in ((1, 1), (1, 0), (0, 0))]
+          + [("chameleon", n, 0, 1) for n in (64, 256)] + [("fofr_a07", 64, 0, 1)])
+
+
+@pytest.mark.parametrize("name,n,restriction,prolongation", _OTHER)
+def test_mixed_fp32_cycles_other_restriction(orc, name, n, restriction, prolongation):
+    """As above with the restriction of the defect and the prolongation
+    switched from each model's default (the mean and the trilinear
+    prolongation for the symmetron, the linear model and the chameleon; the
+    mean and the coefficient-weighted prolongation for f(R)).  Full weighting
+    on the tiled FP32 levels, 64^3 and up, runs the single-pass defect +
+    full-weighting kernel: its evaluation of the defect on the tile's
     one-cell ring and the x filter across steps must match the oracle's full
     weighting, and the coarse source it forms in the same step the oracle's
-    Sigma; 16 coarse planes per workgroup at 512^3, 8 at 256^3, 4 at 128^3, 2
-    at 64^3), the 8-child mean for f(R) (its tiled descent forms Sigma one
-    coarse plane behind, from the means it keeps in LDS)."""
+    Sigma (16 coarse planes per workgroup at 512^3, 8 at 256^3, 4 at 128^3, 2
+    at 64^3).  The mean's tiled descent forms Sigma one coarse plane behind,
+    from the means it keeps in LDS.  f(R) with the trilinear prolongation
+    (its previous default, with full weighting) runs the prolongation inside
+    the first post-smoothing pass; the weighted prolongation runs in its own
+    kernel, in the bottom kernel too, and must match the oracle's weights
+    from e^u (single precision: 2^w)."""
     from paper_1307_6748_amd import synth
     om, sp, a = models(name)
     box = 4.0 * n
     eta = synth.lognormal(n, box, 2.0, 300 + n)
-    fw = 0 if name == "fofr" else 1
     k = 2
-    ro = orc.vcycles(om, eta, box, orc.cold_start(om, eta), k, cfg=orc.Cfg(restrict_fw=bool(fw)))
-    s = _solver(n, box, precision="mixed", max_cycles=k, restriction=fw)
+    ro = orc.vcycles(om, eta, box, orc.cold_start(om, eta), k,
+                     cfg=orc.Cfg(restrict_fw=bool(restriction), prolong_w=bool(prolongation)))
+    s = _solver(n, box, precision="mixed", max_cycles=k, restriction=restriction,
+                prolongation=prolongation)
     phi, st = s.solve(dev(eta), sp, a, 1e-300, check=False)
-    assert st.status == -2 and st.cycles_fp32 == k and st.restriction == fw
+    assert st.status == -2 and st.cycles_fp32 == k
+    assert st.restriction == restriction and st.prolongation == prolongation
     got = cubic(phi, n)
     err = np.max(np.abs(got - ro.phi)) / (np.abs(ro.phi).max() + 1.0)
     assert err <= 1e-6, err
+
+
+def test_weighted_prolongation_needs_a_flux_form_model():
+    from paper_1307_6748_amd import solver as S
+    from paper_1307_6748_amd import synth
+    eta = dev(synth.lognormal(16, 16.0, 1.0, 3))
+    s = _solver(16, 16.0, prolongation=1)
+    with pytest.raises(Exception, match="flux-form"):
+        s.solve(eta, S.symmetron(1.0, 0.5), 1.0, 1e-8, check=False)
+    _, st = s.solve(eta, S.fofr(n=1.0, fR0_abs=1e-5), 1.0, 1e-8, check=False)
+    assert st.status == 0 and st.prolongation == 1 and st.restriction == 0
 
 
 def test_safeguard_hits_match_oracle(orc):
