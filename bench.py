@@ -388,11 +388,11 @@ def main() -> int:
             solver64.close()
             del solver64
 
-    # The transfer operators: the library's per-model choice (the 8-child mean
-    # of the defect; the prolongation weighted by e^u for f(R), trilinear for
-    # the symmetron) against the other restriction, and for f(R) also the
-    # trilinear prolongation with full weighting (its previous choice), same
-    # solver otherwise.
+    # The transfer operators: the library's per-model choice (f(R): full
+    # weighting and the prolongation weighted by e^u; the symmetron: the
+    # 8-child mean and the trilinear prolongation) against the other
+    # restriction, and for f(R) also the trilinear prolongation with its
+    # restriction (its previous choice), same solver otherwise.
     restriction_leg = None
     if not args.no_restriction_compare:
         restriction_leg = {}
@@ -402,7 +402,7 @@ def main() -> int:
             r0, p0 = rec[name][-1].restriction, rec[name][-1].prolongation
             leg = {f"{rlab[r0]}, {plab[p0]}": dict(seconds=per_model[name]["seconds"],
                                                    cycles=per_model[name]["cycles"])}
-            others = [(1 - r0, p0)] + ([(1, 0)] if p0 == 1 and r0 != 1 else [])
+            others = [(1 - r0, p0)] + ([(r0, 0)] if p0 == 1 else [])
             for ro_, po_ in others:
                 so = S.Solver(n, box, precision=args.precision, temporal_block=tb,
                               max_cycles=100, fp32_floor=args.fp32_floor, restriction=ro_,

@@ -131,9 +131,9 @@ typedef struct {
                           weighting, the adjoint of the trilinear prolongation
                           over 8 (weights 1, 3, 3, 1 over 8 per axis; phi and
                           eta keep the mean); -1 = per model at each solve: full
-                          weighting for f(R) with the trilinear prolongation,
-                          else the mean.  The converged field does not depend
-                          on it, the V-cycles' convergence factors do          */
+                          weighting for f(R), the mean for the others.  The
+                          converged field does not depend on it, the V-cycles'
+                          convergence factors do                              */
     int judge_skip;    /* 0: the FP64 fine defect (the judge of the stop test) is
                           evaluated after every V-cycle; 1: after a judged cycle,
                           the cycles that the mean factor per cycle since the

@@ -98,7 +98,7 @@ class Cfg:
     max_cycles: int = 50
     # restriction of the defect: False = mean of the 8 children, True = full
     # weighting; None = per model, the choice the GPU library makes by
-    # default (full weighting only for f(R) with the trilinear prolongation)
+    # default (full weighting for f(R))
     restrict_fw: bool | None = None
     # prolongation: False = trilinear, True = weighted by b = e^u (flux-form
     # models; see orc_prolong_correct_w); None = per model, the GPU
@@ -109,7 +109,7 @@ class Cfg:
         pw = (model == FR_HS) if self.prolong_w is None else bool(self.prolong_w)
         if model not in (FR_HS, CHAMELEON):
             pw = False
-        fw = (model == FR_HS and not pw) if self.restrict_fw is None else bool(self.restrict_fw)
+        fw = (model == FR_HS) if self.restrict_fw is None else bool(self.restrict_fw)
         post = (1 if model in (SYMMETRON, CHAMELEON) else 2) if self.nu_post is None else self.nu_post
         return _Cfg(self.nu_pre, post, self.nu_coarse, self.max_cycles, int(fw), int(pw))
 

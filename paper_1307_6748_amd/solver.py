@@ -164,9 +164,8 @@ class Solver:
     default) weights the prolongation by the flux coefficient e^u for f(R)
     and uses the trilinear one otherwise; 0 / 1 force trilinear / weighted
     (weighted: f(R) and the chameleon only).  restriction = -1 (the default)
-    restricts the defect by full weighting for f(R) with the trilinear
-    prolongation and by the 8-child mean otherwise; 0 / 1 force the mean /
-    full weighting.
+    restricts the defect by full weighting for f(R) and by the 8-child mean
+    otherwise; 0 / 1 force the mean / full weighting.
     judge_skip: skip the FP64 judge on cycles predicted to stay above tol
     (see isis_mg_desc.judge_skip).  nu_post = -1 (the default): one
     post-smoothing sweep for the symmetron and the chameleon, two otherwise."""

@@ -242,7 +242,7 @@ def test_mixed_fp32_cycles_match(orc, name, n):
 
 _OTHER = ([(nm, n, 1, 0) for nm in ("symmetron_a1", "linear", "chameleon") for n in (64, 256)]
           + [("symmetron_a1", 512, 1, 0)]
-          + [("fofr", n, r, p) for n in (64, 256) for r, p in ((1, 1), (1, 0), (0, 0))]
+          + [("fofr", n, r, p) for n in (64, 256) for r, p in ((0, 1), (1, 0), (0, 0))]
           + [("chameleon", n, 0, 1) for n in (64, 256)] + [("fofr_a07", 64, 0, 1)])
 
 
@@ -250,8 +250,8 @@ _OTHER = ([(nm, n, 1, 0) for nm in ("symmetron_a1", "linear", "chameleon") for n
 def test_mixed_fp32_cycles_other_restriction(orc, name, n, restriction, prolongation):
     """As above with the restriction of the defect and the prolongation
     switched from each model's default (the mean and the trilinear
-    prolongation for the symmetron, the linear model and the chameleon; the
-    mean and the coefficient-weighted prolongation for f(R)).  Full weighting
+    prolongation for the symmetron, the linear model and the chameleon; full
+    weighting and the coefficient-weighted prolongation for f(R)).  Full weighting
     on the tiled FP32 levels, 64^3 and up, runs the single-pass defect +
     full-weighting kernel: its evaluation of the defect on the tile's
     one-cell ring and the x filter across steps must match the oracle's full
@@ -288,7 +288,7 @@ def test_weighted_prolongation_needs_a_flux_form_model():
     with pytest.raises(Exception, match="flux-form"):
         s.solve(eta, S.symmetron(1.0, 0.5), 1.0, 1e-8, check=False)
     _, st = s.solve(eta, S.fofr(n=1.0, fR0_abs=1e-5), 1.0, 1e-8, check=False)
-    assert st.status == 0 and st.prolongation == 1 and st.restriction == 0
+    assert st.status == 0 and st.prolongation == 1 and st.restriction == 1
 
 
 def test_safeguard_hits_match_oracle(orc):
