@@ -175,9 +175,8 @@ def solve_bytes(n: int, st, tb: int, nu: tuple, mixed: bool) -> float:
         b = 8 * n3 * (1 + 1 / 7) + (4 * n3 * (1 + 1 / 7) if mixed else 0)  # eta hierarchy (+FP32)
         b += 8 * n3 + 8 * n3 + (4 * n3 if mixed else 0) + 16 * n3            # cold start, r_ref
     cyc64 = st.cycles - st.cycles_fp32
-    for count, s in ((st.cycles_fp32, 4), (cyc64, 8)):
-        if count == 0:
-            continue
+
+    def cycle_bytes(s, fw):
         per = 0.0
         for l in range(nlev):
             nl = n >> l
@@ -187,10 +186,19 @@ def solve_bytes(n: int, st, tb: int, nu: tuple, mixed: bool) -> float:
             # the correction rides in the first post-smoothing pass when that
             # pass is a single sweep
             # (not with the coefficient-weighted prolongation: its own kernel)
-            per += level_bytes(nl, s, passes, l > 0, bool(st.restriction), l == nlev - 1,
+            per += level_bytes(nl, s, passes, l > 0, fw, l == nlev - 1,
                                fused and nu[1] > 0 and (blk == 1 or nu[1] == 1)
                                and not getattr(st, "prolongation", 0))
-        b += count * per
+        return per
+
+    # cycles in order (FP32 first in mixed precision); restriction 2 is full
+    # weighting in the first two cycles and the mean after them
+    done = 0
+    for count, s in ((st.cycles_fp32, 4), (cyc64, 8)):
+        for i in range(count):
+            fw = st.restriction == 1 or (st.restriction == 2 and done + i < 2)
+            b += cycle_bytes(s, fw)
+        done += count
     # the FP64 judge after the judged cycles (every cycle unless judge_skip;
     # the few FP64 cycles at the end of a mixed solve are all judged): reads
     # the iterate (4 or 8 B) and the FP64 density
@@ -352,7 +360,8 @@ def main() -> int:
             cycles=st.cycles, cycles_fp32=st.cycles_fp32, rel_res=st.rel_res,
             temporal_block=st.temporal_block,
             judged_cycles=st.judged_cycles,
-            restriction="full weighting" if st.restriction else "mean of 8",
+            restriction={0: "mean of 8", 1: "full weighting",
+                         2: "full weighting in cycles 1-2, then mean of 8"}[st.restriction],
             prolongation="coefficient-weighted" if st.prolongation else "trilinear",
             cycle=f"V({st.nu_pre},{st.nu_post})",
             safeguard_hits=st.safeguard_hits,
@@ -389,20 +398,26 @@ def main() -> int:
             del solver64
 
     # The transfer operators: the library's per-model choice (f(R): full
-    # weighting and the prolongation weighted by e^u; the symmetron: the
-    # 8-child mean and the trilinear prolongation) against the other
-    # restriction, and for f(R) also the trilinear prolongation with its
-    # restriction (its previous choice), same solver otherwise.
+    # weighting in the first two cycles, then the mean, and the prolongation
+    # weighted by e^u; the symmetron: the 8-child mean and the trilinear
+    # prolongation) against the alternatives (f(R): each restriction alone,
+    # and full weighting with the trilinear prolongation, its previous
+    # choice), same solver otherwise.
     restriction_leg = None
     if not args.no_restriction_compare:
         restriction_leg = {}
-        rlab = {0: "mean of 8", 1: "full weighting"}
+        rlab = {0: "mean of 8", 1: "full weighting",
+                2: "full weighting in cycles 1-2, then mean of 8"}
         plab = {0: "trilinear", 1: "coefficient-weighted"}
         for name, (p, a) in mods.items():
             r0, p0 = rec[name][-1].restriction, rec[name][-1].prolongation
             leg = {f"{rlab[r0]}, {plab[p0]}": dict(seconds=per_model[name]["seconds"],
                                                    cycles=per_model[name]["cycles"])}
-            others = [(1 - r0, p0)] + ([(r0, 0)] if p0 == 1 else [])
+            if r0 == 2:  # f(R) with the weighted prolongation: each restriction alone,
+                # and its previous choice (full weighting, trilinear prolongation)
+                others = [(1, p0), (0, p0), (1, 0)]
+            else:
+                others = [(1 - r0, p0)] + ([(r0, 0)] if p0 == 1 else [])
             for ro_, po_ in others:
                 so = S.Solver(n, box, precision=args.precision, temporal_block=tb,
                               max_cycles=100, fp32_floor=args.fp32_floor, restriction=ro_,

@@ -130,10 +130,12 @@ typedef struct {
                           leaves R open): 0 = mean of the 8 children; 1 = full
                           weighting, the adjoint of the trilinear prolongation
                           over 8 (weights 1, 3, 3, 1 over 8 per axis; phi and
-                          eta keep the mean); -1 = per model at each solve: full
-                          weighting for f(R), the mean for the others.  The
-                          converged field does not depend on it, the V-cycles'
-                          convergence factors do                              */
+                          eta keep the mean); -1 = per model at each solve:
+                          for f(R) full weighting in the first two V-cycles
+                          and the mean after them (full weighting throughout
+                          with the trilinear prolongation), the mean for the
+                          others.  The converged field does not depend on it,
+                          the V-cycles' convergence factors do               */
     int judge_skip;    /* 0: the FP64 fine defect (the judge of the stop test) is
                           evaluated after every V-cycle; 1: after a judged cycle,
                           the cycles that the mean factor per cycle since the
@@ -195,7 +197,8 @@ typedef struct {
                                      every level of side >= 256 (the smaller
                                      levels are not timed), milliseconds          */
     int restriction;              /* the restriction of the defect the solve used
-                                     (0 mean, 1 full weighting)                    */
+                                     (0 mean, 1 full weighting, 2 full weighting
+                                     in the first two cycles, the mean after)     */
     int judged_cycles;            /* V-cycles after which the judge ran          */
     /* Finest-level first post-smoothing pass with the prolongation
      * phi += P(phi_c - phihat_c) fused in (fused sweep kernels with a

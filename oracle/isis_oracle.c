@@ -33,6 +33,8 @@
  *       Option (orc_cfg.restrict_fw): the defect is restricted by full
  *       weighting, the adjoint of P over 8 (weights 1, 3, 3, 1 over 8 per
  *       axis on the 4 fine cells 2I-1 .. 2I+2); phi and rho keep the mean.
+ *       Option (orc_cfg.restrict_fw = 2): full weighting in the first two
+ *       V-cycles of a solve, the mean after them.
  *       Option (orc_cfg.prolong_w, flux-form models): P weighted by the
  *       coefficient b = e^u of the restricted field, see
  *       orc_prolong_correct_w.
@@ -113,7 +115,9 @@ typedef struct {
 
 typedef struct {
     int nu_pre, nu_post, nu_coarse, max_cycles;
-    int restrict_fw; /* 1: full-weighting restriction of the defect (reading R2) */
+    int restrict_fw; /* 1: full-weighting restriction of the defect (reading R2);
+                        2: full weighting in the first two V-cycles of the solve,
+                        the mean of the children after them                      */
     int prolong_w;   /* 1: coefficient-weighted prolongation (reading R2; f(R),
                         chameleon: b = e^u of coarse_hat)                          */
 } orc_cfg;
@@ -670,7 +674,9 @@ int orc_solve(const orc_model* m, const orc_cfg* cfg, int n, double box, const d
     if (!isfinite(r0)) status = ORC_DIVERGED;
     else if (r0 <= tol * r_norm) status = ORC_OK;
     while (status == ORC_NOT_CONVERGED && cyc < cfg->max_cycles) {
-        vcycle(m, cfg, lv, 0, nlev);
+        orc_cfg cc = *cfg; /* restrict_fw 2: full weighting in cycles 1 and 2 only */
+        if (cfg->restrict_fw == 2) cc.restrict_fw = cyc < 2;
+        vcycle(m, &cc, lv, 0, nlev);
         ++cyc;
         if (singular) {
             double mu = mean_of(n, phi);

@@ -97,9 +97,11 @@ class Cfg:
     nu_coarse: int = 32
     max_cycles: int = 50
     # restriction of the defect: False = mean of the 8 children, True = full
-    # weighting; None = per model, the choice the GPU library makes by
-    # default (full weighting for f(R))
-    restrict_fw: bool | None = None
+    # weighting, 2 = full weighting in the first two V-cycles of the solve and
+    # the mean after them; None = per model, the choice the GPU library makes
+    # by default (2 for f(R) with the weighted prolongation, True for f(R)
+    # with the trilinear one, False otherwise)
+    restrict_fw: bool | int | None = None
     # prolongation: False = trilinear, True = weighted by b = e^u (flux-form
     # models; see orc_prolong_correct_w); None = per model, the GPU
     # library's default (weighted for f(R), where it takes fewer V-cycles)
@@ -109,7 +111,10 @@ class Cfg:
         pw = (model == FR_HS) if self.prolong_w is None else bool(self.prolong_w)
         if model not in (FR_HS, CHAMELEON):
             pw = False
-        fw = (model == FR_HS) if self.restrict_fw is None else bool(self.restrict_fw)
+        if self.restrict_fw is None:
+            fw = (2 if pw else 1) if model == FR_HS else 0
+        else:
+            fw = 2 if self.restrict_fw == 2 else int(bool(self.restrict_fw))
         post = (1 if model in (SYMMETRON, CHAMELEON) else 2) if self.nu_post is None else self.nu_post
         return _Cfg(self.nu_pre, post, self.nu_coarse, self.max_cycles, int(fw), int(pw))
 

@@ -90,8 +90,8 @@ int main(void)
     double* coarse = (double*)malloc(sizeof(double) * (size_t)(n3 / 8));
     double* coarse2 = (double*)malloc(sizeof(double) * (size_t)(n3 / 8));
     for (int mi = 0; mi < 4; ++mi) {
-        for (int opt = 0; opt < 4; ++opt) {
-            const int fw = opt & 1, pw = opt >> 1;  /* pw: only the flux-form models use it */
+        for (int opt = 0; opt < 6; ++opt) {
+            const int fw = opt % 3, pw = opt / 3;  /* pw: only the flux-form models use it */
             orc_cfg cfg = {2, 2, 32, 40, fw, pw};
             orc_stats st;
             int rc = orc_solve(&models[mi], &cfg, n, box, eta, phi, 0, 1e-9, &st);

@@ -594,7 +594,9 @@ struct isis_mg {
     // any level, created on the first isis_mg_set_profiling(h, 1)
     static constexpr int kMaxTimed = 2048;
     int tb;  // temporal block of the current solve (desc.temporal_block resolved)
-    int fw;  // full-weighting restriction of the defect (desc.restriction resolved)
+    int fw;  // full-weighting restriction of the defect in the current cycle
+    int fw_after;  // ... after the first fw_first cycles of a solve (with them: full weighting)
+    int fw_first;
     int pw;  // coefficient-weighted prolongation (desc.prolongation resolved)
     int profile;
     int ntimed;
@@ -1064,6 +1066,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         double rprev = r0, rho_prev = 1.0;
         bool fp32_failed = false;
         while (cyc < d.max_cycles) {
+            H->fw = cyc < H->fw_first ? 1 : H->fw_after;
             if ((r = vcycle<float, M32>(H, m32, H->L32, 0, &updates))) return r;
             if (singular && (r = sub_mean<float>(H, H->L32[0].phi, n3))) return r;
             ++cyc;
@@ -1130,6 +1133,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     double rlast = rcur;  // residual at the last judged cycle (cprev)
     blind = 0;
     while (status == ISIS_ERR_NOT_CONVERGED && cyc < d.max_cycles) {
+        H->fw = cyc < H->fw_first ? 1 : H->fw_after;
         if ((r = vcycle<double, M64>(H, m64, H->L64, 0, &updates))) return r;
         if (singular && (r = sub_mean<double>(H, F.phi, n3))) return r;
         ++cyc;
@@ -1394,14 +1398,17 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
     // Per-model prolongation (desc.prolongation = -1): weighted by the flux
     // coefficient e^u for f(R), trilinear for the others (the chameleon: no
     // change).  Per-model restriction of the defect (desc.restriction = -1):
-    // full weighting for f(R), the 8-child mean for the others (for the
-    // canonical models and the chameleon full weighting took one to two
-    // cycles more).  For f(R) the pair measured 8 V-cycles to 1e-8 on the
-    // 512^3 halo workload instead of 11 with the trilinear prolongation, and
-    // converged in every f(R) case measured (|f_R0| = 1e-4 .. 1e-6, a = 0.5
-    // .. 1, n = 1, 2, three densities); the mean with the weighted
-    // prolongation took 7 cycles there but diverged at |f_R0| = 1e-4 and at
-    // a = 0.5, and the trilinear prolongation diverged at a = 0.5.
+    // for f(R) with the weighted prolongation, full weighting in the first
+    // two V-cycles of the solve and the 8-child mean after them; full
+    // weighting throughout with the trilinear one; the mean for the other
+    // models (for the canonical models and the chameleon full weighting took
+    // one to two cycles more).  Measured on f(R) solves to 1e-8 over
+    // |f_R0| = 1e-4 .. 1e-6, a = 0.5 .. 1, n = 1, 2 and three densities: the
+    // mean from the first cycle diverged twice at 512^3 (its first or second
+    // cycle), full weighting throughout converged everywhere in 7-9 cycles,
+    // two full-weighting cycles and then the mean everywhere in 6-7 (8 -> 7
+    // on the 512^3 halo workload; 11 with the trilinear prolongation, which
+    // also diverged once).
     const bool flux_form = params->model == ISIS_FR_HS || params->model == ISIS_CHAMELEON;
     H->pw = H->d.prolongation >= 0 ? H->d.prolongation : (params->model == ISIS_FR_HS ? 1 : 0);
     if (H->pw && !flux_form) {
@@ -1409,10 +1416,19 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
                         "(f(R) or the chameleon)");
         return ISIS_ERR_UNSUPPORTED;
     }
-    H->fw = H->d.restriction >= 0 ? H->d.restriction : (params->model == ISIS_FR_HS ? 1 : 0);
+    H->fw_first = 0;
+    if (H->d.restriction >= 0)
+        H->fw_after = H->d.restriction;
+    else if (params->model == ISIS_FR_HS && H->pw) {
+        H->fw_after = 0;
+        H->fw_first = 2;
+    } else {
+        H->fw_after = params->model == ISIS_FR_HS ? 1 : 0;
+    }
+    H->fw = H->fw_first > 0 ? 1 : H->fw_after;
     H->nu_post = H->d.nu_post >= 0 ? H->d.nu_post : default_nu_post(params->model);
     if (stats) {
-        stats->restriction = H->fw;
+        stats->restriction = H->fw_first > 0 ? 2 : H->fw_after;
         stats->prolongation = H->pw;
         stats->nu_pre = H->d.nu_pre;
         stats->nu_post = H->nu_post;

@@ -113,7 +113,8 @@ class Stats:
     rho_hist: list = field(default_factory=list)  # per-cycle factors, [0] = 0
     safeguard_hits: int = 0  # symmetron: updates with the safeguarded denominator
     ms_smooth: float = 0.0   # profiling on: smoothing on the finest level and sides >= 256
-    restriction: int = 0     # defect restriction used: 0 mean, 1 full weighting
+    restriction: int = 0     # defect restriction used: 0 mean, 1 full weighting,
+                             # 2 full weighting in the first two cycles, then the mean
     judged_cycles: int = 0   # cycles after which the FP64 judge ran
     # finest-level first post-smoothing pass with the prolongation fused in
     # (profiling on): [FP64, FP32]
@@ -164,8 +165,10 @@ class Solver:
     default) weights the prolongation by the flux coefficient e^u for f(R)
     and uses the trilinear one otherwise; 0 / 1 force trilinear / weighted
     (weighted: f(R) and the chameleon only).  restriction = -1 (the default)
-    restricts the defect by full weighting for f(R) and by the 8-child mean
-    otherwise; 0 / 1 force the mean / full weighting.
+    restricts the defect for f(R) by full weighting in the first two V-cycles
+    and by the 8-child mean after them (full weighting throughout with the
+    trilinear prolongation), by the mean for the others; 0 / 1 force the
+    mean / full weighting.
     judge_skip: skip the FP64 judge on cycles predicted to stay above tol
     (see isis_mg_desc.judge_skip).  nu_post = -1 (the default): one
     post-smoothing sweep for the symmetron and the chameleon, two otherwise."""

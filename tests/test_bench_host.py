@@ -125,6 +125,16 @@ def test_solve_bytes_counts_every_kernel_once():
     assert abs(bench.level_bytes(64, 8, 4, True, True, False)
                - (lvl + c64 * 8 * (2 + 3 / 8))) <= 1e-9 * lvl    # FP64 full weighting: two passes
     assert abs(bench.level_bytes(64, 4, 4, True, True, False) - lvl / 2) <= 1e-9 * lvl
+    # restriction 2: full weighting in the first two cycles, the mean after
+    st2 = types.SimpleNamespace(cycles=4, cycles_fp32=0, restriction=2)
+    st0 = types.SimpleNamespace(cycles=2, cycles_fp32=0, restriction=0)
+    st1 = types.SimpleNamespace(cycles=2, cycles_fp32=0, restriction=1)
+    base = bench.solve_bytes(16, types.SimpleNamespace(cycles=0, cycles_fp32=0, restriction=0),
+                             0, (2, 2), False)
+    mixed = bench.solve_bytes(16, st2, 0, (2, 2), False)
+    parts = (bench.solve_bytes(16, st0, 0, (2, 2), False) - base
+             + bench.solve_bytes(16, st1, 0, (2, 2), False) - base + base)
+    assert abs(mixed - parts) <= 1e-9 * mixed
     # the fused sweep levels (>= 256^3, temporal block >= 1) apply the
     # correction inside the first post-smoothing pass: no pass of its own
     st512 = types.SimpleNamespace(cycles=1, cycles_fp32=1, restriction=0, judged_cycles=1)

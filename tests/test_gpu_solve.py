@@ -242,7 +242,7 @@ def test_mixed_fp32_cycles_match(orc, name, n):
 
 _OTHER = ([(nm, n, 1, 0) for nm in ("symmetron_a1", "linear", "chameleon") for n in (64, 256)]
           + [("symmetron_a1", 512, 1, 0)]
-          + [("fofr", n, r, p) for n in (64, 256) for r, p in ((0, 1), (1, 0), (0, 0))]
+          + [("fofr", n, r, p) for n in (64, 256) for r, p in ((0, 1), (1, 1), (1, 0), (0, 0))]
           + [("chameleon", n, 0, 1) for n in (64, 256)] + [("fofr_a07", 64, 0, 1)])
 
 
@@ -251,7 +251,8 @@ def test_mixed_fp32_cycles_other_restriction(orc, name, n, restriction, prolonga
     """As above with the restriction of the defect and the prolongation
     switched from each model's default (the mean and the trilinear
     prolongation for the symmetron, the linear model and the chameleon; full
-    weighting and the coefficient-weighted prolongation for f(R)).  Full weighting
+    weighting in the first two cycles, then the mean, and the
+    coefficient-weighted prolongation for f(R)).  Full weighting
     on the tiled FP32 levels, 64^3 and up, runs the single-pass defect +
     full-weighting kernel: its evaluation of the defect on the tile's
     one-cell ring and the x filter across steps must match the oracle's full
@@ -280,6 +281,27 @@ def test_mixed_fp32_cycles_other_restriction(orc, name, n, restriction, prolonga
     assert err <= 1e-6, err
 
 
+@pytest.mark.parametrize("name,n", [("fofr", 64), ("fofr", 256), ("fofr_a07", 64)])
+def test_mixed_fp32_cycles_fofr_default_schedule(orc, name, n):
+    """Four FP32 cycles with f(R)'s default transfer operators: full
+    weighting in the first two cycles, the 8-child mean in the next two
+    (stats.restriction = 2), the weighted prolongation throughout; element
+    by element against the oracle's default (restrict_fw = 2)."""
+    from paper_1307_6748_amd import synth
+    om, sp, a = models(name)
+    box = 4.0 * n
+    eta = synth.lognormal(n, box, 2.0, 400 + n)
+    k = 4
+    ro = orc.vcycles(om, eta, box, orc.cold_start(om, eta), k)
+    s = _solver(n, box, precision="mixed", max_cycles=k)
+    phi, st = s.solve(dev(eta), sp, a, 1e-300, check=False)
+    assert st.status == -2 and st.cycles_fp32 == k
+    assert st.restriction == 2 and st.prolongation == 1
+    got = cubic(phi, n)
+    err = np.max(np.abs(got - ro.phi)) / (np.abs(ro.phi).max() + 1.0)
+    assert err <= 1e-6, err
+
+
 def test_weighted_prolongation_needs_a_flux_form_model():
     from paper_1307_6748_amd import solver as S
     from paper_1307_6748_amd import synth
@@ -288,7 +310,7 @@ def test_weighted_prolongation_needs_a_flux_form_model():
     with pytest.raises(Exception, match="flux-form"):
         s.solve(eta, S.symmetron(1.0, 0.5), 1.0, 1e-8, check=False)
     _, st = s.solve(eta, S.fofr(n=1.0, fR0_abs=1e-5), 1.0, 1e-8, check=False)
-    assert st.status == 0 and st.prolongation == 1 and st.restriction == 1
+    assert st.status == 0 and st.prolongation == 1 and st.restriction == 2
 
 
 def test_safeguard_hits_match_oracle(orc):

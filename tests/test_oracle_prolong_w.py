@@ -113,3 +113,22 @@ def test_fofr_solve_with_weighted_prolongation_reaches_the_root():
     rt = orc.solve(m, eta, box, tol=1e-12, cfg=orc.Cfg(max_cycles=60, prolong_w=False))
     assert rw.status == orc.OK and rt.status == orc.OK
     assert np.max(np.abs(rw.phi - rt.phi)) <= 1e-8 * (np.abs(rt.phi).max() + 1.0)
+
+
+def test_two_full_weighting_cycles_then_the_mean():
+    """restrict_fw = 2 (f(R)'s default with the weighted prolongation) is two
+    V-cycles with full weighting followed by cycles with the 8-child mean:
+    the same field, bit for bit, as the two runs chained by hand."""
+    from paper_1307_6748_amd import synth
+    m = orc.Model(model=orc.FR_HS, a=1.0, n=1.0, fR0_abs=1e-5, omega_m=0.27, omega_l=0.73)
+    n, box = 16, 8.0
+    eta = synth.lognormal(n, box, 1.5, 6)
+    cold = orc.cold_start(m, eta)
+    both = orc.vcycles(m, eta, box, cold, 5, cfg=orc.Cfg(restrict_fw=2, prolong_w=True))
+    first = orc.vcycles(m, eta, box, cold, 2, cfg=orc.Cfg(restrict_fw=True, prolong_w=True))
+    rest = orc.vcycles(m, eta, box, first.phi, 3, cfg=orc.Cfg(restrict_fw=False, prolong_w=True))
+    assert np.array_equal(both.phi, rest.phi)
+    assert not np.array_equal(both.phi, orc.vcycles(m, eta, box, cold, 5,
+                                                    cfg=orc.Cfg(restrict_fw=True, prolong_w=True)).phi)
+    assert orc.Cfg()._c(orc.FR_HS).restrict_fw == 2
+    assert orc.Cfg(prolong_w=False)._c(orc.FR_HS).restrict_fw == 1
