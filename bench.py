@@ -199,12 +199,14 @@ def solve_bytes(n: int, st, tb: int, nu: tuple, mixed: bool) -> float:
             fw = st.restriction == 1 or (st.restriction == 2 and done + i < 2)
             b += cycle_bytes(s, fw)
         done += count
-    # the FP64 judge after the judged cycles (every cycle unless judge_skip;
-    # the few FP64 cycles at the end of a mixed solve are all judged): reads
-    # the iterate (4 or 8 B) and the FP64 density
+    # the judge after the judged cycles (every cycle unless judge_skip; the
+    # few FP64 cycles at the end of a mixed solve are all judged): the FP64
+    # judge reads the iterate (4 or 8 B) and the FP64 density, the light one
+    # (FP32 cycles with judge_skip) the FP32 iterate and the FP32 density
     judged = getattr(st, "judged_cycles", st.cycles)
-    j64 = min(judged, cyc64)
-    b += (judged - j64) * (4 + 8) * n3 + j64 * (8 + 8) * n3
+    light = getattr(st, "judged_fp32", 0)
+    j64 = min(judged - light, cyc64)
+    b += (judged - light - j64) * (4 + 8) * n3 + j64 * (8 + 8) * n3 + light * (4 + 4) * n3
     return b
 
 
@@ -359,7 +361,7 @@ def main() -> int:
             seconds=secs,
             cycles=st.cycles, cycles_fp32=st.cycles_fp32, rel_res=st.rel_res,
             temporal_block=st.temporal_block,
-            judged_cycles=st.judged_cycles,
+            judged_cycles=st.judged_cycles, judged_fp32=st.judged_fp32,
             restriction={0: "mean of 8", 1: "full weighting",
                          2: "full weighting in cycles 1-2, then mean of 8"}[st.restriction],
             prolongation="coefficient-weighted" if st.prolongation else "trilinear",

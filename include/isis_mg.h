@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define ISIS_MG_ABI_VERSION 4
+#define ISIS_MG_ABI_VERSION 5
 #define ISIS_MG_MAX_HIST 128
 
 typedef enum {
@@ -140,10 +140,15 @@ typedef struct {
                           evaluated after every V-cycle; 1: after a judged cycle,
                           the cycles that the mean factor per cycle since the
                           previous judged one predicts to stay above tol (all
-                          but the last two before the predicted end, at most 4
-                          in a row) run without it.  The stop test is unchanged
-                          (the last cycle is always judged); unjudged cycles
-                          have rel_hist = NaN                                   */
+                          but the last one before the predicted end, at most 4
+                          in a row) run without it, and in mixed precision an
+                          FP32 cycle predicted to end above max(3e-5, 1e3 tol)
+                          relative is judged by the FP32 problem's own defect
+                          (FP32 density and arithmetic; its rel_hist entry is
+                          then accurate to ~1e-7 relative residual; not for
+                          f(R) in the paper's variable).  The stop test is
+                          unchanged (the last cycle is always judged in FP64);
+                          unjudged cycles have rel_hist = NaN                   */
     int prolongation;  /* prolongation of the coarse-grid correction (Sec. 3.1
                           leaves P open): 0 = cell-centred trilinear; 1 =
                           weighted by the flux coefficient b = e^u of the
@@ -199,7 +204,8 @@ typedef struct {
     int restriction;              /* the restriction of the defect the solve used
                                      (0 mean, 1 full weighting, 2 full weighting
                                      in the first two cycles, the mean after)     */
-    int judged_cycles;            /* V-cycles after which the judge ran          */
+    int judged_cycles;            /* V-cycles after which the judge ran (FP64,
+                                     or FP32: judged_fp32)                         */
     /* Finest-level first post-smoothing pass with the prolongation
      * phi += P(phi_c - phihat_c) fused in (fused sweep kernels with a
      * single-sweep first pass, i.e. temporal block 1; profiling on): [0] FP64,
@@ -212,6 +218,8 @@ typedef struct {
     int nu_pre, nu_post;          /* the smoothing sweeps per level the solve used */
     int prolongation;             /* the prolongation the solve used (0 trilinear,
                                      1 coefficient-weighted)                       */
+    int judged_fp32;              /* of judged_cycles, those judged by the FP32
+                                     problem's own defect (desc.judge_skip)        */
 } isis_mg_stats;
 
 typedef struct isis_mg isis_mg_t;

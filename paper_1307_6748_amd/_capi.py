@@ -48,7 +48,7 @@ class StatsC(C.Structure):
                 ("restriction", C.c_int), ("judged_cycles", C.c_int),
                 ("fine_prol_ms", C.c_double * 2), ("fine_prol_launches", C.c_int * 2),
                 ("fine_prol_bytes", C.c_double * 2), ("nu_pre", C.c_int), ("nu_post", C.c_int),
-                ("prolongation", C.c_int)]
+                ("prolongation", C.c_int), ("judged_fp32", C.c_int)]
 
 
 _lib = None

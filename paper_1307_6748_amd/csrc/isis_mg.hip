@@ -760,6 +760,35 @@ int fine_rms(isis_mg* H, const M& m, const TF* phi, const double* eta, double* r
     return ISIS_OK;
 }
 
+// The same norm of the FP32 problem's own defect (FP32 field, FP32 density,
+// float arithmetic, double sums): the light judge of the judge schedule.
+// Only for the tiled sizes (norm_tiled).
+inline bool norm_tiled(int n)
+{
+    using NG = NormTileF;
+    return (n & (n - 1)) == 0 && n % NG::TZ == 0 && n % NG::TY == 0 && n % NG::XC == 0;
+}
+
+template <class M>
+int fine_rms_fp32(isis_mg* H, const M& m, const float* phi, const float* eta, double* out)
+{
+    using NG = NormTileF;
+    const int n = H->d.N;
+    const long n3 = (long)n * n * n;
+    const double h = H->L64[0].h;
+    const long tiles = (long)(n / NG::TZ) * (n / NG::TY) * (n / NG::XC);
+    const int g = (int)std::min<long>(kReduceBlocks, tiles);
+    hipLaunchKernelGGL((k_defect_norm_tiled<float, M, float>), dim3(g), dim3(kBlock), 0, H->s, m,
+                       n, 1.0 / (h * h), 1.0, 0.0, phi, eta, nullptr, H->partial);
+    LAUNCH_CHECK(H->err, "k_defect_norm_tiled");
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, H->s, H->partial, g, H->scal);
+    LAUNCH_CHECK(H->err, "k_reduce");
+    HIP_TRY(H->err, hipMemcpyAsync(H->host, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->s));
+    HIP_TRY(H->err, hipStreamSynchronize(H->s));
+    *out = std::sqrt(H->host[0] / (double)n3);
+    return ISIS_OK;
+}
+
 template <class T>
 int sub_mean(isis_mg* H, T* f, long n3)
 {
@@ -905,16 +934,26 @@ constexpr double kFloorJumpMax = 1e-6;
 
 // Judge schedule (desc.judge_skip): after a judged cycle whose residual rc
 // fell at the mean factor rho per cycle since the previous judged one, the
-// number of cycles until rc rho^m <= tol is m; the next `ahead` cycles then
-// run without the judge, ahead = min(m - 2, 4) >= 0, so the judge resumes two
-// cycles before the predicted end (the factors of these solves rise towards
-// their asymptotic value, so the prediction errs on the early side).
+// number of cycles until rc rho^m <= target is m; the next `ahead` cycles
+// then run without the judge, ahead = min(m - 1, 4) >= 0, so the judge
+// resumes at the cycle predicted to reach the target (the factors of these
+// solves rise towards their asymptotic value, so the prediction errs on the
+// early side, and a residual still above the target is judged again after
+// the next cycle).
 inline int judge_ahead(bool lazy, int cyc, double rc, double rho, double target)
 {
     if (!lazy || cyc < 2 || !(rho > 0.0) || !(rho < 0.6) || !(rc > target)) return 0;
     const double m = std::ceil(std::log(target / rc) / std::log(rho));
-    return (int)std::max(0.0, std::min(m - 2.0, 4.0));
+    return (int)std::max(0.0, std::min(m - 1.0, 4.0));
 }
+
+// Judge schedule, FP32 cycles: a cycle whose residual is predicted to stay
+// above max(kLightJudgeMin, 1e3 tol) (relative) is judged by the FP32
+// problem's own defect (fine_rms_fp32), whose rounding (a relative residual
+// of ~1e-7 at most: the FP32 cycles' round-off floor) is then below 1% of the
+// residual; a light result below that level is taken again by the FP64 judge,
+// so the stop test and the predictive hand-over to FP64 see the FP64 defect.
+constexpr double kLightJudgeMin = 3e-5;
 
 // The solve for one model; M64/M32 are its double and float device models.
 // In mixed precision the FP32 field is (field - shift32) * M32::kVar: f(R) in
@@ -1034,6 +1073,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
 
     const bool lazy = d.judge_skip != 0;
     int blind = 0, judged = 0, cprev = 0;  // judge schedule; cprev: last judged cycle
+    int judged_fp32 = 0;                   // of which by the light (FP32) judge
     // Mixed precision, phase 1: FP32 V-cycles on the FP32 copy of the
     // problem, monitored by the FP64 defect of the FP32 iterate.  Skipped when
     // the initial field is already near the FP32 round-off floor, where FP32
@@ -1065,6 +1105,12 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         const double fp32_floor = predict ? 0.0 : d.fp32_floor;
         double rprev = r0, rho_prev = 1.0;
         bool fp32_failed = false;
+        // Light judges (judge schedule): the FP32 problem's defect is the
+        // FP64 one's only where both solve in the same variable.
+        const bool light_ok = lazy && shift32 == 0.0 && norm_tiled(N);
+        const double light_min = std::max(kLightJudgeMin, 1e3 * tol) * rnorm;
+        const double first_factor =
+            H->cold_first[p.model] > 0.0 ? H->cold_first[p.model] : 1e-2;
         while (cyc < d.max_cycles) {
             H->fw = cyc < H->fw_first ? 1 : H->fw_after;
             if ((r = vcycle<float, M32>(H, m32, H->L32, 0, &updates))) return r;
@@ -1078,9 +1124,19 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             }
             blind = 0;
             ++judged;
-            double rc;
-            if ((r = fine_rms<float, M64>(H, m64, H->L32[0].phi, density, nullptr, &rc,
-                                          M32::kVarInv, shift32)))
+            double rc = 0.0;
+            // predicted residual: the last judged one at the mean factor per
+            // cycle since (before the first judged cycle, the model's
+            // first-cycle factor)
+            const double rho_est = judged == 1 ? first_factor : rho_prev;
+            bool light = light_ok && rprev * std::pow(rho_est, cyc - cprev) >= light_min;
+            if (light) {
+                if ((r = fine_rms_fp32<M32>(H, m32, H->L32[0].phi, H->L32[0].eta, &rc))) return r;
+                light = rc >= light_min;  // else (or NaN) the FP64 judge decides
+            }
+            if (light) ++judged_fp32;
+            else if ((r = fine_rms<float, M64>(H, m64, H->L32[0].phi, density, nullptr, &rc,
+                                               M32::kVarInv, shift32)))
                 return r;
             if (st) st->rel_hist[cyc] = rc / rnorm;
             if (cyc == 1) first_rel = rc / rnorm;
@@ -1197,6 +1253,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         st->cell_updates = updates;
         st->safeguard_hits = (long long)*hits_host;
         st->judged_cycles = judged;
+        st->judged_fp32 = judged_fp32;
         // per-cycle factors; after cycles without the judge, the mean factor
         // per cycle since the previous judged one (NaN for the unjudged ones)
         int prev = 0;

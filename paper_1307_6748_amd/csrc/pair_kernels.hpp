@@ -693,8 +693,10 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_pairs(M m, int n, double
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Finest-level defect and per-block partial sums of r^2, computed in double
-// precision: each workgroup streams a TY x TZ tile of the y-z plane along x
+// Finest-level defect and per-block partial sums of r^2, computed in the
+// arithmetic type TA (double: the judge of the stop test; float: the FP32
+// problem's own defect, with its FP32 density) and summed in double: each
+// workgroup streams a TY x TZ tile of the y-z plane along x
 // through a ring of three planes in LDS (phi and, for staged models such as
 // f(R), e^phi), so every value is fetched from HBM about once and each
 // exponential is computed once per loaded cell (about 1.3 per cell with the
@@ -713,20 +715,23 @@ struct NormTile {
 };
 using NormTileF = NormTile<8, 64, 32>;
 
-template <class TF, class M>
-__global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double ih2, double uscale, double uoffset,
+template <class TF, class M, class TA = double>
+__global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double ih2_, double uscale_,
+                                                              double uoffset_,
                                                               const TF* __restrict__ phi,
-                                                              const double* __restrict__ eta,
+                                                              const TA* __restrict__ eta,
                                                               double* __restrict__ res,
                                                               double* __restrict__ partial)
 {
     using G = NormTileF;
-    using SO = StageOp<double, M>;
+    using SO = StageOp<TA, M>;
     using VF = typename Vec2<TF>::type;
     using VD = typename Vec2<double>::type;
+    using VA = typename Vec2<TA>::type;
     constexpr bool STAGED = SO::kStaged;
-    __shared__ __align__(16) double ring[3][G::PLANE];
-    __shared__ __align__(16) double xring[STAGED ? 3 : 1][STAGED ? G::PLANE : 2];
+    const TA ih2 = (TA)ih2_, uscale = (TA)uscale_, uoffset = (TA)uoffset_;
+    __shared__ __align__(16) TA ring[3][G::PLANE];
+    __shared__ __align__(16) TA xring[STAGED ? 3 : 1][STAGED ? G::PLANE : 2];
     __shared__ double exptab[SO::kTable ? kExpTable : 1];
     if constexpr (SO::kTable) {
         exp_table_fill(exptab);
@@ -773,17 +778,17 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
             for (int q = 0; q < G::LPT; ++q) regs[q] = *reinterpret_cast<const VF*>(pl + poff[q]);
         };
         auto deposit = [&](int x) __attribute__((always_inline)) {
-            double* d = ring[(x - x0 + 3) % 3];
+            TA* d = ring[(x - x0 + 3) % 3];
 #pragma unroll
             for (int q = 0; q < G::LPT; ++q) {
                 const int k = tid + q * G::NT;
                 if ((q + 1) * G::NT <= G::PAIRS || k < G::PAIRS) {
-                    const double a = fma((double)regs[q].x, uscale, uoffset),
-                                 b = fma((double)regs[q].y, uscale, uoffset);
-                    *reinterpret_cast<VD*>(d + 2 * k) = VD{a, b};
+                    const TA a = fma((TA)regs[q].x, uscale, uoffset),
+                             b = fma((TA)regs[q].y, uscale, uoffset);
+                    *reinterpret_cast<VA*>(d + 2 * k) = VA{a, b};
                     if constexpr (STAGED) {
-                        double* e = xring[(x - x0 + 3) % 3];
-                        *reinterpret_cast<VD*>(e + 2 * k) = VD{SO::stage(a, exptab), SO::stage(b, exptab)};
+                        TA* e = xring[(x - x0 + 3) % 3];
+                        *reinterpret_cast<VA*>(e + 2 * k) = VA{SO::stage(a, exptab), SO::stage(b, exptab)};
                     }
                 }
             }
@@ -795,7 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
         deposit(x0 - 1);
         load(x0);
         deposit(x0);
-        VD enext = *reinterpret_cast<const VD*>(eta + eta_at(x0));
+        VA enext = *reinterpret_cast<const VA*>(eta + eta_at(x0));
         load(x0 + 1);
         __syncthreads();
         for (int x = x0; x < x0 + G::XC; ++x) {
@@ -803,48 +808,48 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
             // (clamped to the chunk: branch-free, so the compiler's wait
             // counts stay exact) overlap the stencil work below.
             deposit(x + 1);
-            const VD e2 = enext;
+            const VA e2 = enext;
             const size_t g = eta_at(x);
-            enext = *reinterpret_cast<const VD*>(eta + eta_at(min(x + 1, x0 + G::XC - 1)));
+            enext = *reinterpret_cast<const VA*>(eta + eta_at(min(x + 1, x0 + G::XC - 1)));
             load(min(x + 2, x0 + G::XC));
             __syncthreads();
-            const double* pv = ring[(x - 1 - x0 + 3) % 3];
-            const double* cu = ring[(x - x0 + 3) % 3];
-            const double* nx = ring[(x + 1 - x0 + 3) % 3];
+            const TA* pv = ring[(x - 1 - x0 + 3) % 3];
+            const TA* cu = ring[(x - x0 + 3) % 3];
+            const TA* nx = ring[(x + 1 - x0 + 3) % 3];
             const int o = (rr + 1) * G::EZ + 2 + 2 * cp;
-            const VD c = *reinterpret_cast<const VD*>(cu + o);
-            const VD xm = *reinterpret_cast<const VD*>(pv + o);
-            const VD xp = *reinterpret_cast<const VD*>(nx + o);
-            const VD ym = *reinterpret_cast<const VD*>(cu + o - G::EZ);
-            const VD yp = *reinterpret_cast<const VD*>(cu + o + G::EZ);
-            const double zm = cu[o - 1], zp = cu[o + 2];
-            VD ec, exm, exp_, eym, eyp;
-            double ezm = 0.0, ezp = 0.0;
+            const VA c = *reinterpret_cast<const VA*>(cu + o);
+            const VA xm = *reinterpret_cast<const VA*>(pv + o);
+            const VA xp = *reinterpret_cast<const VA*>(nx + o);
+            const VA ym = *reinterpret_cast<const VA*>(cu + o - G::EZ);
+            const VA yp = *reinterpret_cast<const VA*>(cu + o + G::EZ);
+            const TA zm = cu[o - 1], zp = cu[o + 2];
+            VA ec, exm, exp_, eym, eyp;
+            TA ezm = TA(0), ezp = TA(0);
             if constexpr (STAGED) {
-                const double* epv = xring[(x - 1 - x0 + 3) % 3];
-                const double* ecu = xring[(x - x0 + 3) % 3];
-                const double* enx = xring[(x + 1 - x0 + 3) % 3];
-                ec = *reinterpret_cast<const VD*>(ecu + o);
-                exm = *reinterpret_cast<const VD*>(epv + o);
-                exp_ = *reinterpret_cast<const VD*>(enx + o);
-                eym = *reinterpret_cast<const VD*>(ecu + o - G::EZ);
-                eyp = *reinterpret_cast<const VD*>(ecu + o + G::EZ);
+                const TA* epv = xring[(x - 1 - x0 + 3) % 3];
+                const TA* ecu = xring[(x - x0 + 3) % 3];
+                const TA* enx = xring[(x + 1 - x0 + 3) % 3];
+                ec = *reinterpret_cast<const VA*>(ecu + o);
+                exm = *reinterpret_cast<const VA*>(epv + o);
+                exp_ = *reinterpret_cast<const VA*>(enx + o);
+                eym = *reinterpret_cast<const VA*>(ecu + o - G::EZ);
+                eyp = *reinterpret_cast<const VA*>(ecu + o + G::EZ);
                 ezm = ecu[o - 1];
                 ezp = ecu[o + 2];
             }
             double L2[2];
 #pragma unroll
             for (int dk = 0; dk < 2; ++dk) {
-                double nbv[6];
+                TA nbv[6];
                 nbv[0] = xm[dk];
                 nbv[1] = xp[dk];
                 nbv[2] = ym[dk];
                 nbv[3] = yp[dk];
                 nbv[4] = dk ? c[0] : zm;
                 nbv[5] = dk ? zp : c[1];
-                double L, D;
+                TA L, D;
                 if constexpr (STAGED) {
-                    double enb[6];
+                    TA enb[6];
                     enb[0] = exm[dk];
                     enb[1] = exp_[dk];
                     enb[2] = eym[dk];
@@ -855,8 +860,8 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
                 } else {
                     m.op(c[dk], nbv, e2[dk], ih2, L, D);
                 }
-                L2[dk] = L;
-                acc += L * L;
+                L2[dk] = (double)L;
+                acc += L2[dk] * L2[dk];
             }
             if (res) *reinterpret_cast<VD*>(res + g) = VD{L2[0], L2[1]};
             __syncthreads();  // plane x-1's slot is refilled next

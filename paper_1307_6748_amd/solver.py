@@ -115,7 +115,7 @@ class Stats:
     ms_smooth: float = 0.0   # profiling on: smoothing on the finest level and sides >= 256
     restriction: int = 0     # defect restriction used: 0 mean, 1 full weighting,
                              # 2 full weighting in the first two cycles, then the mean
-    judged_cycles: int = 0   # cycles after which the FP64 judge ran
+    judged_cycles: int = 0   # cycles after which the judge ran (FP64, or FP32: judged_fp32)
     # finest-level first post-smoothing pass with the prolongation fused in
     # (profiling on): [FP64, FP32]
     fine_prol_ms: list = field(default_factory=lambda: [0.0, 0.0])
@@ -124,6 +124,7 @@ class Stats:
     nu_pre: int = 2          # smoothing sweeps per level the solve used
     nu_post: int = 2
     prolongation: int = 0    # prolongation used: 0 trilinear, 1 coefficient-weighted
+    judged_fp32: int = 0     # judged cycles judged by the FP32 problem's own defect
 
     @staticmethod
     def from_c(status: int, s: A.StatsC) -> "Stats":
@@ -134,7 +135,7 @@ class Stats:
                      list(s.rho_hist[: s.cycles + 1]), int(s.safeguard_hits), s.ms_smooth,
                      s.restriction, s.judged_cycles, list(s.fine_prol_ms),
                      list(s.fine_prol_launches), list(s.fine_prol_bytes), s.nu_pre, s.nu_post,
-                     s.prolongation)
+                     s.prolongation, s.judged_fp32)
 
 
 def _ptr(t: torch.Tensor | None):
@@ -169,8 +170,9 @@ class Solver:
     and by the 8-child mean after them (full weighting throughout with the
     trilinear prolongation), by the mean for the others; 0 / 1 force the
     mean / full weighting.
-    judge_skip: skip the FP64 judge on cycles predicted to stay above tol
-    (see isis_mg_desc.judge_skip).  nu_post = -1 (the default): one
+    judge_skip: skip the judge on cycles predicted to stay above tol, and
+    judge FP32 cycles predicted to stay far above it by the FP32 problem's
+    own defect (see isis_mg_desc.judge_skip).  nu_post = -1 (the default): one
     post-smoothing sweep for the symmetron and the chameleon, two otherwise."""
 
     def __init__(self, N: int, box: float, nu_pre: int = 2, nu_post: int = -1,

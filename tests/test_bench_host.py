@@ -135,6 +135,13 @@ def test_solve_bytes_counts_every_kernel_once():
     parts = (bench.solve_bytes(16, st0, 0, (2, 2), False) - base
              + bench.solve_bytes(16, st1, 0, (2, 2), False) - base + base)
     assert abs(mixed - parts) <= 1e-9 * mixed
+    # a light judge (FP32 iterate and FP32 density) instead of the FP64 judge
+    # of an FP32 iterate (FP32 iterate and FP64 density): 4 B per cell less
+    stl = types.SimpleNamespace(cycles=3, cycles_fp32=2, restriction=0, judged_cycles=3,
+                                judged_fp32=1)
+    st64j = types.SimpleNamespace(cycles=3, cycles_fp32=2, restriction=0, judged_cycles=3)
+    d = bench.solve_bytes(128, st64j, 0, (2, 2), True) - bench.solve_bytes(128, stl, 0, (2, 2), True)
+    assert abs(d - 4 * 128 ** 3) <= 1e-9 * 128 ** 3
     # the fused sweep levels (>= 256^3, temporal block >= 1) apply the
     # correction inside the first post-smoothing pass: no pass of its own
     st512 = types.SimpleNamespace(cycles=1, cycles_fp32=1, restriction=0, judged_cycles=1)

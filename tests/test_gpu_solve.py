@@ -409,6 +409,42 @@ def test_judge_skip_keeps_the_stop_test(name, precision):
     assert diff <= 1e-5, diff
 
 
+@pytest.mark.parametrize("name", ["symmetron_a1", "symmetron_a05", "fofr", "fofr_a07",
+                                  "fofr_paper_u", "chameleon", "chameleon_n05", "linear",
+                                  "linear_m0"])
+def test_light_judge_agrees_with_the_fp64_judge(name):
+    """Mixed precision with the judge schedule: FP32 cycles predicted to end
+    far above tol are judged by the FP32 problem's own defect.  The FP32
+    iterates are the same as with the FP64 judge after every cycle, so up to
+    the hand-over each judged entry of the history must be the FP64 one: bit
+    for bit below the light level (3e-5), within the FP32 defect's rounding
+    above it.  f(R) in the paper's variable solves its FP32 cycles in another
+    variable and keeps the FP64 judge."""
+    _, sp, a = models(name)
+    w = _wl("fr_256", 128)
+    eta = dev(w["eta"])
+    _, st0 = _solver(128, w["box"], precision="mixed").solve(eta, sp, a, 1e-8)
+    phi1, st1 = _solver(128, w["box"], precision="mixed", judge_skip=True).solve(eta, sp, a,
+                                                                                 1e-8)
+    assert st0.status == 0 and st1.status == 0 and st1.rel_res <= 1e-8
+    assert st0.judged_fp32 == 0
+    assert st1.judged_cycles == int(np.sum(np.isfinite(st1.rel_hist[1:])))
+    differ = above = 0
+    for k in range(1, min(st0.cycles_fp32, st1.cycles_fp32) + 1):
+        g, o = st1.rel_hist[k], st0.rel_hist[k]
+        if not np.isfinite(g):
+            continue
+        above += g >= 3e-5
+        if g != o:
+            differ += 1
+            assert g >= 3e-5 and abs(g - o) <= 1e-3 * o + 1e-7, (k, g, o)
+    assert differ <= st1.judged_fp32 <= above
+    if name == "fofr_paper_u":
+        assert st1.judged_fp32 == 0
+    else:
+        assert st1.judged_fp32 >= 1  # the first cycle (predicted ~1e-2) at least
+
+
 @pytest.mark.parametrize("name,post", [("symmetron_a1", 1), ("chameleon", 1), ("fofr", 2),
                                        ("linear", 2)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
