@@ -124,16 +124,25 @@ __device__ __forceinline__ T& at_bytes(T* base, unsigned off)
 // the tile's window live in registers (each thread the same elements), coarse
 // plane s/2 + 1 replacing s/2 - 1 at each even step s, fetched two steps
 // ahead.
-template <class T, class M, int TB, int TY, int TZ, int NT, bool SIG, bool PROL = false>
+// TI (not with PROL): the type of `in`; a float input of a double pass holds
+// the field as stored in single precision, and each loaded value v enters as
+// v * in_scale + in_offset (the FP32 iterate handed over to FP64 cycles).
+template <class T, class M, int TB, int TY, int TZ, int NT, bool SIG, bool PROL = false,
+          class TI = T>
 __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
-                                                    const T* __restrict__ in, T* __restrict__ out,
+                                                    const TI* __restrict__ in, T* __restrict__ out,
                                                     const T* __restrict__ eta,
                                                     const T* __restrict__ sigma,
                                                     const T* __restrict__ cphi = nullptr,
-                                                    const T* __restrict__ cphat = nullptr)
+                                                    const T* __restrict__ cphat = nullptr,
+                                                    T in_scale = T(1), T in_offset = T(0))
 {
+    static_assert(std::is_same<TI, T>::value || (!PROL && sizeof(TI) < sizeof(T)),
+                  "a converted input is wider, and not with the fused prolongation");
     using G = FusedGeom<T, TB, TY, TZ, NT>;
     using V = typename Vec2<T>::type;
+    using VI = typename Vec2<TI>::type;
+    constexpr bool CONV = !std::is_same<TI, T>::value;
     using SO = StageOp<T, M>;
     constexpr bool STAGED = SO::kStaged;
     constexpr int NK = 2 * TB;
@@ -322,14 +331,16 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
     };
 
     unsigned hits = 0;  // safeguard activations on owned cells (kGuard models)
-    V pA[G::LPT], pB[G::LPT];
+    VI pA[G::LPT], pB[G::LPT];
     T eA[NK][G::MAXI], eB[NK][G::MAXI];
     T sA[SIG ? NK : 1][SIG ? G::MAXI : 1], sB[SIG ? NK : 1][SIG ? G::MAXI : 1];
 
-    auto load_plane = [&](int x, V (&regs)[G::LPT]) __attribute__((always_inline)) {
-        const T* src = in + (size_t)(x & msk) * n2;
+    auto load_plane = [&](int x, VI (&regs)[G::LPT]) __attribute__((always_inline)) {
+        const TI* src = in + (size_t)(x & msk) * n2;
+        constexpr unsigned shr = CONV ? (SZ == 8 ? 1 : 0) : 0;  // poff counts T-sized elements
 #pragma unroll
-        for (int q = 0; q < G::LPT; ++q) regs[q] = at_bytes(reinterpret_cast<const V*>(src), poff[q]);
+        for (int q = 0; q < G::LPT; ++q)
+            regs[q] = at_bytes(reinterpret_cast<const VI*>(src), poff[q] >> shr);
     };
     // Density (and FAS source) of stage k's cells on plane p (parity PB).
     auto fetch_stage = [&](auto kc, auto pbc, int p, T (&e)[NK][G::MAXI],
@@ -345,9 +356,9 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
         });
     };
 
-    auto deposit = [&](auto slc, V (&regs)[G::LPT]) __attribute__((always_inline)) {
+    auto deposit = [&](auto slc, VI (&regs)[G::LPT]) __attribute__((always_inline)) {
         constexpr int SL = decltype(slc)::value;
-        correct(regs);
+        if constexpr (PROL) correct(regs);
         T* dst = ring + SL * G::PLANE;
         T* xd = xring + SL * G::PLANE;
 #pragma unroll
@@ -355,11 +366,19 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
             if ((q + 1) * NT <= G::PAIRS || tid + q * NT < G::PAIRS) {
                 const int oe = doff[q];      // column 2cp (even half)
                 const int oo = oe + G::HZ;   // column 2cp+1 (odd half)
-                dst[oe] = regs[q].x;
-                dst[oo] = regs[q].y;
+                T a, b;
+                if constexpr (CONV) {
+                    a = fma((T)regs[q].x, in_scale, in_offset);
+                    b = fma((T)regs[q].y, in_scale, in_offset);
+                } else {
+                    a = regs[q].x;
+                    b = regs[q].y;
+                }
+                dst[oe] = a;
+                dst[oo] = b;
                 if constexpr (STAGED) {
-                    xd[oe] = SO::stage(regs[q].x, exptab);
-                    xd[oo] = SO::stage(regs[q].y, exptab);
+                    xd[oe] = SO::stage(a, exptab);
+                    xd[oo] = SO::stage(b, exptab);
                 }
             }
         }
@@ -452,7 +471,7 @@ __global__ __launch_bounds__(NT) void k_sweep_fused(M m, int n, int nxc, T ih2,
     // (which held plane s) receives plane s+2.  ec/sc hold this step's cell
     // data, en/sn receive the next step's (with LATE2, the black stage's
     // entries of ec/sc are consumed here and refilled for step s+2).
-    auto step = [&](auto jc, int s, V (&spare)[G::LPT], V (&ready)[G::LPT],
+    auto step = [&](auto jc, int s, VI (&spare)[G::LPT], VI (&ready)[G::LPT],
                     T (&ec)[NK][G::MAXI], T (&sc)[SIG ? NK : 1][SIG ? G::MAXI : 1],
                     T (&en)[NK][G::MAXI], T (&sn)[SIG ? NK : 1][SIG ? G::MAXI : 1]) __attribute__((always_inline)) {
         constexpr int J = decltype(jc)::value;
@@ -582,16 +601,16 @@ inline int fused_chunks(int n, int tiles, int resident)
     return n / fused_chunk(n);
 }
 
-template <class T, class M, int TB, bool SIG, bool PROL = false>
-int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T* eta,
+template <class T, class M, int TB, bool SIG, bool PROL = false, class TI = T>
+int launch_fused_pass(const M& m, int n, double h, const TI* in, T* out, const T* eta,
                       const T* sigma, hipStream_t s, char* err, const T* cphi = nullptr,
-                      const T* cphat = nullptr)
+                      const T* cphat = nullptr, double in_scale = 1.0, double in_offset = 0.0)
 {
     using Tile = FusedTile<T, M, TB>;
     constexpr int TY = Tile::TY, TZ = Tile::TZ, NT = Tile::NT;
     constexpr int lds = fused_lds_bytes<T, M, TB, TY, TZ, PROL>();
     static_assert(lds <= Tile::kFull, "LDS overflow");
-    auto kern = k_sweep_fused<T, M, TB, TY, TZ, NT, SIG, PROL>;
+    auto kern = k_sweep_fused<T, M, TB, TY, TZ, NT, SIG, PROL, TI>;
     static std::atomic<unsigned> lds_done{0};  // per instantiation: devices set up
     if (ensure_dynamic_lds((const void*)kern, lds, lds_done) != hipSuccess) {
         snprintf(err, 512, "hipFuncSetAttribute(shared %d B) failed", lds);
@@ -604,7 +623,7 @@ int launch_fused_pass(const M& m, int n, double h, const T* in, T* out, const T*
     const int blocks = tiles * nxc;
     T ih2 = (T)(1.0 / (h * h));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, s, m, n, nxc, ih2, in, out, eta, sigma,
-                       cphi, cphat);
+                       cphi, cphat, (T)in_scale, (T)in_offset);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         snprintf(err, 512, "k_sweep_fused: %s", hipGetErrorString(e));
@@ -633,17 +652,43 @@ inline int fused_first_pass(int count, int tb) { return (tb >= 2 && count >= 2) 
 // cphat, side n/2), phi += P(cphi - cphat) first, inside the first pass,
 // which must then be a single sweep (fused_first_pass == 1): in a two-sweep
 // pass the extra registers cost a third of the workgroups per CU, more than
-// the separate prolongation pass saves.
+// the separate prolongation pass saves.  With in32 (double passes, no cphi,
+// count >= 1, no FAS source), the first pass reads the field from in32 (its
+// values times in_scale plus in_offset) instead of *phi, which it only
+// writes to through the ping-pong.
 template <class T, class M>
 int launch_fused_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta,
                         const T* sigma, int count, int tb, hipStream_t s, char* err,
-                        const T* cphi = nullptr, const T* cphat = nullptr)
+                        const T* cphi = nullptr, const T* cphat = nullptr,
+                        const float* in32 = nullptr, double in_scale = 1.0, double in_offset = 0.0)
 {
     if (cphi && fused_first_pass(count, tb) != 1) {
         snprintf(err, 512, "fused prolongation needs a single-sweep first pass");
         return -4;
     }
+    if (in32 && (sizeof(T) != 8 || cphi || sigma || count < 1)) {
+        snprintf(err, 512, "a single-precision input needs a double pass without prolongation "
+                           "or FAS source");
+        return -4;
+    }
     int done = 0;
+    if constexpr (sizeof(T) == 8) {
+        if (in32) {  // the first pass, from the single-precision field
+            const int step = fused_first_pass(count, tb);
+            const int r = step == 2
+                              ? launch_fused_pass<T, M, 2, false, false, float>(
+                                    m, n, h, in32, *tmp, eta, nullptr, s, err, nullptr, nullptr,
+                                    in_scale, in_offset)
+                              : launch_fused_pass<T, M, 1, false, false, float>(
+                                    m, n, h, in32, *tmp, eta, nullptr, s, err, nullptr, nullptr,
+                                    in_scale, in_offset);
+            if (r) return r;
+            T* t = *phi;
+            *phi = *tmp;
+            *tmp = t;
+            done = step;
+        }
+    }
     while (done < count) {
         const int step = (tb >= 2 && count - done >= 2) ? 2 : 1;
         const bool prol = cphi && done == 0;

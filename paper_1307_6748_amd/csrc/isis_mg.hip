@@ -315,9 +315,18 @@ bool prolong_fused(int n, int count, int tb, int min_fused_n = kFusedSolverMinN)
 template <class T, class M>
 int launch_sweeps(const M& m, int n, double h, T** phi, T** tmp, const T* eta, const T* sigma,
                   int count, int tb, hipStream_t s, char* err, int min_fused_n = kFusedSolverMinN,
-                  const T* cphi = nullptr, const T* cphat = nullptr, bool pw = false)
+                  const T* cphi = nullptr, const T* cphat = nullptr, bool pw = false,
+                  const float* in32 = nullptr, double in_scale = 1.0, double in_offset = 0.0)
 {
     constexpr int PWc = weighted_code<T, M>();
+    if (in32) {  // the field in single precision (fused double levels only)
+        if (!(count > 0 && fused_level<T, M>(n, tb, min_fused_n) && !cphi)) {
+            snprintf(err, 512, "launch_sweeps: a single-precision input needs fused sweeps");
+            return ISIS_ERR_INVALID_ARG;
+        }
+        return launch_fused_sweeps<T, M>(m, n, h, phi, tmp, eta, sigma, count, tb, s, err,
+                                         nullptr, nullptr, in32, in_scale, in_offset);
+    }
     if (cphi && pw && PWc != 0) {
         int r = launch_prolong<T, PWc>(n, *phi, cphi, cphat, s, err);
         if (r) return r;
@@ -598,6 +607,10 @@ struct isis_mg {
     int fw_after;  // ... after the first fw_first cycles of a solve (with them: full weighting)
     int fw_first;
     int pw;  // coefficient-weighted prolongation (desc.prolongation resolved)
+    // FP32 iterate handed over to the FP64 cycles, consumed by their first
+    // finest-level smoothing pass (value * in32_scale + in32_offset)
+    const float* in32 = nullptr;
+    double in32_scale = 1.0, in32_offset = 0.0;
     int profile;
     int ntimed;
     int events_ready;
@@ -819,8 +832,18 @@ int timed_block(isis_mg* H, const M& m, LevP<T>& f, int l, int count, const T* c
                        H->ntimed < isis_mg::kMaxTimed;
     const int q = H->ntimed;
     if (timed) HIP_TRY(H->err, hipEventRecord(H->ev0[q], H->s));
+    // the FP32 iterate handed over to the FP64 cycles (solve_impl), read by
+    // the first pass of their first smoothing step in place of the field
+    const float* in32 = nullptr;
+    if constexpr (sizeof(T) == 8) {
+        if (l == 0 && count > 0 && H->in32) {
+            in32 = H->in32;
+            H->in32 = nullptr;
+        }
+    }
     int r = launch_sweeps<T, M>(m, f.n, f.h, &f.phi, &f.tmp, f.eta, f.sigma, count, tb, H->s,
-                                H->err, kFusedSolverMinN, cphi, cphat);
+                                H->err, kFusedSolverMinN, cphi, cphat, false, in32,
+                                H->in32_scale, H->in32_offset);
     if (r) return r;
     if (timed) {
         HIP_TRY(H->err, hipEventRecord(H->ev1[q], H->s));
@@ -832,7 +855,8 @@ int timed_block(isis_mg* H, const M& m, LevP<T>& f, int l, int count, const T* c
         H->tupd[q] = n3 * count;
         // compulsory bytes: per pass read phi, eta, write phi; the fused
         // prolongation adds the two coarse fields
-        H->tbytes[q] = (double)passes * n3 * 3.0 * sizeof(T) + (cphi ? 2.0 * n3 / 8 * sizeof(T) : 0.0);
+        H->tbytes[q] = (double)passes * n3 * 3.0 * sizeof(T) + (cphi ? 2.0 * n3 / 8 * sizeof(T) : 0.0) -
+                       (in32 ? n3 * (sizeof(T) - sizeof(float)) : 0.0);
         H->tprec[q] = sizeof(T) == 4 ? 1 : 0;
         H->tlevel[q] = l;
         H->tprol[q] = cphi ? 1 : 0;
@@ -971,6 +995,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     const bool mixed = (d.precision == ISIS_MIXED);
     int r;
     H->ntimed = 0;
+    H->in32 = nullptr;
     HIP_TRY(H->err, hipMemsetAsync(H->hits(), 0, sizeof(unsigned long long), H->s));
     H->L64[0].phi = field;
     H->L64[0].tmp = H->tmp0;
@@ -1174,10 +1199,21 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         }
         // Promote the FP32 iterate unless it is no better than the field the
         // phase started from (then the FP64 cycles continue from that field).
+        // When FP64 cycles follow and their first finest-level smoothing pass
+        // is a fused one, that pass reads the FP32 iterate itself (timed_block)
+        // instead of a converted copy.
         if (!fp32_failed && rcur < r0) {
-            hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock), 0,
-                               H->s, n3, H->L32[0].phi, F.phi, M32::kVarInv, shift32);
-            LAUNCH_CHECK(H->err, "k_convert");
+            const bool fp64_next = status != ISIS_OK && cyc < d.max_cycles;
+            if (fp64_next && d.nu_pre > 0 && H->lb != 0 && H->nlev > 1 &&
+                fused_level<double, M64>(N, H->tb)) {
+                H->in32 = H->L32[0].phi;
+                H->in32_scale = M32::kVarInv;
+                H->in32_offset = shift32;
+            } else {
+                hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n3)), dim3(kBlock),
+                                   0, H->s, n3, H->L32[0].phi, F.phi, M32::kVarInv, shift32);
+                LAUNCH_CHECK(H->err, "k_convert");
+            }
         } else {
             status = ISIS_ERR_NOT_CONVERGED;
             rcur = r0;

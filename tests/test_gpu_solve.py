@@ -409,6 +409,36 @@ def test_judge_skip_keeps_the_stop_test(name, precision):
     assert diff <= 1e-5, diff
 
 
+@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "chameleon", "linear"])
+def test_fp32_iterate_handed_to_the_fused_fp64_pass(name):
+    """At 256^3 the first FP64 smoothing pass after the FP32 cycles reads the
+    FP32 iterate itself (converted as it is loaded) instead of a converted
+    copy: the mixed solve must give, bit for bit, the field of an FP64 solve
+    that starts from the FP32 phase's converted result and runs the same FP64
+    cycles."""
+    _, sp, a = models(name)
+    w = _wl("fr_256")
+    n = 256
+    eta = dev(w["eta"])
+    kw = dict(restriction=0)
+    phi, st = _solver(n, w["box"], precision="mixed", **kw).solve(eta, sp, a, 1e-8)
+    assert st.status == 0 and st.cycles > st.cycles_fp32 >= 1
+    k, j = st.cycles_fp32, st.cycles - st.cycles_fp32
+    # the FP32 phase alone (the cycle limit stops it there; its result is converted)
+    phi32, st32 = _solver(n, w["box"], precision="mixed", max_cycles=k, **kw).solve(
+        eta, sp, a, 1e-8, check=False)
+    assert st32.cycles == k and st32.cycles_fp32 == k
+    ref, st64 = _solver(n, w["box"], precision="fp64", max_cycles=j, **kw).solve(
+        eta, sp, a, 1e-8, phi=phi32.clone(), use_guess=1)
+    assert st64.cycles == j and st64.status == 0
+    assert bool(torch_equal(phi, ref)), float((phi - ref).abs().max())
+
+
+def torch_equal(x, y):
+    import torch
+    return torch.equal(x, y)
+
+
 @pytest.mark.parametrize("name", ["symmetron_a1", "symmetron_a05", "fofr", "fofr_a07",
                                   "fofr_paper_u", "chameleon", "chameleon_n05", "linear",
                                   "linear_m0"])
