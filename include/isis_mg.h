@@ -139,13 +139,14 @@ typedef struct {
     int judge_skip;    /* 0: the FP64 fine defect (the judge of the stop test) is
                           evaluated after every V-cycle; 1: after a judged cycle,
                           the cycles that the mean factor per cycle since the
-                          previous judged one predicts to stay above tol (all
-                          but the last one before the predicted end, at most 4
-                          in a row) run without it, and in mixed precision an
+                          previous judged one predicts to stay above tol (at
+                          most 4 in a row: FP64 cycles all but the last before
+                          the predicted end, FP32 cycles all but the last two)
+                          run without it, and in mixed precision an
                           FP32 cycle predicted to end above max(3e-5, 1e3 tol)
                           relative is judged by the FP32 problem's own defect
                           (FP32 density and arithmetic; its rel_hist entry is
-                          then accurate to ~1e-7 relative residual; not for
+                          then within 1% of the FP64 one; not for
                           f(R) in the paper's variable).  The stop test is
                           unchanged (the last cycle is always judged in FP64);
                           unjudged cycles have rel_hist = NaN                   */

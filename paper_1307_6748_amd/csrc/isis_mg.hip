@@ -959,24 +959,30 @@ constexpr double kFloorJumpMax = 1e-6;
 // Judge schedule (desc.judge_skip): after a judged cycle whose residual rc
 // fell at the mean factor rho per cycle since the previous judged one, the
 // number of cycles until rc rho^m <= target is m; the next `ahead` cycles
-// then run without the judge, ahead = min(m - 1, 4) >= 0, so the judge
-// resumes at the cycle predicted to reach the target (the factors of these
-// solves rise towards their asymptotic value, so the prediction errs on the
-// early side, and a residual still above the target is judged again after
-// the next cycle).
-inline int judge_ahead(bool lazy, int cyc, double rc, double rho, double target)
+// then run without the judge, ahead = min(m - margin, 4) >= 0.  FP64 cycles
+// (margin 1) resume the judge at the cycle predicted to reach the target: the
+// factors of these solves rise towards their asymptotic value, so the
+// prediction errs on the early side, and a residual still above the target
+// is judged again after the next cycle.  FP32 cycles (margin 2) resume one
+// cycle earlier: their factor collapses at the FP32 round-off floor, which
+// the prediction cannot see and which lies above the hand-over level for
+// some problems (the Poisson equation of the Newtonian potential: ~4e-6
+// relative), so a later judge would let cycles run on at the floor.
+inline int judge_ahead(bool lazy, int cyc, double rc, double rho, double target, int margin)
 {
     if (!lazy || cyc < 2 || !(rho > 0.0) || !(rho < 0.6) || !(rc > target)) return 0;
     const double m = std::ceil(std::log(target / rc) / std::log(rho));
-    return (int)std::max(0.0, std::min(m - 1.0, 4.0));
+    return (int)std::max(0.0, std::min(m - margin, 4.0));
 }
 
 // Judge schedule, FP32 cycles: a cycle whose residual is predicted to stay
 // above max(kLightJudgeMin, 1e3 tol) (relative) is judged by the FP32
-// problem's own defect (fine_rms_fp32), whose rounding (a relative residual
-// of ~1e-7 at most: the FP32 cycles' round-off floor) is then below 1% of the
-// residual; a light result below that level is taken again by the FP64 judge,
-// so the stop test and the predictive hand-over to FP64 see the FP64 defect.
+// problem's own defect (fine_rms_fp32), whose rounding (about the FP32
+// cycles' round-off floor: 2e-7 relative for the symmetron, 4e-6 for the
+// Poisson equation of the Newtonian potential) adds to the residual in
+// quadrature, under 1% of it; a light result below that level is taken again
+// by the FP64 judge, so the stop test and the predictive hand-over to FP64 see
+// the FP64 defect.
 constexpr double kLightJudgeMin = 3e-5;
 
 // The solve for one model; M64/M32 are its double and float device models.
@@ -1195,7 +1201,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             rprev = rc;
             cprev = cyc;
             // the FP32 phase hands over one cycle early: aim one cycle short
-            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm / std::max(rho, 1e-300));
+            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm / std::max(rho, 1e-300), 2);
         }
         // Promote the FP32 iterate unless it is no better than the field the
         // phase started from (then the FP64 cycles continue from that field).
@@ -1222,7 +1228,10 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
 
     // FP64 V-cycles (the whole solve in ISIS_FP64; the refinement phase in
     // ISIS_MIXED).
-    double rlast = rcur;  // residual at the last judged cycle (cprev)
+    // residual at the last judged cycle, clast (the FP32 phase ends with a
+    // judged cycle, or restarts from the initial field's r0)
+    double rlast = rcur;
+    int clast = cyc;
     blind = 0;
     while (status == ISIS_ERR_NOT_CONVERGED && cyc < d.max_cycles) {
         H->fw = cyc < H->fw_first ? 1 : H->fw_after;
@@ -1244,12 +1253,12 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         if (!std::isfinite(rc) || rc > 1e3 * r0) status = ISIS_ERR_DIVERGED;
         else if (rc <= tol * rnorm) status = ISIS_OK;
         else {
-            const int gap = cyc - cprev;
+            const int gap = cyc - clast;
             const double rho = std::pow(rc / rlast, 1.0 / std::max(gap, 1));
-            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm);
+            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm, 1);
         }
         rlast = rc;
-        cprev = cyc;
+        clast = cyc;
     }
     if (F.phi != field) {  // an odd number of fused passes left the result in tmp0
         HIP_TRY(H->err, hipMemcpyAsync(field, F.phi, sizeof(double) * n3,
