@@ -1565,6 +1565,7 @@ int isis_mg_solve(isis_mg_t* H, const double* density, double* field,
                        density, field, tol, use_guess, stats);
         break;
     }
+    H->in32 = nullptr;  // a solve that ended early may not have consumed it
     if (stats) {
         auto t1 = std::chrono::steady_clock::now();
         stats->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();

@@ -409,7 +409,7 @@ def test_judge_skip_keeps_the_stop_test(name, precision):
     assert diff <= 1e-5, diff
 
 
-@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "chameleon", "linear"])
+@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "chameleon", "linear", "fofr_paper_u"])
 def test_fp32_iterate_handed_to_the_fused_fp64_pass(name):
     """At 256^3 the first FP64 smoothing pass after the FP32 cycles reads the
     FP32 iterate itself (converted as it is loaded) instead of a converted
@@ -431,7 +431,13 @@ def test_fp32_iterate_handed_to_the_fused_fp64_pass(name):
     ref, st64 = _solver(n, w["box"], precision="fp64", max_cycles=j, **kw).solve(
         eta, sp, a, 1e-8, phi=phi32.clone(), use_guess=1)
     assert st64.cycles == j and st64.status == 0
-    assert bool(torch_equal(phi, ref)), float((phi - ref).abs().max())
+    if name == "fofr_paper_u":
+        # the variable's offset: the conversion kernel's multiply-add may round
+        # apart from the pass's fused one, by an ulp of the converted value
+        scale = float(ref.abs().max())
+        assert float((phi - ref).abs().max()) <= 1e-14 * scale
+    else:
+        assert bool(torch_equal(phi, ref)), float((phi - ref).abs().max())
 
 
 def torch_equal(x, y):
