@@ -1203,11 +1203,16 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
             if (rho > 0.6 || jump ||
                 (predict ? rc * rho <= 0.7 * tol * rnorm : rc <= fp32_floor * rnorm))
                 break;
+            // a factor more than twice the previous judged one (that of a
+            // cycle after the first, which starts from the cold start) may be
+            // the floor coming into view: judge the next cycle too
+            const bool rising = cprev >= 2 && rho > 2.0 * rho_prev;
             rho_prev = rho;
             rprev = rc;
             cprev = cyc;
             // the FP32 phase hands over one cycle early: aim one cycle short
-            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm / std::max(rho, 1e-300), 2);
+            blind = rising ? 0
+                           : judge_ahead(lazy, cyc, rc, rho, tol * rnorm / std::max(rho, 1e-300), 2);
         }
         // Promote the FP32 iterate unless it is no better than the field the
         // phase started from (then the FP64 cycles continue from that field).
@@ -1238,6 +1243,7 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     // judged cycle, or restarts from the initial field's r0)
     double rlast = rcur;
     int clast = cyc;
+    double rho_last = 0.0;  // factor at the last judged FP64 cycle after the first cycle
     blind = 0;
     while (status == ISIS_ERR_NOT_CONVERGED && cyc < d.max_cycles) {
         H->fw = cyc < H->fw_first ? 1 : H->fw_after;
@@ -1261,7 +1267,10 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
         else {
             const int gap = cyc - clast;
             const double rho = std::pow(rc / rlast, 1.0 / std::max(gap, 1));
-            blind = judge_ahead(lazy, cyc, rc, rho, tol * rnorm, 1);
+            // erratic or rising factors (more than twice the last): no skipping
+            const bool rising = rho_last > 0.0 && rho > 2.0 * rho_last;
+            blind = rising ? 0 : judge_ahead(lazy, cyc, rc, rho, tol * rnorm, 1);
+            if (cyc >= 2) rho_last = rho;
         }
         rlast = rc;
         clast = cyc;

@@ -385,7 +385,8 @@ def test_mixed_from_a_near_converged_guess(orc, name):
 
 
 @pytest.mark.parametrize("name,precision", [("fofr", "mixed"), ("fofr", "fp64"),
-                                            ("symmetron_a1", "mixed")])
+                                            ("symmetron_a1", "mixed"), ("chameleon", "mixed"),
+                                            ("linear_m0", "mixed"), ("fofr_a07", "mixed")])
 def test_judge_skip_keeps_the_stop_test(name, precision):
     """Skipping the FP64 judge on cycles predicted to stay above tol: the
     final residual is judged and <= tol, the solve takes at most one cycle
