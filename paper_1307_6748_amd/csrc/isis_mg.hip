@@ -1024,13 +1024,20 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
     const double h0 = H->L64[0].h;
     double cold_rms, r_ref;
     using NG = NormTileF;
+    // From the cold start in mixed precision the FP32 copy is the field the
+    // cycles start from; the FP64 field is needed only if the FP32 phase
+    // does not run or does not promote its iterate, and is then written
+    // there (cold_pending).
+    bool cold_pending = false;
     if ((N & (N - 1)) == 0 && N % NG::TZ == 0 && N % NG::TY == 0 && N % NG::XC == 0) {
+        cold_pending = cold32;
         // one pass over the FP64 density: cold start, its copies, the
         // density's FP32 copy and first restriction, and both sums
         const long tiles = (long)(N / NG::TZ) * (N / NG::TY) * (N / NG::XC);
         const int g = (int)std::min<long>(kReduceBlocks, tiles);
         hipLaunchKernelGGL((k_setup_tiled<M64>), dim3(g), dim3(kBlock), 0, H->s, m64, N,
-                           1.0 / (h0 * h0), density, cold, cold32 ? H->L32[0].phi : nullptr,
+                           1.0 / (h0 * h0), density, cold_pending ? nullptr : cold,
+                           cold32 ? H->L32[0].phi : nullptr,
                            M32::kVar, -shift32 * M32::kVar, mixed ? H->L32[0].eta : nullptr,
                            H->L64[1].eta, H->partial, H->partial + kReduceBlocks);
         LAUNCH_CHECK(H->err, "k_setup_tiled");
@@ -1231,10 +1238,16 @@ int solve_impl(isis_mg* H, const M64& m64, const M32& m32, const isis_model_para
                                    0, H->s, n3, H->L32[0].phi, F.phi, M32::kVarInv, shift32);
                 LAUNCH_CHECK(H->err, "k_convert");
             }
+            cold_pending = false;
         } else {
             status = ISIS_ERR_NOT_CONVERGED;
             rcur = r0;
         }
+    }
+    if (cold_pending) {  // the FP64 field is the cold start after all
+        hipLaunchKernelGGL((k_cold_start<double, M64>), dim3(grid_for(n3)), dim3(kBlock), 0, H->s,
+                           m64, n3, density, field);
+        LAUNCH_CHECK(H->err, "k_cold_start");
     }
 
     // FP64 V-cycles (the whole solve in ISIS_FP64; the refinement phase in

@@ -874,7 +874,8 @@ __global__ __launch_bounds__(kBlock) void k_defect_norm_tiled(M m, int n, double
 // Solve setup in one pass over the FP64 density (tiles, ring and summation
 // order of k_defect_norm_tiled): the cold start phi_c = cold(eta), computed
 // for every loaded value and staged in the ring, gives the defect whose
-// squares sum to r_ref^2 (partial); the same pass writes phi_c to `cold`, its
+// squares sum to r_ref^2 (partial); the same pass writes phi_c to `cold` (if
+// not NULL), its
 // FP32 copy (cold - shift) * kVar to cold32 (if not NULL), the FP32 copy of
 // eta to eta32 (if not NULL) and the 8-child mean of eta to eta_c (the next
 // level, children summed in the order of k_restrict: x, then y, then z), and
@@ -1023,7 +1024,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_tiled(M m, int n, double ih2,
                 acc += L * L;
                 acc2 += c[dk] * c[dk];
             }
-            *reinterpret_cast<VD*>(cold + g) = c;
+            if (cold) *reinterpret_cast<VD*>(cold + g) = c;
             if (cold32)
                 *reinterpret_cast<VF*>(cold32 + g) =
                     VF{(float)(c[0] * scale32 + offset32), (float)(c[1] * scale32 + offset32)};

@@ -441,6 +441,28 @@ def test_fp32_iterate_handed_to_the_fused_fp64_pass(name):
         assert bool(torch_equal(phi, ref)), float((phi - ref).abs().max())
 
 
+@pytest.mark.parametrize("name", ["symmetron_a1", "fofr", "chameleon"])
+def test_mixed_cold_start_written_when_no_cycle_runs(name):
+    """A uniform density makes the cold start the exact root, so the solve
+    runs no cycle.  From the cold start the mixed setup leaves the FP64 field
+    to the FP32 cycles; here it must still return the cold start itself,
+    the FP64 solve's field (the buffers start as NaN)."""
+    import torch
+    from paper_1307_6748_amd import synth
+    _, sp, a = models(name)
+    n = 128
+    eta = dev(synth.uniform(n, 2.0))
+    out = {}
+    for prec in ("fp64", "mixed"):
+        phi = torch.full_like(eta, float("nan"))
+        phi, st = _solver(n, 64.0, precision=prec).solve(eta, sp, a, 1e-8, phi=phi)
+        assert st.status == 0 and st.cycles == 0, (prec, st.cycles)
+        out[prec] = phi
+    assert bool(torch.isfinite(out["mixed"]).all())
+    rel = float(((out["mixed"] - out["fp64"]).abs() / out["fp64"].abs().clamp_min(1e-300)).max())
+    assert rel <= 4e-16, rel
+
+
 def torch_equal(x, y):
     import torch
     return torch.equal(x, y)
